@@ -1,0 +1,151 @@
+"""Pins of the oracle's PP-GMRES(m) and its FP32 iterative-refinement loop.
+
+Pinned against: the numbers printed for the Laplacian example of Section V
+(tests/golden/sec5_laplacian.json), dense direct solves, finite termination
+of full GMRES, monotone residuals, and the counting convention of Section III
+(three dots per iteration).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import gmres, poly
+from paper_1907_00072_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def sec5(golden_dir):
+    return json.load(open(os.path.join(golden_dir, "sec5_laplacian.json")))
+
+
+@pytest.fixture(scope="module")
+def lap():
+    A = W.laplacian5(201)
+    return A.to_scipy(), np.ones(A.n)
+
+
+def _alpha_p(roots, alpha):
+    return 1.0 - np.prod([1.0 - alpha / t for t in roots], axis=0).real
+
+
+def test_sec5_bad_polynomial_from_b(sec5, lap):
+    A, b = lap
+    assert A.shape[0] == 40401
+    roots, s = poly.build_poly(A, b, sec5["roots"])
+    al = np.linspace(0.0, 8.0, 40001)
+    lo = _alpha_p(roots, al).min()
+    ref = sec5["v0_equals_b"]["min_alpha_p_alpha_on_0_8"]
+    assert ref - 50 <= lo <= ref + 50, lo
+
+
+@pytest.mark.slow
+def test_sec5_stall_after_2550_iterations(sec5, lap):
+    A, b = lap
+    roots, s = poly.build_poly(A, b, sec5["roots"])
+    x, st = gmres.pp_gmres(A, b, sec5["m"], sec5["tol"], roots=roots, max_iters=2550)
+    assert st.iters == 2550 and not st.converged
+    ref = sec5["v0_equals_b"]["relres_after_2550_iterations"]
+    assert abs(st.relres_true - ref) <= 0.005, st.relres_true
+
+
+def test_sec5_random_start_vector(sec5, lap):
+    A, b = lap
+    v0 = W.uniform(A.shape[0], 0)
+    x, st = gmres.pp_gmres(A, b, sec5["m"], sec5["tol"], v0=v0, d=sec5["roots"], max_iters=400)
+    ref = sec5["random_v0_uniform_m1_1"]["iterations_to_tol"]
+    assert st.converged and abs(st.iters - ref) <= 4, st.iters
+    lo, hi = sec5["random_v0_uniform_m1_1"]["alpha_p_alpha_range_on_bulk"]
+    vals = _alpha_p(st.roots, np.linspace(0.5, 8.0, 20001))
+    assert vals.min() >= lo and vals.max() <= hi
+
+
+def test_full_gmres_terminates_and_matches_dense_solve():
+    n = 40
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((n, n)) / np.sqrt(n) + 2 * np.eye(n)
+    b = rng.standard_normal(n)
+    x, st = gmres.pp_gmres(A, b, m=n, tol=1e-13)
+    assert st.cycles == 1 and st.iters <= n
+    ref = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_polynomial_gmres_matches_dense_solve():
+    n = 60
+    rng = np.random.default_rng(32)
+    A = rng.standard_normal((n, n)) / np.sqrt(n) + 2 * np.eye(n)
+    b = rng.standard_normal(n)
+    x, st = gmres.pp_gmres(A, b, m=10, tol=1e-12, v0=W.uniform(n, 33), d=5, max_iters=200)
+    ref = np.linalg.solve(A, b)
+    assert st.converged
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("d", [0, 10])
+def test_config1_solution_and_monotone_residuals(d):
+    P = W.config(1)
+    A = P.A.to_scipy()
+    x, st = gmres.pp_gmres(A, P.b, P.m, P.tol, v0=P.v0, d=d, max_iters=1000)
+    assert st.converged
+    assert np.linalg.norm(P.b - A @ x) / np.linalg.norm(P.b) < P.tol
+    ref = spla.spsolve(A.tocsc(), P.b)
+    # forward error <= cond * tol; cond(A) of this operator is ~1e3
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-4
+    h = np.asarray(st.history)
+    # the implicit residual never increases inside a cycle; the true one never across cycles
+    starts = np.cumsum([0] + [P.m] * (st.cycles - 1))
+    for c0 in starts:
+        seg = h[c0:c0 + P.m]
+        assert np.all(np.diff(seg) <= 1e-12 * seg[:-1])
+    th = np.asarray(st.true_history)
+    assert np.all(np.diff(th) <= 1e-10 * th[:-1])
+
+
+def test_polynomial_reduces_iterations_and_dots():
+    P = W.config(1)
+    A = P.A.to_scipy()
+    _, s0 = gmres.pp_gmres(A, P.b, P.m, P.tol, max_iters=1000)
+    _, s1 = gmres.pp_gmres(A, P.b, P.m, P.tol, v0=P.v0, d=P.d, max_iters=1000)
+    assert s1.iters * 5 < s0.iters
+    assert s1.dots * 5 < s0.dots
+
+
+def test_counting_convention():
+    """Section III: three dots per Arnoldi step; d products with A per preconditioned step."""
+    P = W.config(1)
+    A = P.A.to_scipy()
+    for d in (0, 10):
+        _, st = gmres.pp_gmres(A, P.b, P.m, P.tol, v0=P.v0, d=d, max_iters=1000)
+        s = st.nroots
+        build_spmv = s
+        build_dots = 3 * s + 1 if d else 0
+        per_step = max(s, 1)
+        cyc = st.cycles
+        assert st.spmvs == build_spmv + 1 + st.iters * per_step + cyc * (max(s - 1, 0) + 1)
+        assert st.dots == build_dots + 1 + 3 * st.iters + cyc
+
+
+def test_single_cycle_implicit_equals_true_residual():
+    n = 200
+    rng = np.random.default_rng(34)
+    A = rng.standard_normal((n, n)) / np.sqrt(n) + 3 * np.eye(n)
+    b = rng.standard_normal(n)
+    x, st = gmres.pp_gmres(A, b, m=15, tol=1e-30, max_iters=15)
+    assert st.cycles == 1 and st.iters == 15
+    assert abs(st.relres_implicit - st.relres_true) <= 1e-9 * st.relres_true
+
+
+def test_iterative_refinement_fp32_inner():
+    P = W.config(1)
+    A = P.A.to_scipy()
+    x, st = gmres.pp_gmres_ir(A, P.b, P.m, P.d, 1e-10, P.v0, max_outer=20)
+    assert st.converged and st.relres_true < 1e-10
+    assert st.outer >= 2            # one FP32 cycle cannot reach 1e-10 alone
+    ref = spla.spsolve(A.tocsc(), P.b)
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-6
+    # the float32 polynomial is close to (but not the same as) the float64 one
+    r64, _ = poly.build_poly(A, P.v0, P.d)
+    assert np.max(np.abs(np.sort(st.roots.real) - np.sort(r64.real)) / np.abs(np.sort(r64.real))) < 1e-3
