@@ -1,0 +1,216 @@
+/*
+ * pp.h -- C ABI of libpp: polynomial-preconditioned GMRES(m) on MI355X (gfx950).
+ *
+ * Method: Loe, Thornquist & Boman, "Polynomial Preconditioned GMRES to Reduce
+ * Communication in Parallel Computing" (arXiv 1907.00072).  The preconditioner
+ * is the GMRES minimum-residual polynomial p(A) of Section II, used on the right
+ * of GMRES(m) with two-pass classical Gram-Schmidt (Section III): solve
+ * A p(A) y = b, then x = p(A) y.
+ *
+ * Degree convention.  d = number of roots of the residual polynomial
+ * pi(alpha) = 1 - alpha p(alpha); p has degree d-1.  The paper's "deg" is d-1
+ * (its power basis has deg+1 columns and costs deg+1 products, Sections II-III).
+ * Applying p costs d-1 sparse products; one preconditioned step A p(A) v costs d.
+ *
+ * Root form.  The paper forms p from a power basis and the normal equations
+ * (Section II, eqs. (1)-(2)) and notes that this is unstable at higher degree
+ * (Section IV) and that more stable constructions exist (end of Section II,
+ * Section VIII).  This library uses the stable product form: the zeros of pi are
+ * the harmonic Ritz values theta_i of A on K_d(A, v0), the eigenvalues of
+ * H_d + h_{d+1,d}^2 H_d^{-T} e_d e_d^T from d Arnoldi steps on v0; they are
+ * applied in modified Leja order, a conjugate pair as one real quadratic factor.
+ * Both forms are the same polynomial in exact arithmetic.
+ *
+ * Conventions for every entry point
+ *  - Device pointers are HIP device (or managed) memory on the current device;
+ *    the caller owns them and the library keeps none of them past the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is ordered on that stream.  Calls that return results to the
+ *    host (build, solve) synchronise the stream before returning; pp_apply,
+ *    pp_csr_transpose and pp_csr_grad also synchronise, so every call is
+ *    complete on return and its temporaries can be reused.
+ *  - Internal temporaries (Krylov basis, chain vectors, reduction partials) come
+ *    from a per-device arena owned by the library, grown on demand and kept
+ *    until pp_release_workspace() or process exit.  Calls are serialised by a
+ *    library-wide lock.
+ *  - Return value: 0 = success; > 0 = warning, outputs are valid (see codes);
+ *    < 0 = error, outputs are unspecified (inputs are never modified, except x
+ *    in pp_gmres_solve, which then holds the last finite iterate).
+ *  - Reductions are two-stage in a fixed order without floating-point atomics,
+ *    so repeated calls with the same inputs give bitwise-identical results.
+ */
+#ifndef PP_H
+#define PP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define PP_OK 0
+#define PP_ERR_ARG (-1)       /* null pointer, n <= 0, d < 0, m < 1, tol <= 0, dtype or size mismatch */
+#define PP_ERR_HIP (-2)       /* a HIP runtime call failed */
+#define PP_ERR_NOMEM (-3)     /* device or pinned-host allocation failed */
+#define PP_ERR_EIG (-4)       /* Hessenberg QR iteration did not converge */
+#define PP_ERR_SINGULAR (-5)  /* H_d singular, or a zero / non-finite root */
+#define PP_WARN_DEGREE_REDUCED 1 /* Arnoldi on v0 broke down after s < d steps: s roots */
+#define PP_WARN_NOT_CONVERGED 2  /* iteration cap reached; x is the last iterate */
+#define PP_WARN_NONFINITE 3      /* NaN/Inf met; x is the last finite iterate */
+
+/* ---- value types ----------------------------------------------------- */
+#define PP_F64 0
+#define PP_F32 1
+
+/* ---- solve precision -------------------------------------------------- */
+#define PP_PREC_F64 0    /* everything in FP64 */
+#define PP_PREC_F32_IR 1 /* FP32 chain + CGS2 inside an FP64 refinement loop */
+
+/* Square sparse matrix in CSR form, all arrays in device memory.
+ * row_ptr[n+1] int32, row_ptr[0] = 0, nondecreasing, row_ptr[n] = nnz < 2^31;
+ * col_ind[nnz] int32 in [0, n) (any order inside a row; sorted is fastest);
+ * vals[nnz] of type dtype.  Duplicate (row, col) entries are summed. */
+typedef struct pp_csr {
+  int64_t n;
+  int64_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col_ind;
+  const void *vals;
+  int32_t dtype; /* PP_F64 or PP_F32 */
+} pp_csr;
+
+/* Opaque polynomial: n, the Leja-ordered roots (host, FP64) and the dtype it was
+ * built in.  Library-owned; free with pp_poly_free.  It holds no device memory
+ * and no pointer into A: pass the same A it was built from to pp_apply. */
+typedef struct pp_poly pp_poly;
+
+/* Optional solver controls.  Zero-initialise and set what you need; zero
+ * fields take the defaults shown. */
+typedef struct pp_opts {
+  int32_t max_iters;      /* cap on Arnoldi steps (inner steps for F32_IR); 0 -> 100000 */
+  int32_t precision;      /* PP_PREC_F64 (0) or PP_PREC_F32_IR */
+  double inner_tol;       /* F32_IR: inner cycle stops at this relative reduction; 0 -> 1e-5 */
+  int32_t max_outer;      /* F32_IR: cap on refinement steps; 0 -> 100 */
+  const double *v0;       /* device[n] start vector for the polynomial; NULL -> use b.
+                             Section V recommends a random vector (e.g. U(-1,1)). */
+  const pp_poly *poly;    /* reuse this polynomial instead of building one (d ignored) */
+  const float *vals_f32;  /* F32_IR: device[nnz] FP32 copy of A's values; NULL -> made internally */
+  double *history;        /* host[history_cap]: implicit relative residual after each step */
+  int32_t history_cap;
+  int32_t timing;         /* nonzero: fill the per-phase times in pp_stats (adds events) */
+} pp_opts;
+
+/* Solve statistics (all counts follow Section III: a "dot" is one block inner
+ * product or norm, three per Arnoldi step with CGS2). */
+typedef struct pp_stats {
+  int32_t status;          /* same as the return value */
+  int32_t iters;           /* Arnoldi steps of the (inner) GMRES */
+  int32_t cycles;          /* GMRES(m) cycles (restarts + 1) */
+  int32_t outer;           /* F32_IR refinement steps (0 in FP64 mode) */
+  int32_t nroots;          /* roots used (<= d; 0 = no polynomial) */
+  int32_t history_len;     /* entries written to opts->history */
+  int64_t spmvs;           /* sparse products with A, including the build */
+  int64_t dots;            /* block inner products and norms, including the build */
+  double relres_true;      /* ||b - A x|| / ||b|| at return (FP64) */
+  double relres_implicit;  /* last implicit (least-squares) estimate */
+  double t_total;          /* seconds, wall clock of the call */
+  double t_poly;           /* seconds building the polynomial (wall clock) */
+  double t_chain;          /* seconds in the p(A) chain kernels      (timing != 0) */
+  double t_spmv;           /* seconds in plain products / residuals  (timing != 0) */
+  double t_orth;           /* seconds in CGS2 kernels and reductions (timing != 0) */
+  double t_host;           /* seconds in host least squares and syncs (timing != 0) */
+} pp_stats;
+
+/* Build the polynomial for (A, v0) with d roots.
+ * Passage: Section II (the minimum-residual polynomial for a start vector v0),
+ * Section V (v0 random rather than b); root form as described above.
+ * Runs d Arnoldi steps (CGS2) on v0 in A's dtype on the device, then on the host
+ * in FP64 the harmonic Ritz eigenproblem (Francis double-shift QR) and the
+ * modified Leja order.
+ *   A   : matrix (PP_F64 or PP_F32)
+ *   v0  : device[n] FP64 start vector (cast to A's dtype for the Arnoldi); not modified
+ *   d   : 1 <= d <= min(n, 256)
+ *   out : receives a new pp_poly on success or warning
+ * Returns PP_OK, PP_WARN_DEGREE_REDUCED (fewer roots), PP_ERR_ARG, PP_ERR_SINGULAR
+ * (H_d singular, zero v0, or a zero/non-finite root), PP_ERR_EIG, PP_ERR_HIP, PP_ERR_NOMEM. */
+int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_poly **out);
+
+/* y = p(A) v.  Passage: Section II ("apply p(A) to a given vector").
+ * Product form in Leja order: for a real root theta, y += prod/theta and
+ * prod -= A prod / theta; a pair a +- ib is one real quadratic step with
+ * c1 = 2a/|theta|^2, c2 = 1/|theta|^2.  d-1 fused CSR-product + update kernels.
+ *   v, y : device[n] of A's dtype; may not alias.  y is overwritten.
+ * Returns PP_OK, PP_ERR_ARG (poly built for another n), PP_ERR_HIP, PP_ERR_NOMEM. */
+int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *stream);
+
+/* Solve A x = b with GMRES(m) right-preconditioned by the d-root polynomial.
+ * Passage: Section III (GMRES(m), two-pass classical Gram-Schmidt, relative
+ * residual ||b - A x|| / ||b|| < tol, polynomial on the right), Section V
+ * (start vector), Section II (the polynomial).  d = 0 runs plain GMRES(m).
+ *   A   : PP_F64 matrix (F32_IR makes or takes an FP32 copy of the values)
+ *   b   : device[n] FP64; x: device[n] FP64, in: x0, out: solution
+ *   m   : restart length, 1 <= m <= 256; tol > 0
+ *   opt : may be NULL (defaults); st: may be NULL
+ * A cycle ends early when the implicit residual drops below tol; convergence
+ * is decided on the true residual recomputed in FP64 after each cycle.
+ * F32_IR: the outer FP64 loop computes r = b - A x; an inner FP32 GMRES cycle
+ * (at most m steps, stop at relative reduction inner_tol) solves for the
+ * correction of r/||r||, and x += ||r|| * correction in FP64.
+ * Returns PP_OK, PP_WARN_DEGREE_REDUCED, PP_WARN_NOT_CONVERGED, PP_WARN_NONFINITE,
+ * or an error code. */
+int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, double tol,
+                   const pp_opts *opt, void *stream, pp_stats *st);
+
+/* Copy the Leja-ordered roots to host arrays re[cap], im[cap]; *d_out = number
+ * of roots.  A complex pair appears as (Im > 0, its conjugate) in adjacent slots.
+ * Returns PP_ERR_ARG if cap is too small or a pointer is NULL. */
+int pp_poly_roots(const pp_poly *p, double *re, double *im, int cap, int *d_out);
+
+/* Make a polynomial from given roots (host arrays), e.g. to resume a solve with
+ * the roots of an earlier build.  The roots are used in the order given; a
+ * complex root must be immediately followed by its exact conjugate, with the
+ * Im > 0 member first.  dtype is the value type it will be applied in.
+ * Returns PP_ERR_ARG on malformed pairs, PP_ERR_SINGULAR on a zero or
+ * non-finite root. */
+int pp_poly_from_roots(int64_t n, const double *re, const double *im, int d, int dtype,
+                       pp_poly **out);
+
+void pp_poly_free(pp_poly *p);
+
+/* Harmonic Ritz values from a host Hessenberg matrix, in modified Leja order.
+ * Host only, no device work.  Hbar is (s+1) x s, column-major with leading
+ * dimension ldh >= s+1 (the Arnoldi relation A Q_s = Q_{s+1} Hbar).  Outputs
+ * re[s], im[s].  Returns PP_ERR_SINGULAR if H_s is singular or a root is zero,
+ * PP_ERR_EIG if the QR iteration fails. */
+int pp_roots_from_hessenberg(const double *Hbar, int ldh, int s, double *re, double *im);
+
+/* Transpose of A in CSR form (the adjoint operator for the backward solve).
+ * Outputs are caller-allocated device arrays: rp_t[n+1], ci_t[nnz], vals_t[nnz]
+ * (A's dtype).  Columns of each output row come out sorted ascending.
+ * Returns PP_OK, PP_ERR_ARG, PP_ERR_HIP, PP_ERR_NOMEM. */
+int pp_csr_transpose(const pp_csr *A, int32_t *rp_t, int32_t *ci_t, void *vals_t, void *stream);
+
+/* Gradient of a loss with respect to A's stored values, given the adjoint
+ * solution lam (A^T lam = dL/dx) and the forward solution x:
+ * g_vals[k] = -lam[row(k)] * x[col(k)] for every stored entry k.
+ * All pointers device FP64 (lam[n], x[n], g_vals[nnz]); A's dtype is ignored
+ * (only the pattern is read).  Returns PP_OK, PP_ERR_ARG, PP_ERR_HIP. */
+int pp_csr_grad(const pp_csr *A, const double *lam, const double *x, double *g_vals,
+                void *stream);
+
+/* Free the library's device and pinned-host arena on every device. */
+void pp_release_workspace(void);
+
+/* Human-readable name of a status code (static string). */
+const char *pp_status_string(int code);
+
+/* Library version string, e.g. "libpp 0.1.0 gfx950". */
+const char *pp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PP_H */

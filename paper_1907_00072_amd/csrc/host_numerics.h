@@ -1,0 +1,39 @@
+// Host-side dense numerics for the polynomial build (FP64, no device code).
+#pragma once
+
+#include <vector>
+
+namespace ppn {
+
+// One step of the product-form chain in Leja order.
+//  kind == 0 (real root theta): c1 = 1/theta
+//  kind == 1 (pair a +- ib):   c1 = 2a/|theta|^2, c2 = 1/|theta|^2
+struct Step {
+  int kind;
+  double c1, c2;
+};
+
+// Eigenvalues of an s x s upper Hessenberg matrix (column-major, ld = s) by
+// Francis double-shift QR.  H is overwritten.  Complex eigenvalues come out as
+// exact conjugate pairs, real ones with wi == 0 exactly.  Returns 0 or a
+// negative PP_ERR_* code.
+int hessenberg_eigvals(int s, double *H, double *wr, double *wi);
+
+// Harmonic Ritz values of the (s+1) x s Hessenberg Hbar (column-major, ld):
+// eigenvalues of H_s + h^2 f e_s^T with H_s^T f = e_s, h = Hbar(s, s-1).
+int harmonic_ritz(const double *Hbar, int ldh, int s, std::vector<double> &wr,
+                  std::vector<double> &wi);
+
+// Modified Leja order (largest modulus first; then maximal product of
+// distances to the roots taken so far; complex roots as (Im>0, conjugate);
+// repeats last; ties to the earlier root in (Re, Im) order).
+int leja_order(const std::vector<double> &wr, const std::vector<double> &wi,
+               std::vector<double> &or_, std::vector<double> &oi);
+
+// Chain steps for roots already in order (pairs adjacent, Im>0 first).
+// Returns 0, or PP_ERR_ARG for a malformed pair, PP_ERR_SINGULAR for a zero or
+// non-finite root.
+int step_table(const std::vector<double> &re, const std::vector<double> &im,
+               std::vector<Step> &steps);
+
+}  // namespace ppn

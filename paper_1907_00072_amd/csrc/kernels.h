@@ -1,0 +1,128 @@
+// Launch wrappers for the gfx950 kernels (internal to libpp).
+//
+// Every wrapper enqueues on `stream` and returns the hipError_t of the launch.
+// Vectors are device arrays of T (double or float) unless stated; "scale"
+// pointers are device doubles multiplying the vector they belong to (nullptr
+// = 1).  Basis matrices V are column-major with leading dimension ldv.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ppk {
+
+constexpr int kBlock = 256;   // threads per workgroup (4 wavefronts of 64)
+constexpr int kMaxCols = 64;  // columns handled by one fused CGS2 sweep
+
+// CSR matrix view on the device.
+template <typename T>
+struct Csr {
+  int n;
+  int nnz;
+  const int32_t *rp;
+  const int32_t *ci;
+  const T *va;
+};
+
+// One launch of the fused product + root-update chain.
+//  kind 0 (real root): y = y_in + c1*p; p' = p - c1*A p  (fold: y += cf*p', p' not stored)
+//  kind 1 (pair, first half): t = A p; y = y_in + c1*p - c2*t (t stored unless last)
+//  kind 2 (pair, second half): p' = p - c1*t + c2*A t (fold: y = y_in + cf*p', p' not stored)
+// g is the gathered vector (p for kinds 0/1, t for kind 2), self is p for kind 2.
+template <typename T>
+struct ChainArgs {
+  const T *g;
+  const double *gscale;
+  const T *self;
+  const double *sscale;
+  T *out;
+  const T *y_in;  // nullptr = zero
+  T *y_out;
+  double c1, c2, cf;
+};
+
+template <typename T>
+hipError_t launch_chain(const Csr<T> &A, int kind, bool fold, bool noout, const ChainArgs<T> &a,
+                        hipStream_t stream);
+
+// y_out = y_in + c * (gscale * g) elementwise (a degree-0 polynomial step).
+template <typename T>
+hipError_t launch_axpy(int n, double c, const T *g, const double *gscale, const T *y_in, T *y_out,
+                       hipStream_t stream);
+
+// out = A * (gscale * g).
+template <typename T>
+hipError_t launch_spmv(const Csr<T> &A, const T *g, const double *gscale, T *out,
+                       hipStream_t stream);
+
+// out = b - A x (out may be a T-typed vector of the same type as A), and
+// partial[tile] = sum over the tile of out^2 (double).  Returns the tile count.
+template <typename T>
+hipError_t launch_residual(const Csr<T> &A, const T *b, const T *x, T *out, double *partial,
+                           int *ntiles, hipStream_t stream);
+
+// Number of workgroups of the CGS2 kernels for a vector of length n.
+int orth_grid(int n);
+
+// partial[(c0+c) * G + g] = sum over block g's rows of V(i, c0+c) * w(i), c < nc <= kMaxCols.
+template <typename T>
+hipError_t launch_dots(int n, const T *V, int64_t ldv, int c0, int nc, const T *w,
+                       double *partial, hipStream_t stream);
+
+// out = w_in - sum_c V(:, c) * coef(c),  coef(c) = sign * a(c) * (b ? b(c) : 1), nc <= kMaxCols.
+// w_in may be nullptr (zero) and may equal out.  With dots: partial dots of the
+// new vector with V(:, 0..nc) as in launch_dots.  With norm: partial[g] = sum of
+// out^2 over block g (double).
+template <typename T>
+hipError_t launch_update(int n, const T *V, int64_t ldv, int nc, const double *coef_a,
+                         const double *coef_b, double sign, const T *w_in, T *out, bool dots,
+                         bool norm, double *partial, hipStream_t stream);
+
+// partial[g] = sum over block g of (scale*x(i))^2 in double; optionally also
+// writes out32 = (float)(scale * x) when out32 != nullptr (the refinement cast).
+template <typename T>
+hipError_t launch_norm2(int n, const T *x, const double *scale, float *out32, double *partial,
+                        hipStream_t stream);
+
+// Second stage of the column reductions:
+//   h[c] = colscale[c0+c] * sum_g partial[(c0+c)*G + g];  coef[c] = colscale[c0+c] * h[c].
+hipError_t launch_reduce_cols(const double *partial, int G, int c0, int nc, const double *colscale,
+                              double *h, double *coef, hipStream_t stream);
+
+// Norm finalisation: nrm[0] = sqrt(sum_g partial[g]); if inv != nullptr,
+// inv[0] = 1/nrm (0 when nrm == 0).
+hipError_t launch_reduce_norm(const double *partial, int G, double *nrm, double *inv,
+                              hipStream_t stream);
+
+// Fill a device array with a value.
+template <typename T>
+hipError_t launch_fill(int64_t n, T value, T *x, hipStream_t stream);
+
+// x (double) += alpha * (double) d (float or double); alpha from device (*alpha_dev).
+template <typename T>
+hipError_t launch_axpy_f64(int n, const double *alpha_dev, const T *d, double *x,
+                           hipStream_t stream);
+
+// out32 = (float) in64
+hipError_t launch_cast_f32(int64_t n, const double *in, float *out, hipStream_t stream);
+
+// out = (T) in64 (copy when T == double)
+template <typename T>
+hipError_t launch_copy_from_f64(int n, const double *in, T *out, hipStream_t stream);
+
+// CSR transpose helpers and gradient.
+hipError_t launch_count_cols(int nnz, const int32_t *ci, int32_t *cnt, hipStream_t stream);
+hipError_t launch_exclusive_scan(int n, const int32_t *in, int32_t *out, int32_t *tmp,
+                                 hipStream_t stream);  // out[0..n], tmp >= scan_tmp_size(n)
+int64_t scan_tmp_size(int n);
+template <typename T>
+hipError_t launch_scatter_transpose(int n, const int32_t *rp, const int32_t *ci, const T *va,
+                                    const int32_t *rp_t, int32_t *cursor, int32_t *ci_t, T *va_t,
+                                    hipStream_t stream);
+template <typename T>
+hipError_t launch_sort_rows(int n, const int32_t *rp, int32_t *ci, T *va, hipStream_t stream);
+hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const double *lam,
+                           const double *x, double *g, hipStream_t stream);
+
+}  // namespace ppk

@@ -1,0 +1,733 @@
+// gfx950 kernels of the polynomial-preconditioned GMRES hot path.
+//
+// Every kernel here is bandwidth-bound (sparse products, GEMV-shaped
+// orthogonalisation), so there is no MFMA: the design goal is coalesced
+// streaming of the matrix and the Krylov basis from HBM and a single pass over
+// each per step.
+//
+// * Sparse products use a "CSR-stream" tile: a workgroup owns 256 consecutive
+//   rows; its threads first stream the tile's nonzeros contiguously (values,
+//   column indices and the gathered vector entry), writing the products into
+//   LDS, then each thread sums its own row from LDS.  Short stencil rows (5, 7 or
+//   27 entries) therefore cost fully coalesced loads instead of one
+//   partially-used cache line per row per lane.  The root update of the
+//   polynomial chain is fused into the epilogue of the same tile, so one launch
+//   reads A once and the chain vectors once.
+// * Tiles are remapped so that each of the 8 XCDs walks a contiguous range of
+//   rows (hardware dispatches workgroups round-robin over the XCDs): the
+//   vector entries a tile gathers from neighbouring rows / planes then tend to
+//   sit in that XCD's L2.
+// * The Gram-Schmidt kernels keep one basis row per thread in registers (a
+//   template bound on the column count), so each sweep reads every basis
+//   column once and updates the vector and accumulates the next pass's dot
+//   products in the same sweep.
+// * All reductions are two-stage in a fixed order (per-workgroup partials in
+//   memory, then a second kernel), with no floating-point atomics, so results
+//   are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace ppk {
+
+namespace {
+
+constexpr int kXcd = 8;
+constexpr int kOrthRowsTarget = 2048;  // aim for about this many CGS2 workgroups
+
+template <typename T>
+struct LdsCap;
+template <>
+struct LdsCap<double> {
+  static constexpr int value = 2048;
+};
+template <>
+struct LdsCap<float> {
+  static constexpr int value = 4096;
+};
+
+// Logical tile of workgroup b when the hardware deals workgroups to the XCDs
+// round-robin: XCD x receives workgroups x, x+8, ... and is given the
+// contiguous tile range [start_x, start_x + count_x).  A bijection on [0, G).
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  const int per = G / kXcd, rem = G % kXcd;
+  const int x = b % kXcd, i = b / kXcd;
+  return x * per + min(x, rem) + i;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the 256 threads of a workgroup, identical on every thread.
+__device__ __forceinline__ double block_sum(double v, double *red4) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red4[wv] = v;
+  __syncthreads();
+  const double r = ((red4[0] + red4[1]) + red4[2]) + red4[3];
+  __syncthreads();
+  return r;
+}
+
+// Row sums of A * g for the tile's rows (thread t -> row r0 + t).  All threads of
+// the workgroup must call it.  Rows past n return 0.
+template <typename T>
+__device__ __forceinline__ T tile_row_sum(const Csr<T> &A, const T *__restrict__ g, int r0,
+                                          int nrows, int *s_rp, T *s_buf) {
+  constexpr int CAP = LdsCap<T>::value;
+  const int t = threadIdx.x;
+  if (t < nrows) s_rp[t] = A.rp[r0 + t];
+  if (t == 0) s_rp[nrows] = A.rp[r0 + nrows];
+  __syncthreads();
+  const int kb = s_rp[0], ke = s_rp[nrows];
+  int rb = 0, re = 0;
+  if (t < nrows) {
+    rb = s_rp[t];
+    re = s_rp[t + 1];
+  }
+  T acc = T(0);
+  for (int c0 = kb; c0 < ke; c0 += CAP) {
+    const int c1 = min(c0 + CAP, ke);
+    for (int k = c0 + t; k < c1; k += kBlock) {
+      const T v = __builtin_nontemporal_load(A.va + k);
+      const int c = __builtin_nontemporal_load(A.ci + k);
+      s_buf[k - c0] = v * g[c];
+    }
+    __syncthreads();
+    const int lo = max(rb, c0), hi = min(re, c1);
+    for (int k = lo; k < hi; ++k) acc += s_buf[k - c0];
+    __syncthreads();
+  }
+  return acc;
+}
+
+// ------------------------------------------------------------------ chain
+template <typename T, int KIND, bool FOLD, bool NOOUT>
+__global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
+  __shared__ int s_rp[kBlock + 1];
+  __shared__ T s_buf[LdsCap<T>::value];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int r0 = tile * kBlock;
+  const int nrows = min(kBlock, A.n - r0);
+  const T gs = a.gscale ? (T)(*a.gscale) : T(1);
+  const T acc = tile_row_sum(A, a.g, r0, nrows, s_rp, s_buf);
+  const int t = threadIdx.x;
+  if (t >= nrows) return;
+  const int i = r0 + t;
+  const T c1 = (T)a.c1, c2 = (T)a.c2, cf = (T)a.cf;
+  if constexpr (KIND == 0) {
+    const T p = gs * a.g[i];
+    const T ap = gs * acc;
+    T y = (a.y_in ? a.y_in[i] : T(0)) + c1 * p;
+    const T pn = p - c1 * ap;
+    if constexpr (FOLD) {
+      y += cf * pn;
+    } else {
+      a.out[i] = pn;
+    }
+    a.y_out[i] = y;
+  } else if constexpr (KIND == 1) {
+    const T p = gs * a.g[i];
+    const T tt = gs * acc;
+    a.y_out[i] = (a.y_in ? a.y_in[i] : T(0)) + c1 * p - c2 * tt;
+    if constexpr (!NOOUT) a.out[i] = tt;
+  } else {
+    const T ss = a.sscale ? (T)(*a.sscale) : T(1);
+    const T pn = ss * a.self[i] - c1 * (gs * a.g[i]) + c2 * (gs * acc);
+    if constexpr (FOLD) {
+      a.y_out[i] = a.y_in[i] + cf * pn;
+    } else {
+      a.out[i] = pn;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spmv(Csr<T> A, const T *__restrict__ g,
+                                                 const double *gscale, T *__restrict__ out) {
+  __shared__ int s_rp[kBlock + 1];
+  __shared__ T s_buf[LdsCap<T>::value];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int r0 = tile * kBlock;
+  const int nrows = min(kBlock, A.n - r0);
+  const T acc = tile_row_sum(A, g, r0, nrows, s_rp, s_buf);
+  if (threadIdx.x < nrows) out[r0 + threadIdx.x] = (gscale ? (T)(*gscale) : T(1)) * acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(Csr<T> A, const T *__restrict__ b,
+                                                     const T *__restrict__ x, T *__restrict__ out,
+                                                     double *__restrict__ partial) {
+  __shared__ int s_rp[kBlock + 1];
+  __shared__ T s_buf[LdsCap<T>::value];
+  __shared__ double red[4];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int r0 = tile * kBlock;
+  const int nrows = min(kBlock, A.n - r0);
+  const T acc = tile_row_sum(A, x, r0, nrows, s_rp, s_buf);
+  double sq = 0.0;
+  if (threadIdx.x < nrows) {
+    const T r = b[r0 + threadIdx.x] - acc;
+    out[r0 + threadIdx.x] = r;
+    sq = (double)r * (double)r;
+  }
+  sq = block_sum(sq, red);
+  if (threadIdx.x == 0) partial[tile] = sq;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpy(int n, double c, const T *__restrict__ g,
+                                                 const double *gscale, const T *y_in, T *y_out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const T gs = gscale ? (T)(*gscale) : T(1);
+  y_out[i] = (y_in ? y_in[i] : T(0)) + (T)c * (gs * g[i]);
+}
+
+// ------------------------------------------------------------------ CGS2
+template <typename T, int NCB>
+__global__ __launch_bounds__(kBlock) void k_dots(int n, int rpt, const T *__restrict__ V,
+                                                 int64_t ldv, int c0, int nc,
+                                                 const T *__restrict__ w,
+                                                 double *__restrict__ partial) {
+  __shared__ double red[4][NCB];
+  T acc[NCB];
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) acc[c] = T(0);
+  const int64_t base = (int64_t)blockIdx.x * rpt * kBlock + threadIdx.x;
+  const T *Vc = V + (int64_t)c0 * ldv;
+  for (int r = 0; r < rpt; ++r) {
+    const int64_t i = base + (int64_t)r * kBlock;
+    if (i < n) {
+      const T wi = w[i];
+#pragma unroll
+      for (int c = 0; c < NCB; ++c)
+        if (c < nc) acc[c] += __builtin_nontemporal_load(Vc + (int64_t)c * ldv + i) * wi;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) {
+    if (c < nc) {
+      const double s = wave_sum((double)acc[c]);
+      if (lane == 0) red[wv][c] = s;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nc) {
+    const int c = threadIdx.x;
+    partial[(int64_t)(c0 + c) * gridDim.x + blockIdx.x] =
+        ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+  }
+}
+
+template <typename T, int NCB, bool DOTS, bool NORM>
+__global__ __launch_bounds__(kBlock) void k_update(int n, int rpt, const T *__restrict__ V,
+                                                   int64_t ldv, int nc, const double *coef_a,
+                                                   const double *coef_b, double sign,
+                                                   const T *w_in, T *out,
+                                                   double *__restrict__ partial) {
+  __shared__ T s_coef[NCB];
+  __shared__ double red[4][DOTS ? NCB : 1];
+  __shared__ double red4[4];
+  if ((int)threadIdx.x < nc) {
+    const int c = threadIdx.x;
+    s_coef[c] = (T)(sign * coef_a[c] * (coef_b ? coef_b[c] : 1.0));
+  }
+  __syncthreads();
+  T acc[DOTS ? NCB : 1];
+#pragma unroll
+  for (int c = 0; c < (DOTS ? NCB : 1); ++c) acc[c] = T(0);
+  double nacc = 0.0;
+  const int64_t base = (int64_t)blockIdx.x * rpt * kBlock + threadIdx.x;
+  for (int r = 0; r < rpt; ++r) {
+    const int64_t i = base + (int64_t)r * kBlock;
+    if (i < n) {
+      T v[NCB];
+#pragma unroll
+      for (int c = 0; c < NCB; ++c)
+        if (c < nc) v[c] = __builtin_nontemporal_load(V + (int64_t)c * ldv + i);
+      T wi = w_in ? w_in[i] : T(0);
+#pragma unroll
+      for (int c = 0; c < NCB; ++c)
+        if (c < nc) wi -= v[c] * s_coef[c];
+      out[i] = wi;
+      if constexpr (DOTS) {
+#pragma unroll
+        for (int c = 0; c < NCB; ++c)
+          if (c < nc) acc[c] += v[c] * wi;
+      }
+      if constexpr (NORM) nacc += (double)wi * (double)wi;
+    }
+  }
+  if constexpr (DOTS) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+      if (c < nc) {
+        const double s = wave_sum((double)acc[c]);
+        if (lane == 0) red[wv][c] = s;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+      const int c = threadIdx.x;
+      partial[(int64_t)c * gridDim.x + blockIdx.x] =
+          ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    }
+  }
+  if constexpr (NORM) {
+    const double s = block_sum(nacc, red4);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_norm2(int n, int rpt, const T *__restrict__ x,
+                                                  const double *scale, float *out32,
+                                                  double *__restrict__ partial) {
+  __shared__ double red4[4];
+  const double sc = scale ? *scale : 1.0;
+  double acc = 0.0;
+  const int64_t base = (int64_t)blockIdx.x * rpt * kBlock + threadIdx.x;
+  for (int r = 0; r < rpt; ++r) {
+    const int64_t i = base + (int64_t)r * kBlock;
+    if (i < n) {
+      const double v = (double)x[i] * sc;
+      if (out32) {
+        const float f = (float)v;
+        out32[i] = f;
+        acc += (double)f * (double)f;
+      } else {
+        acc += v * v;
+      }
+    }
+  }
+  acc = block_sum(acc, red4);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_cols(const double *__restrict__ partial, int G,
+                                                        int c0, const double *colscale, double *h,
+                                                        double *coef) {
+  __shared__ double red4[4];
+  const int c = c0 + blockIdx.x;
+  double s = 0.0;
+  for (int g = threadIdx.x; g < G; g += kBlock) s += partial[(int64_t)c * G + g];
+  s = block_sum(s, red4);
+  if (threadIdx.x == 0) {
+    const double sc = colscale ? colscale[c] : 1.0;
+    const double hv = sc * s;
+    h[c] = hv;
+    if (coef) coef[c] = sc * hv;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_norm(const double *__restrict__ partial, int G,
+                                                        double *nrm, double *inv) {
+  __shared__ double red4[4];
+  double s = 0.0;
+  for (int g = threadIdx.x; g < G; g += kBlock) s += partial[g];
+  s = block_sum(s, red4);
+  if (threadIdx.x == 0) {
+    const double r = sqrt(s);
+    nrm[0] = r;
+    if (inv) inv[0] = (r > 0.0) ? 1.0 / r : 0.0;
+  }
+}
+
+// ------------------------------------------------------------ elementwise
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, T value, T *x) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = value;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpy_f64(int n, const double *alpha,
+                                                     const T *__restrict__ d, double *x) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] += (*alpha) * (double)d[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_f32(int64_t n, const double *__restrict__ in,
+                                                     float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy_from_f64(int n, const double *__restrict__ in,
+                                                          T *__restrict__ out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = (T)in[i];
+}
+
+// ------------------------------------------------------------- transpose
+__global__ __launch_bounds__(kBlock) void k_count_cols(int nnz, const int32_t *__restrict__ ci,
+                                                       int32_t *cnt) {
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < nnz; k += gridDim.x * kBlock)
+    atomicAdd(&cnt[ci[k]], 1);
+}
+
+constexpr int kScanPerThread = 4;
+constexpr int kScanPerBlock = kBlock * kScanPerThread;
+
+// Exclusive scan of thread sums inside a workgroup; returns the workgroup total.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *s, int32_t *excl) {
+  const int t = threadIdx.x;
+  s[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int32_t add = (t >= off) ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  *excl = s[t] - v;
+  const int32_t total = s[kBlock - 1];
+  __syncthreads();
+  return total;
+}
+
+// out[1 + i] = inclusive scan of in inside each 1024-element chunk; tmp[chunk] = chunk total.
+__global__ __launch_bounds__(kBlock) void k_scan_chunks(int n, const int32_t *__restrict__ in,
+                                                        int32_t *__restrict__ out,
+                                                        int32_t *__restrict__ tmp) {
+  __shared__ int32_t s[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + threadIdx.x * kScanPerThread;
+  int32_t v[kScanPerThread];
+  int32_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPerThread; ++q) {
+    v[q] = (base + q < n) ? in[base + q] : 0;
+    sum += v[q];
+  }
+  int32_t excl;
+  const int32_t total = block_exclusive_scan(sum, s, &excl);
+  int32_t run = excl;
+#pragma unroll
+  for (int q = 0; q < kScanPerThread; ++q) {
+    run += v[q];
+    if (base + q < n) out[1 + base + q] = run;
+  }
+  if (threadIdx.x == 0) tmp[blockIdx.x] = total;
+}
+
+// Exclusive scan of the chunk totals in place (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_scan_tops(int nchunks, int32_t *tmp) {
+  __shared__ int32_t s[kBlock];
+  int32_t carry = 0;
+  for (int c0 = 0; c0 < nchunks; c0 += kBlock) {
+    const int i = c0 + threadIdx.x;
+    const int32_t v = (i < nchunks) ? tmp[i] : 0;
+    int32_t excl;
+    const int32_t total = block_exclusive_scan(v, s, &excl);
+    if (i < nchunks) tmp[i] = carry + excl;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(int n, int32_t *out,
+                                                     const int32_t *__restrict__ tmp) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i == 0) out[0] = 0;
+  if (i < n) out[1 + i] += tmp[i / kScanPerBlock];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter_transpose(
+    int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const T *__restrict__ va, const int32_t *__restrict__ rp_t, int32_t *cursor,
+    int32_t *__restrict__ ci_t, T *__restrict__ va_t) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = ci[k];
+    const int pos = rp_t[j] + atomicAdd(&cursor[j], 1);
+    ci_t[pos] = i;
+    va_t[pos] = va[k];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sort_rows(int n, const int32_t *__restrict__ rp,
+                                                      int32_t *ci, T *va) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int lo = rp[i], hi = rp[i + 1];
+  for (int k = lo + 1; k < hi; ++k) {
+    const int key = ci[k];
+    const T val = va[k];
+    int q = k - 1;
+    while (q >= lo && ci[q] > key) {
+      ci[q + 1] = ci[q];
+      va[q + 1] = va[q];
+      --q;
+    }
+    ci[q + 1] = key;
+    va[q + 1] = val;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_csr_grad(int n, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci,
+                                                     const double *__restrict__ lam,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ g) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double li = lam[i];
+  for (int k = rp[i]; k < rp[i + 1]; ++k) g[k] = -li * x[ci[k]];
+}
+
+inline int tiles_of(int n) { return (n + kBlock - 1) / kBlock; }
+inline unsigned blocks_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+inline int orth_rpt(int n) {
+  const int64_t per = (int64_t)kBlock * kOrthRowsTarget;
+  int rpt = (int)((n + per - 1) / per);
+  return rpt < 1 ? 1 : rpt;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- wrappers
+template <typename T>
+hipError_t launch_chain(const Csr<T> &A, int kind, bool fold, bool noout, const ChainArgs<T> &a,
+                        hipStream_t stream) {
+  const dim3 grid(tiles_of(A.n)), block(kBlock);
+  if (kind == 0) {
+    if (fold)
+      hipLaunchKernelGGL((k_chain<T, 0, true, false>), grid, block, 0, stream, A, a);
+    else
+      hipLaunchKernelGGL((k_chain<T, 0, false, false>), grid, block, 0, stream, A, a);
+  } else if (kind == 1) {
+    if (noout)
+      hipLaunchKernelGGL((k_chain<T, 1, false, true>), grid, block, 0, stream, A, a);
+    else
+      hipLaunchKernelGGL((k_chain<T, 1, false, false>), grid, block, 0, stream, A, a);
+  } else {
+    if (fold)
+      hipLaunchKernelGGL((k_chain<T, 2, true, false>), grid, block, 0, stream, A, a);
+    else
+      hipLaunchKernelGGL((k_chain<T, 2, false, false>), grid, block, 0, stream, A, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axpy(int n, double c, const T *g, const double *gscale, const T *y_in, T *y_out,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL((k_axpy<T>), dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, c, g, gscale,
+                     y_in, y_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spmv(const Csr<T> &A, const T *g, const double *gscale, T *out,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL((k_spmv<T>), dim3(tiles_of(A.n)), dim3(kBlock), 0, stream, A, g, gscale,
+                     out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_residual(const Csr<T> &A, const T *b, const T *x, T *out, double *partial,
+                           int *ntiles, hipStream_t stream) {
+  *ntiles = tiles_of(A.n);
+  hipLaunchKernelGGL((k_residual<T>), dim3(*ntiles), dim3(kBlock), 0, stream, A, b, x, out,
+                     partial);
+  return hipGetLastError();
+}
+
+int orth_grid(int n) {
+  const int rpt = orth_rpt(n);
+  const int64_t per = (int64_t)kBlock * rpt;
+  return (int)((n + per - 1) / per);
+}
+
+template <typename T>
+hipError_t launch_dots(int n, const T *V, int64_t ldv, int c0, int nc, const T *w,
+                       double *partial, hipStream_t stream) {
+  if (nc < 1 || nc > kMaxCols) return hipErrorInvalidValue;
+  const int rpt = orth_rpt(n), G = orth_grid(n);
+  const dim3 grid(G), block(kBlock);
+  if (nc <= 8)
+    hipLaunchKernelGGL((k_dots<T, 8>), grid, block, 0, stream, n, rpt, V, ldv, c0, nc, w, partial);
+  else if (nc <= 16)
+    hipLaunchKernelGGL((k_dots<T, 16>), grid, block, 0, stream, n, rpt, V, ldv, c0, nc, w,
+                       partial);
+  else if (nc <= 32)
+    hipLaunchKernelGGL((k_dots<T, 32>), grid, block, 0, stream, n, rpt, V, ldv, c0, nc, w,
+                       partial);
+  else
+    hipLaunchKernelGGL((k_dots<T, 64>), grid, block, 0, stream, n, rpt, V, ldv, c0, nc, w,
+                       partial);
+  return hipGetLastError();
+}
+
+template <typename T, bool DOTS, bool NORM>
+static void update_dispatch(int n, const T *V, int64_t ldv, int nc, const double *ca,
+                            const double *cb, double sign, const T *w_in, T *out, double *partial,
+                            hipStream_t stream) {
+  const int rpt = orth_rpt(n), G = orth_grid(n);
+  const dim3 grid(G), block(kBlock);
+  if (nc <= 8)
+    hipLaunchKernelGGL((k_update<T, 8, DOTS, NORM>), grid, block, 0, stream, n, rpt, V, ldv, nc,
+                       ca, cb, sign, w_in, out, partial);
+  else if (nc <= 16)
+    hipLaunchKernelGGL((k_update<T, 16, DOTS, NORM>), grid, block, 0, stream, n, rpt, V, ldv, nc,
+                       ca, cb, sign, w_in, out, partial);
+  else if (nc <= 32)
+    hipLaunchKernelGGL((k_update<T, 32, DOTS, NORM>), grid, block, 0, stream, n, rpt, V, ldv, nc,
+                       ca, cb, sign, w_in, out, partial);
+  else
+    hipLaunchKernelGGL((k_update<T, 64, DOTS, NORM>), grid, block, 0, stream, n, rpt, V, ldv, nc,
+                       ca, cb, sign, w_in, out, partial);
+}
+
+template <typename T>
+hipError_t launch_update(int n, const T *V, int64_t ldv, int nc, const double *coef_a,
+                         const double *coef_b, double sign, const T *w_in, T *out, bool dots,
+                         bool norm, double *partial, hipStream_t stream) {
+  if (nc < 1 || nc > kMaxCols || (dots && norm)) return hipErrorInvalidValue;
+  if (dots)
+    update_dispatch<T, true, false>(n, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
+                                    stream);
+  else if (norm)
+    update_dispatch<T, false, true>(n, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
+                                    stream);
+  else
+    update_dispatch<T, false, false>(n, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
+                                     stream);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_norm2(int n, const T *x, const double *scale, float *out32, double *partial,
+                        hipStream_t stream) {
+  hipLaunchKernelGGL((k_norm2<T>), dim3(orth_grid(n)), dim3(kBlock), 0, stream, n, orth_rpt(n), x,
+                     scale, out32, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_cols(const double *partial, int G, int c0, int nc, const double *colscale,
+                              double *h, double *coef, hipStream_t stream) {
+  hipLaunchKernelGGL(k_reduce_cols, dim3(nc), dim3(kBlock), 0, stream, partial, G, c0, colscale, h,
+                     coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_norm(const double *partial, int G, double *nrm, double *inv,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(kBlock), 0, stream, partial, G, nrm, inv);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(int64_t n, T value, T *x, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_fill<T>), dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, value, x);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axpy_f64(int n, const double *alpha_dev, const T *d, double *x,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL((k_axpy_f64<T>), dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, alpha_dev,
+                     d, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_f32(int64_t n, const double *in, float *out, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_f32, dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, in, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy_from_f64(int n, const double *in, T *out, hipStream_t stream) {
+  hipLaunchKernelGGL((k_copy_from_f64<T>), dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, in,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_cols(int nnz, const int32_t *ci, int32_t *cnt, hipStream_t stream) {
+  if (nnz <= 0) return hipSuccess;
+  unsigned g = blocks_of(nnz);
+  if (g > 65536u) g = 65536u;
+  hipLaunchKernelGGL(k_count_cols, dim3(g), dim3(kBlock), 0, stream, nnz, ci, cnt);
+  return hipGetLastError();
+}
+
+int64_t scan_tmp_size(int n) { return (n + kScanPerBlock - 1) / kScanPerBlock + 1; }
+
+hipError_t launch_exclusive_scan(int n, const int32_t *in, int32_t *out, int32_t *tmp,
+                                 hipStream_t stream) {
+  const int nch = (n + kScanPerBlock - 1) / kScanPerBlock;
+  if (nch > 0) {
+    hipLaunchKernelGGL(k_scan_chunks, dim3(nch), dim3(kBlock), 0, stream, n, in, out, tmp);
+    hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(kBlock), 0, stream, nch, tmp);
+  }
+  hipLaunchKernelGGL(k_scan_add, dim3(n > 0 ? blocks_of(n) : 1), dim3(kBlock), 0, stream, n, out,
+                     tmp);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scatter_transpose(int n, const int32_t *rp, const int32_t *ci, const T *va,
+                                    const int32_t *rp_t, int32_t *cursor, int32_t *ci_t, T *va_t,
+                                    hipStream_t stream) {
+  hipLaunchKernelGGL((k_scatter_transpose<T>), dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, rp,
+                     ci, va, rp_t, cursor, ci_t, va_t);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sort_rows(int n, const int32_t *rp, int32_t *ci, T *va, hipStream_t stream) {
+  hipLaunchKernelGGL((k_sort_rows<T>), dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, rp, ci, va);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const double *lam,
+                           const double *x, double *g, hipStream_t stream) {
+  hipLaunchKernelGGL(k_csr_grad, dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, rp, ci, lam, x,
+                     g);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+#define PP_INST(T)                                                                              \
+  template hipError_t launch_chain<T>(const Csr<T> &, int, bool, bool, const ChainArgs<T> &,    \
+                                      hipStream_t);                                             \
+  template hipError_t launch_axpy<T>(int, double, const T *, const double *, const T *, T *,    \
+                                     hipStream_t);                                              \
+  template hipError_t launch_spmv<T>(const Csr<T> &, const T *, const double *, T *,           \
+                                     hipStream_t);                                              \
+  template hipError_t launch_residual<T>(const Csr<T> &, const T *, const T *, T *, double *,  \
+                                         int *, hipStream_t);                                   \
+  template hipError_t launch_dots<T>(int, const T *, int64_t, int, int, const T *, double *,    \
+                                     hipStream_t);                                              \
+  template hipError_t launch_update<T>(int, const T *, int64_t, int, const double *,            \
+                                       const double *, double, const T *, T *, bool, bool,      \
+                                       double *, hipStream_t);                                  \
+  template hipError_t launch_norm2<T>(int, const T *, const double *, float *, double *,        \
+                                      hipStream_t);                                             \
+  template hipError_t launch_fill<T>(int64_t, T, T *, hipStream_t);                             \
+  template hipError_t launch_axpy_f64<T>(int, const double *, const T *, double *,              \
+                                         hipStream_t);                                          \
+  template hipError_t launch_copy_from_f64<T>(int, const double *, T *, hipStream_t);           \
+  template hipError_t launch_scatter_transpose<T>(int, const int32_t *, const int32_t *,        \
+                                                  const T *, const int32_t *, int32_t *,        \
+                                                  int32_t *, T *, hipStream_t);                 \
+  template hipError_t launch_sort_rows<T>(int, const int32_t *, int32_t *, T *, hipStream_t);
+
+PP_INST(double)
+PP_INST(float)
+template hipError_t launch_fill<int32_t>(int64_t, int32_t, int32_t *, hipStream_t);
+
+}  // namespace ppk

@@ -1,0 +1,996 @@
+// libpp host driver: the C ABI of include/pp.h.
+//
+// The device does every O(n) step (kernels.hip); the host keeps only the
+// small dense state of the method: the (m+1) x m Hessenberg matrix, its Givens
+// rotations and least-squares solution, and the d x d harmonic Ritz
+// eigenproblem (host_numerics.cpp).  Each Arnoldi step ends with one
+// device-to-host copy of the new Hessenberg column (the two CGS passes'
+// coefficients and the norm) and one stream synchronisation.
+//
+// Basis storage: column c of the Krylov basis is kept unnormalised in V and
+// scaled on the fly by colscale[c] (a device array written by the norm
+// reduction), so no separate normalisation pass is needed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/pp.h"
+#include "host_numerics.h"
+#include "kernels.h"
+
+struct pp_poly {
+  int64_t n;
+  int dtype;
+  std::vector<double> re, im;
+  std::vector<ppn::Step> steps;
+};
+
+namespace {
+
+using ppk::Csr;
+
+constexpr int kMaxM = 256;
+constexpr int kMaxD = 256;
+constexpr double kBreakdownRtol = 1e-12;
+
+#define PP_TRY_HIP(expr)                              \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return PP_ERR_HIP;          \
+  } while (0)
+#define PP_TRY(expr)                                  \
+  do {                                                \
+    int r_ = (expr);                                  \
+    if (r_ < 0) return r_;                            \
+  } while (0)
+
+std::mutex g_lock;
+
+struct Arena {
+  char *dev = nullptr;
+  size_t dev_cap = 0;
+  double *host = nullptr;  // pinned
+  size_t host_cap = 0;     // in doubles
+};
+std::vector<Arena> g_arena;
+
+int current_arena(Arena **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PP_ERR_HIP;
+  if ((int)g_arena.size() <= dev) g_arena.resize(dev + 1);
+  *out = &g_arena[dev];
+  return PP_OK;
+}
+
+int ensure_arena(Arena *a, size_t dev_bytes, size_t host_doubles) {
+  if (dev_bytes > a->dev_cap) {
+    if (a->dev) {
+      if (hipDeviceSynchronize() != hipSuccess) return PP_ERR_HIP;
+      (void)hipFree(a->dev);
+      a->dev = nullptr;
+      a->dev_cap = 0;
+    }
+    if (hipMalloc((void **)&a->dev, dev_bytes) != hipSuccess) {
+      a->dev = nullptr;
+      return PP_ERR_NOMEM;
+    }
+    a->dev_cap = dev_bytes;
+  }
+  if (host_doubles > a->host_cap) {
+    if (a->host) (void)hipHostFree(a->host);
+    a->host = nullptr;
+    a->host_cap = 0;
+    if (hipHostMalloc((void **)&a->host, host_doubles * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess) {
+      a->host = nullptr;
+      return PP_ERR_NOMEM;
+    }
+    a->host_cap = host_doubles;
+  }
+  return PP_OK;
+}
+
+// Sequential 256-byte aligned carving of the device arena.  With base == nullptr
+// it only measures.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(char *b) : base(b) {}
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+inline int64_t pad_ld(int64_t n) { return (n + 63) / 64 * 64; }
+
+// Device workspace of one solve in compute type T.
+template <typename T>
+struct Work {
+  int n = 0, L = 0, G = 0;  // L = basis columns, G = CGS2 workgroups
+  int64_t ldv = 0;
+  T *V = nullptr, *P0 = nullptr, *P1 = nullptr, *Tb = nullptr, *Z = nullptr, *W = nullptr,
+    *U = nullptr;
+  double *partial = nullptr;
+  double *colscale = nullptr;  // [L]
+  double *hbuf = nullptr;      // [2L + 8]: h1 | h2 | nrm
+  double *coef1 = nullptr, *coef2 = nullptr, *ybuf = nullptr;  // [L] each
+  double *misc = nullptr;      // [16]
+  double *host = nullptr;      // pinned [2L + 8 + L]
+
+  template <typename C>
+  void carve(C &c, int n_, int L_) {
+    n = n_;
+    L = L_;
+    G = ppk::orth_grid(n_);
+    ldv = pad_ld(n_);
+    V = c.template take<T>((size_t)ldv * L);
+    P0 = c.template take<T>(ldv);
+    P1 = c.template take<T>(ldv);
+    Tb = c.template take<T>(ldv);
+    Z = c.template take<T>(ldv);
+    W = c.template take<T>(ldv);
+    U = c.template take<T>(ldv);
+    const size_t tiles = (size_t)(n_ + ppk::kBlock - 1) / ppk::kBlock;
+    partial = c.template take<double>(std::max((size_t)L * G, tiles) + 64);
+    colscale = c.template take<double>(L);
+    hbuf = c.template take<double>(2 * (size_t)L + 8);
+    coef1 = c.template take<double>(L);
+    coef2 = c.template take<double>(L);
+    ybuf = c.template take<double>(L);
+    misc = c.template take<double>(16);
+  }
+  size_t host_doubles() const { return 3 * (size_t)L + 16; }
+};
+
+struct Timers {
+  bool on = false;
+  hipEvent_t ev[5] = {};
+  double chain = 0, spmv = 0, orth = 0, host = 0;
+  int init() {
+    for (auto &e : ev)
+      if (hipEventCreate(&e) != hipSuccess) return PP_ERR_HIP;
+    return PP_OK;
+  }
+  ~Timers() {
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void mark(int k, hipStream_t s) {
+    if (on) (void)hipEventRecord(ev[k], s);
+  }
+  void collect() {
+    if (!on) return;
+    float a = 0, b = 0, c = 0;
+    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&c, ev[2], ev[3]);
+    chain += a * 1e-3;
+    spmv += b * 1e-3;
+    orth += c * 1e-3;
+  }
+};
+
+struct Counters {
+  int64_t spmvs = 0, dots = 0;
+  int iters = 0;
+  double *history = nullptr;
+  int history_cap = 0, history_len = 0;
+  void push(double v) {
+    if (history && history_len < history_cap) history[history_len++] = v;
+  }
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+inline bool finite(double v) { return std::isfinite(v); }
+
+// ------------------------------------------------------------------ chain
+// y_out = y_in + p(A) (gscale * g) for the step table; y_in may be nullptr
+// (zero) or equal y_out.  Uses P0, P1, Tb as chain temporaries.
+template <typename T>
+int run_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
+              const double *gscale, const T *y_in, T *y_out, T *P0, T *P1, T *Tb,
+              hipStream_t s, Counters *cnt) {
+  const int K = (int)steps.size();
+  const T *cur = g;
+  const double *cs = gscale;
+  const T *yi = y_in;
+  T *bufs[2] = {P0, P1};
+  int pb = 0;
+  for (int k = 0; k < K; ++k) {
+    const ppn::Step &st = steps[k];
+    const bool last = (k == K - 1);
+    const bool fold = (k + 2 == K) && steps[k + 1].kind == 0;
+    const double cf = fold ? steps[k + 1].c1 : 0.0;
+    if (st.kind == 0) {
+      if (last) {  // only for a single real root
+        PP_TRY_HIP(ppk::launch_axpy<T>(A.n, st.c1, cur, cs, yi, y_out, s));
+        break;
+      }
+      ppk::ChainArgs<T> a{cur, cs, nullptr, nullptr, fold ? nullptr : bufs[pb], yi, y_out,
+                          st.c1, 0.0, cf};
+      PP_TRY_HIP(ppk::launch_chain<T>(A, 0, fold, false, a, s));
+      if (cnt) cnt->spmvs++;
+      yi = y_out;
+      if (fold) break;
+      cur = bufs[pb];
+      cs = nullptr;
+      pb ^= 1;
+    } else {
+      ppk::ChainArgs<T> a{cur, cs, nullptr, nullptr, last ? nullptr : Tb, yi, y_out,
+                          st.c1, st.c2, 0.0};
+      PP_TRY_HIP(ppk::launch_chain<T>(A, 1, false, last, a, s));
+      if (cnt) cnt->spmvs++;
+      yi = y_out;
+      if (last) break;
+      ppk::ChainArgs<T> b{Tb, nullptr, cur, cs, fold ? nullptr : bufs[pb], yi, y_out,
+                          st.c1, st.c2, cf};
+      PP_TRY_HIP(ppk::launch_chain<T>(A, 2, fold, false, b, s));
+      if (cnt) cnt->spmvs++;
+      if (fold) break;
+      cur = bufs[pb];
+      cs = nullptr;
+      pb ^= 1;
+    }
+  }
+  return PP_OK;
+}
+
+// out = w_in - V(:, 0..nc) coef (chunks of kMaxCols columns); optional norm of out.
+template <typename T>
+int update_any(Work<T> &w, int nc, const double *coef, const T *w_in, T *out, bool norm,
+               hipStream_t s) {
+  for (int c0 = 0; c0 < nc; c0 += ppk::kMaxCols) {
+    const int cc = std::min(ppk::kMaxCols, nc - c0);
+    const bool lastc = (c0 + cc >= nc);
+    PP_TRY_HIP(ppk::launch_update<T>(w.n, w.V + (int64_t)c0 * w.ldv, w.ldv, cc, coef + c0,
+                                     nullptr, 1.0, c0 == 0 ? w_in : out, out, false,
+                                     norm && lastc, w.partial, s));
+  }
+  return PP_OK;
+}
+
+template <typename T>
+int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s) {
+  for (int c0 = 0; c0 < nc; c0 += ppk::kMaxCols) {
+    const int cc = std::min(ppk::kMaxCols, nc - c0);
+    PP_TRY_HIP(ppk::launch_dots<T>(w.n, w.V, w.ldv, c0, cc, vec, w.partial, s));
+  }
+  return PP_OK;
+}
+
+// One Arnoldi step j: w = Op(V_j), two CGS passes, V_{j+1} = w / ||w||.
+// hcol[0..j+1] receives column j of Hbar; *w0 an estimate of ||Op(V_j)||.
+// Returns PP_OK, or PP_WARN_NONFINITE when a coefficient is not finite.
+template <typename T>
+int arnoldi_step(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &w, int j,
+                 hipStream_t s, Timers &tm, Counters &cnt, double *hcol, double *w0) {
+  const T *vj = w.V + (int64_t)j * w.ldv;
+  const double *sj = w.colscale + j;
+  tm.mark(0, s);
+  if (steps && !steps->empty()) {
+    PP_TRY(run_chain<T>(A, *steps, vj, sj, nullptr, w.Z, w.P0, w.P1, w.Tb, s, &cnt));
+    tm.mark(1, s);
+    PP_TRY_HIP(ppk::launch_spmv<T>(A, w.Z, nullptr, w.W, s));
+  } else {
+    tm.mark(1, s);
+    PP_TRY_HIP(ppk::launch_spmv<T>(A, vj, sj, w.W, s));
+  }
+  cnt.spmvs++;
+  tm.mark(2, s);
+  const int nc = j + 1;
+  const int L = w.L;
+  double *h1 = w.hbuf, *h2 = w.hbuf + L, *nrm = w.hbuf + 2 * L;
+  T *vnext = w.V + (int64_t)(j + 1) * w.ldv;
+  // pass 1: h1 = V^T w
+  PP_TRY(dots_any<T>(w, nc, w.W, s));
+  PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, w.G, 0, nc, w.colscale, h1, w.coef1, s));
+  if (nc <= ppk::kMaxCols) {
+    // w -= V h1, fused with pass 2's dots
+    PP_TRY_HIP(ppk::launch_update<T>(w.n, w.V, w.ldv, nc, w.coef1, nullptr, 1.0, w.W, w.W, true,
+                                     false, w.partial, s));
+  } else {
+    PP_TRY(update_any<T>(w, nc, w.coef1, w.W, w.W, false, s));
+    PP_TRY(dots_any<T>(w, nc, w.W, s));
+  }
+  PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, w.G, 0, nc, w.colscale, h2, w.coef2, s));
+  // pass 2 update, norm, store as column j+1
+  PP_TRY(update_any<T>(w, nc, w.coef2, w.W, vnext, true, s));
+  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, w.G, nrm, w.colscale + j + 1, s));
+  cnt.dots += 3;
+  tm.mark(3, s);
+  PP_TRY_HIP(hipMemcpyAsync(w.host, w.hbuf, (2 * (size_t)L + 1) * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  const double t0 = tm.on ? now_s() : 0.0;
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  tm.collect();
+  double a2 = 0.0;
+  bool ok = true;
+  for (int i = 0; i < nc; ++i) {
+    const double x1 = w.host[i], x2 = w.host[L + i];
+    hcol[i] = x1 + x2;
+    a2 += x1 * x1 + x2 * x2;
+    ok = ok && finite(x1) && finite(x2);
+  }
+  const double hn = w.host[2 * L];
+  hcol[j + 1] = hn;
+  *w0 = std::sqrt(a2 + hn * hn);
+  if (tm.on) tm.host += now_s() - t0;
+  return (ok && finite(hn)) ? PP_OK : PP_WARN_NONFINITE;
+}
+
+// Start column: V(:,0) = (T) src (device double), colscale[0] = 1/||.||; returns the norm.
+template <typename T>
+int start_from_vector(Work<T> &w, const double *src, hipStream_t s, double *beta) {
+  PP_TRY_HIP(ppk::launch_copy_from_f64<T>(w.n, src, w.V, s));
+  PP_TRY_HIP(ppk::launch_norm2<T>(w.n, w.V, nullptr, nullptr, w.partial, s));
+  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, w.G, w.misc, w.colscale, s));
+  PP_TRY_HIP(hipMemcpyAsync(w.host, w.misc, sizeof(double), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  *beta = w.host[0];
+  return PP_OK;
+}
+
+// d Arnoldi steps on v0, harmonic Ritz values, Leja order, step table.
+template <typename T>
+int build_poly_impl(const Csr<T> &A, const double *v0, int d, Work<T> &w, hipStream_t s,
+                    Counters &cnt, pp_poly *out) {
+  double beta = 0.0;
+  PP_TRY(start_from_vector<T>(w, v0, s, &beta));
+  cnt.dots += 1;
+  if (!(beta > 0.0) || !finite(beta)) return PP_ERR_SINGULAR;
+  const int ldh = d + 1;
+  std::vector<double> Hbar((size_t)ldh * d, 0.0), hcol(d + 1);
+  Timers tm;
+  int sdim = d;
+  for (int j = 0; j < d; ++j) {
+    double w0 = 0.0;
+    int rc = arnoldi_step<T>(A, nullptr, w, j, s, tm, cnt, hcol.data(), &w0);
+    if (rc < 0) return rc;
+    if (rc == PP_WARN_NONFINITE) return PP_ERR_SINGULAR;
+    for (int i = 0; i <= j + 1; ++i) Hbar[i + (size_t)j * ldh] = hcol[i];
+    if (hcol[j + 1] <= kBreakdownRtol * w0) {
+      sdim = j + 1;
+      break;
+    }
+  }
+  std::vector<double> wr, wi, lr, li;
+  PP_TRY(ppn::harmonic_ritz(Hbar.data(), ldh, sdim, wr, wi));
+  PP_TRY(ppn::leja_order(wr, wi, lr, li));
+  std::vector<ppn::Step> steps;
+  PP_TRY(ppn::step_table(lr, li, steps));
+  out->n = A.n;
+  out->re = lr;
+  out->im = li;
+  out->steps = steps;
+  return sdim < d ? PP_WARN_DEGREE_REDUCED : PP_OK;
+}
+
+// Givens least squares state of one cycle.
+struct Lsq {
+  int m;
+  std::vector<double> R, cs, sn, g;
+  explicit Lsq(int m_) : m(m_), R((size_t)(m_ + 1) * m_, 0.0), cs(m_), sn(m_), g(m_ + 1, 0.0) {}
+  // add column j (length j+2); returns |g_{j+1}|
+  double add(int j, double *h) {
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+      h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+      h[i] = t;
+    }
+    const double a = h[j], b = h[j + 1];
+    double c = 1.0, sv = 0.0, r = a;
+    if (b != 0.0) {
+      r = std::hypot(a, b);
+      c = a / r;
+      sv = b / r;
+    }
+    cs[j] = c;
+    sn[j] = sv;
+    h[j] = r;
+    h[j + 1] = 0.0;
+    for (int i = 0; i <= j; ++i) R[i + (size_t)j * (m + 1)] = h[i];
+    g[j + 1] = -sv * g[j];
+    g[j] = c * g[j];
+    return std::fabs(g[j + 1]);
+  }
+  void solve(int k, double *y) const {
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int c = i + 1; c < k; ++c) acc -= R[i + (size_t)c * (m + 1)] * y[c];
+      y[i] = acc / R[i + (size_t)i * (m + 1)];
+    }
+  }
+};
+
+// One GMRES(m) cycle from V(:,0) (colscale[0] set) with start residual norm beta.
+// Returns steps taken in *k and the solution coefficients in y.
+template <typename T>
+int gmres_cycle(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &w, int m,
+                double beta, double tol_abs, double bscale, int max_steps, hipStream_t s,
+                Timers &tm, Counters &cnt, std::vector<double> &y, int *k, double *res,
+                bool *nonfinite) {
+  Lsq ls(m);
+  ls.g[0] = beta;
+  std::vector<double> hcol(m + 2);
+  *k = 0;
+  *res = beta;
+  *nonfinite = false;
+  const int jmax = std::min(m, max_steps);
+  for (int j = 0; j < jmax; ++j) {
+    double w0 = 0.0;
+    int rc = arnoldi_step<T>(A, steps, w, j, s, tm, cnt, hcol.data(), &w0);
+    if (rc < 0) return rc;
+    cnt.iters++;
+    if (rc == PP_WARN_NONFINITE) {
+      *nonfinite = true;
+      break;
+    }
+    const double hn = hcol[j + 1];
+    *res = ls.add(j, hcol.data());
+    *k = j + 1;
+    cnt.push(*res / bscale);
+    if (!finite(*res)) {
+      *nonfinite = true;
+      break;
+    }
+    if (hn <= kBreakdownRtol * w0 || *res < tol_abs) break;
+  }
+  y.assign(std::max(*k, 1), 0.0);
+  if (*k > 0 && !*nonfinite) {
+    ls.solve(*k, y.data());
+    for (int i = 0; i < *k; ++i)
+      if (!finite(y[i])) *nonfinite = true;
+  }
+  return PP_OK;
+}
+
+// x_out = x_in + p(A) V(:,0..k) (colscale o y)   [x_in may equal x_out, or be nullptr]
+template <typename T>
+int cycle_update(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &w, int k,
+                 const std::vector<double> &y, const T *x_in, T *x_out, hipStream_t s,
+                 Counters &cnt) {
+  if (k <= 0) return PP_OK;
+  std::memcpy(w.host + 2 * w.L + 8, y.data(), k * sizeof(double));
+  PP_TRY_HIP(hipMemcpyAsync(w.ybuf, w.host + 2 * w.L + 8, k * sizeof(double),
+                            hipMemcpyHostToDevice, s));
+  const bool poly = steps && !steps->empty();
+  for (int c0 = 0; c0 < k; c0 += ppk::kMaxCols) {
+    const int cc = std::min(ppk::kMaxCols, k - c0);
+    T *dst = poly ? w.U : x_out;
+    const T *src = poly ? (c0 == 0 ? nullptr : w.U) : (c0 == 0 ? x_in : x_out);
+    PP_TRY_HIP(ppk::launch_update<T>(w.n, w.V + (int64_t)c0 * w.ldv, w.ldv, cc, w.ybuf + c0,
+                                     w.colscale + c0, -1.0, src, dst, false, false, w.partial,
+                                     s));
+  }
+  if (poly) PP_TRY(run_chain<T>(A, *steps, w.U, nullptr, x_in, x_out, w.P0, w.P1, w.Tb, s, &cnt));
+  // the host staging of y must not be reused before the copy has run
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  return PP_OK;
+}
+
+int check_csr(const pp_csr *A) {
+  if (!A || A->n <= 0 || A->nnz < 0 || A->n >= (int64_t)1 << 31 || A->nnz >= (int64_t)1 << 31)
+    return PP_ERR_ARG;
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col_ind || !A->vals))) return PP_ERR_ARG;
+  if (A->dtype != PP_F64 && A->dtype != PP_F32) return PP_ERR_ARG;
+  return PP_OK;
+}
+
+template <typename T>
+Csr<T> view(const pp_csr *A, const void *vals) {
+  return Csr<T>{(int)A->n, (int)A->nnz, A->row_ptr, A->col_ind, static_cast<const T *>(vals)};
+}
+
+template <typename T>
+int apply_impl(const pp_csr *A, const pp_poly *p, const void *v, void *y, hipStream_t s) {
+  Arena *ar = nullptr;
+  PP_TRY(current_arena(&ar));
+  const int n = (int)A->n;
+  Carver meas(nullptr);
+  T *bufs[3];
+  for (auto &b : bufs) b = meas.take<T>(pad_ld(n));
+  PP_TRY(ensure_arena(ar, meas.off + 256, 64));
+  Carver c(ar->dev);
+  for (auto &b : bufs) b = c.take<T>(pad_ld(n));
+  const Csr<T> M = view<T>(A, A->vals);
+  const T *vv = static_cast<const T *>(v);
+  T *yy = static_cast<T *>(y);
+  if (p->steps.empty()) {
+    PP_TRY_HIP(ppk::launch_fill<T>(n, T(0), yy, s));
+  } else {
+    PP_TRY(run_chain<T>(M, p->steps, vv, nullptr, nullptr, yy, bufs[0], bufs[1], bufs[2], s,
+                        nullptr));
+  }
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  return PP_OK;
+}
+
+template <typename T>
+int build_impl(const pp_csr *A, const double *v0, int d, hipStream_t s, pp_poly **out) {
+  Arena *ar = nullptr;
+  PP_TRY(current_arena(&ar));
+  const int n = (int)A->n;
+  Work<T> w;
+  Carver meas(nullptr);
+  w.carve(meas, n, d + 1);
+  PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
+  Carver c(ar->dev);
+  w.carve(c, n, d + 1);
+  w.host = ar->host;
+  Counters cnt;
+  pp_poly *p = new pp_poly();
+  p->dtype = A->dtype;
+  int rc = build_poly_impl<T>(view<T>(A, A->vals), v0, d, w, s, cnt, p);
+  if (rc < 0) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return rc;
+}
+
+// Everything a solve needs from the FP64 side.
+struct SolveIn {
+  const pp_csr *A;
+  const double *b;
+  double *x;
+  int m, d;
+  double tol;
+  pp_opts o;
+  hipStream_t s;
+};
+
+int worst(int a, int b) {
+  if (a < 0 || b < 0) return std::min(a, b);
+  return std::max(a, b);
+}
+
+// ||b|| in FP64 (device) -> host.
+int norm_f64(Work<double> &w, const double *x, hipStream_t s, double *out) {
+  PP_TRY_HIP(ppk::launch_norm2<double>(w.n, x, nullptr, nullptr, w.partial, s));
+  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, w.G, w.misc + 1, nullptr, s));
+  PP_TRY_HIP(hipMemcpyAsync(w.host, w.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  *out = w.host[0];
+  return PP_OK;
+}
+
+// r = b - A x into V(:,0), colscale[0] = 1/||r||; returns ||r||.
+int residual_f64(const Csr<double> &A, Work<double> &w, const double *b, const double *x,
+                 hipStream_t s, double *beta) {
+  int nt = 0;
+  PP_TRY_HIP(ppk::launch_residual<double>(A, b, x, w.V, w.partial, &nt, s));
+  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, nt, w.misc, w.colscale, s));
+  PP_TRY_HIP(hipMemcpyAsync(w.host, w.misc, sizeof(double), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  *beta = w.host[0];
+  return PP_OK;
+}
+
+int solve_f64(const SolveIn &in, pp_stats *st) {
+  const double t_start = now_s();
+  Arena *ar = nullptr;
+  PP_TRY(current_arena(&ar));
+  const int n = (int)in.A->n;
+  const int L = std::max(in.m, in.o.poly ? 0 : in.d) + 1;
+  Work<double> w;
+  Carver meas(nullptr);
+  w.carve(meas, n, L);
+  double *xsave = meas.take<double>(n);
+  PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
+  Carver c(ar->dev);
+  w.carve(c, n, L);
+  xsave = c.take<double>(n);
+  w.host = ar->host;
+  const Csr<double> A = view<double>(in.A, in.A->vals);
+  hipStream_t s = in.s;
+  Counters cnt;
+  cnt.history = in.o.history;
+  cnt.history_cap = in.o.history ? in.o.history_cap : 0;
+  Timers tm;
+  if (in.o.timing) {
+    PP_TRY(tm.init());
+    tm.on = true;
+  }
+  int status = PP_OK;
+  double bnorm = 0.0;
+  PP_TRY(norm_f64(w, in.b, s, &bnorm));
+  if (!finite(bnorm)) return PP_ERR_ARG;
+  auto finish = [&](double relres_true, double relres_impl, int cycles) {
+    if (st) {
+      st->iters = cnt.iters;
+      st->cycles = cycles;
+      st->spmvs = cnt.spmvs;
+      st->dots = cnt.dots;
+      st->relres_true = relres_true;
+      st->relres_implicit = relres_impl;
+      st->history_len = cnt.history_len;
+      st->t_chain = tm.chain;
+      st->t_spmv = tm.spmv;
+      st->t_orth = tm.orth;
+      st->t_host = tm.host;
+      st->t_total = now_s() - t_start;
+    }
+  };
+  if (bnorm == 0.0) {
+    PP_TRY_HIP(ppk::launch_fill<double>(n, 0.0, in.x, s));
+    PP_TRY_HIP(hipStreamSynchronize(s));
+    finish(0.0, 0.0, 0);
+    return PP_OK;
+  }
+  // the polynomial
+  pp_poly built;
+  const std::vector<ppn::Step> *steps = nullptr;
+  if (in.o.poly) {
+    steps = &in.o.poly->steps;
+  } else if (in.d > 0) {
+    const double t0 = now_s();
+    int rc = build_poly_impl<double>(A, in.o.v0 ? in.o.v0 : in.b, in.d, w, s, cnt, &built);
+    if (rc < 0) return rc;
+    status = worst(status, rc);
+    steps = &built.steps;
+    if (st) st->t_poly = now_s() - t0;
+  }
+  const int nroots = in.o.poly ? (int)in.o.poly->re.size() : (in.d > 0 ? (int)built.re.size() : 0);
+  if (st) st->nroots = nroots;
+  const int max_iters = in.o.max_iters > 0 ? in.o.max_iters : 100000;
+  double beta = 0.0;
+  PP_TRY(residual_f64(A, w, in.b, in.x, s, &beta));
+  cnt.spmvs++;
+  cnt.dots++;
+  double relres = beta / bnorm, relimp = relres;
+  int cycles = 0;
+  std::vector<double> y;
+  if (!finite(relres)) {
+    finish(relres, relres, 0);
+    return worst(status, PP_WARN_NONFINITE);
+  }
+  while (relres >= in.tol && cnt.iters < max_iters) {
+    ++cycles;
+    PP_TRY_HIP(hipMemcpyAsync(xsave, in.x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int k = 0;
+    double res = 0.0;
+    bool nonfinite = false;
+    PP_TRY(gmres_cycle<double>(A, steps, w, in.m, beta, in.tol * bnorm, bnorm,
+                               max_iters - cnt.iters, s, tm, cnt, y, &k, &res, &nonfinite));
+    if (nonfinite) {
+      status = worst(status, PP_WARN_NONFINITE);
+      break;
+    }
+    relimp = res / bnorm;
+    PP_TRY(cycle_update<double>(A, steps, w, k, y, in.x, in.x, s, cnt));
+    double nb = 0.0;
+    PP_TRY(residual_f64(A, w, in.b, in.x, s, &nb));
+    cnt.spmvs++;
+    cnt.dots++;
+    if (!finite(nb)) {
+      PP_TRY_HIP(hipMemcpyAsync(in.x, xsave, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PP_TRY_HIP(hipStreamSynchronize(s));
+      status = worst(status, PP_WARN_NONFINITE);
+      break;
+    }
+    beta = nb;
+    relres = beta / bnorm;
+  }
+  if (status != PP_WARN_NONFINITE && relres >= in.tol) status = worst(status, PP_WARN_NOT_CONVERGED);
+  finish(relres, relimp, cycles);
+  return status;
+}
+
+int solve_f32_ir(const SolveIn &in, pp_stats *st) {
+  const double t_start = now_s();
+  Arena *ar = nullptr;
+  PP_TRY(current_arena(&ar));
+  const int n = (int)in.A->n;
+  const int64_t nnz = in.A->nnz;
+  const int L = std::max(in.m, in.o.poly ? 0 : in.d) + 1;
+  Work<float> w;
+  Work<double> w64;  // only the residual / norm pieces are used
+  Carver meas(nullptr);
+  w.carve(meas, n, L);
+  w64.carve(meas, n, 1);
+  float *vals32 = in.o.vals_f32 ? nullptr : meas.take<float>(nnz > 0 ? nnz : 1);
+  double *xsave = meas.take<double>(n);
+  PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles() + 16));
+  Carver c(ar->dev);
+  w.carve(c, n, L);
+  w64.carve(c, n, 1);
+  vals32 = in.o.vals_f32 ? nullptr : c.take<float>(nnz > 0 ? nnz : 1);
+  xsave = c.take<double>(n);
+  w.host = ar->host;
+  w64.host = ar->host;
+  hipStream_t s = in.s;
+  const Csr<double> A64 = view<double>(in.A, in.A->vals);
+  if (!in.o.vals_f32) PP_TRY_HIP(ppk::launch_cast_f32(nnz, (const double *)in.A->vals, vals32, s));
+  const Csr<float> A32 = view<float>(in.A, in.o.vals_f32 ? (const void *)in.o.vals_f32 : vals32);
+  Counters cnt;
+  cnt.history = in.o.history;
+  cnt.history_cap = in.o.history ? in.o.history_cap : 0;
+  Timers tm;
+  if (in.o.timing) {
+    PP_TRY(tm.init());
+    tm.on = true;
+  }
+  int status = PP_OK;
+  double bnorm = 0.0;
+  PP_TRY(norm_f64(w64, in.b, s, &bnorm));
+  if (!finite(bnorm)) return PP_ERR_ARG;
+  int outer = 0;
+  auto finish = [&](double relres_true, double relres_impl) {
+    if (st) {
+      st->iters = cnt.iters;
+      st->cycles = outer;
+      st->outer = outer;
+      st->spmvs = cnt.spmvs;
+      st->dots = cnt.dots;
+      st->relres_true = relres_true;
+      st->relres_implicit = relres_impl;
+      st->history_len = cnt.history_len;
+      st->t_chain = tm.chain;
+      st->t_spmv = tm.spmv;
+      st->t_orth = tm.orth;
+      st->t_host = tm.host;
+      st->t_total = now_s() - t_start;
+    }
+  };
+  if (bnorm == 0.0) {
+    PP_TRY_HIP(ppk::launch_fill<double>(n, 0.0, in.x, s));
+    PP_TRY_HIP(hipStreamSynchronize(s));
+    finish(0.0, 0.0);
+    return PP_OK;
+  }
+  pp_poly built;
+  const std::vector<ppn::Step> *steps = nullptr;
+  if (in.o.poly) {
+    steps = &in.o.poly->steps;
+  } else if (in.d > 0) {
+    const double t0 = now_s();
+    int rc = build_poly_impl<float>(A32, in.o.v0 ? in.o.v0 : in.b, in.d, w, s, cnt, &built);
+    if (rc < 0) return rc;
+    status = worst(status, rc);
+    steps = &built.steps;
+    if (st) st->t_poly = now_s() - t0;
+  }
+  if (st)
+    st->nroots = in.o.poly ? (int)in.o.poly->re.size() : (in.d > 0 ? (int)built.re.size() : 0);
+  const int max_iters = in.o.max_iters > 0 ? in.o.max_iters : 100000;
+  const int max_outer = in.o.max_outer > 0 ? in.o.max_outer : 100;
+  const double inner_tol = in.o.inner_tol > 0 ? in.o.inner_tol : 1e-5;
+  double relres = 0.0, relimp = 0.0;
+  std::vector<double> y;
+  double *r64 = w64.V;  // FP64 residual
+  for (;;) {
+    double beta = 0.0;
+    PP_TRY(residual_f64(A64, w64, in.b, in.x, s, &beta));
+    cnt.spmvs++;
+    cnt.dots++;
+    relres = beta / bnorm;
+    if (!finite(relres)) {
+      if (outer > 0) {
+        PP_TRY_HIP(hipMemcpyAsync(in.x, xsave, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        PP_TRY_HIP(hipStreamSynchronize(s));
+      }
+      status = worst(status, PP_WARN_NONFINITE);
+      break;
+    }
+    if (relres < in.tol) break;
+    if (outer >= max_outer || cnt.iters >= max_iters) {
+      status = worst(status, PP_WARN_NOT_CONVERGED);
+      break;
+    }
+    // V32(:,0) = (float)(r / beta), with its FP32 norm
+    PP_TRY_HIP(ppk::launch_norm2<double>(n, r64, w64.colscale, w.V, w.partial, s));
+    PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, w.G, w.misc, w.colscale, s));
+    PP_TRY_HIP(hipMemcpyAsync(w.host, w.misc, sizeof(double), hipMemcpyDeviceToHost, s));
+    PP_TRY_HIP(hipMemcpyAsync(w64.misc + 2, &beta, sizeof(double), hipMemcpyHostToDevice, s));
+    PP_TRY_HIP(hipStreamSynchronize(s));
+    const double beta_in = w.host[0];
+    cnt.dots++;
+    PP_TRY_HIP(hipMemcpyAsync(xsave, in.x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int k = 0;
+    double res = 0.0;
+    bool nonfinite = false;
+    PP_TRY(gmres_cycle<float>(A32, steps, w, in.m, beta_in, inner_tol * beta_in, beta_in,
+                              max_iters - cnt.iters, s, tm, cnt, y, &k, &res, &nonfinite));
+    ++outer;
+    if (nonfinite) {
+      status = worst(status, PP_WARN_NONFINITE);
+      break;
+    }
+    relimp = relres * res / beta_in;
+    // d32 = p(A32) V32 (colscale o y), then x += beta * d32 in FP64
+    PP_TRY(cycle_update<float>(A32, steps, w, k, y, nullptr, w.Z, s, cnt));
+    PP_TRY_HIP(ppk::launch_axpy_f64<float>(n, w64.misc + 2, w.Z, in.x, s));
+  }
+  finish(relres, relimp);
+  return status;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_poly **out) {
+  if (!out || !v0) return PP_ERR_ARG;
+  *out = nullptr;
+  PP_TRY(check_csr(A));
+  if (d < 1 || d > kMaxD || d > A->n) return PP_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_lock);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return A->dtype == PP_F64 ? build_impl<double>(A, v0, d, s, out)
+                            : build_impl<float>(A, v0, d, s, out);
+}
+
+int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *stream) {
+  PP_TRY(check_csr(A));
+  if (!p || !v || !y || v == y || p->n != A->n) return PP_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_lock);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return A->dtype == PP_F64 ? apply_impl<double>(A, p, v, y, s)
+                            : apply_impl<float>(A, p, v, y, s);
+}
+
+int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, double tol,
+                   const pp_opts *opt, void *stream, pp_stats *st) {
+  if (st) std::memset(st, 0, sizeof(*st));
+  PP_TRY(check_csr(A));
+  if (!b || !x || m < 1 || m > kMaxM || !(tol > 0) || d < 0 || d > kMaxD || A->dtype != PP_F64)
+    return PP_ERR_ARG;
+  SolveIn in{A, b, x, m, d, tol, pp_opts{}, static_cast<hipStream_t>(stream)};
+  if (opt) in.o = *opt;
+  if (in.o.precision != PP_PREC_F64 && in.o.precision != PP_PREC_F32_IR) return PP_ERR_ARG;
+  if (in.o.poly) {
+    if (in.o.poly->n != A->n) return PP_ERR_ARG;
+  } else if (d > A->n) {
+    return PP_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_lock);
+  int rc = in.o.precision == PP_PREC_F64 ? solve_f64(in, st) : solve_f32_ir(in, st);
+  if (st) st->status = rc;
+  return rc;
+}
+
+int pp_poly_roots(const pp_poly *p, double *re, double *im, int cap, int *d_out) {
+  if (!p || !d_out) return PP_ERR_ARG;
+  const int d = (int)p->re.size();
+  *d_out = d;
+  if (d > 0 && (!re || !im || cap < d)) return PP_ERR_ARG;
+  for (int i = 0; i < d; ++i) {
+    re[i] = p->re[i];
+    im[i] = p->im[i];
+  }
+  return PP_OK;
+}
+
+int pp_poly_from_roots(int64_t n, const double *re, const double *im, int d, int dtype,
+                       pp_poly **out) {
+  if (!out || n <= 0 || d < 0 || d > kMaxD || (d > 0 && (!re || !im)) ||
+      (dtype != PP_F64 && dtype != PP_F32))
+    return PP_ERR_ARG;
+  *out = nullptr;
+  std::vector<double> r(re, re + d), i(im, im + d);
+  std::vector<ppn::Step> steps;
+  PP_TRY(ppn::step_table(r, i, steps));
+  pp_poly *p = new pp_poly();
+  p->n = n;
+  p->dtype = dtype;
+  p->re = r;
+  p->im = i;
+  p->steps = steps;
+  *out = p;
+  return PP_OK;
+}
+
+void pp_poly_free(pp_poly *p) { delete p; }
+
+int pp_roots_from_hessenberg(const double *Hbar, int ldh, int s, double *re, double *im) {
+  if (!Hbar || !re || !im || s < 1 || s > 4096 || ldh < s + 1) return PP_ERR_ARG;
+  std::vector<double> wr, wi, lr, li;
+  PP_TRY(ppn::harmonic_ritz(Hbar, ldh, s, wr, wi));
+  PP_TRY(ppn::leja_order(wr, wi, lr, li));
+  for (int k = 0; k < s; ++k) {
+    re[k] = lr[k];
+    im[k] = li[k];
+  }
+  return PP_OK;
+}
+
+int pp_csr_transpose(const pp_csr *A, int32_t *rp_t, int32_t *ci_t, void *vals_t, void *stream) {
+  PP_TRY(check_csr(A));
+  if (!rp_t || (A->nnz > 0 && (!ci_t || !vals_t))) return PP_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_lock);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = (int)A->n, nnz = (int)A->nnz;
+  Arena *ar = nullptr;
+  PP_TRY(current_arena(&ar));
+  Carver meas(nullptr);
+  meas.take<int32_t>(n);
+  meas.take<int32_t>(n);
+  meas.take<int32_t>(ppk::scan_tmp_size(n));
+  PP_TRY(ensure_arena(ar, meas.off + 256, 64));
+  Carver c(ar->dev);
+  int32_t *cnt = c.take<int32_t>(n);
+  int32_t *cursor = c.take<int32_t>(n);
+  int32_t *tmp = c.take<int32_t>(ppk::scan_tmp_size(n));
+  PP_TRY_HIP(ppk::launch_fill<int32_t>(n, 0, cnt, s));
+  PP_TRY_HIP(ppk::launch_fill<int32_t>(n, 0, cursor, s));
+  PP_TRY_HIP(ppk::launch_count_cols(nnz, A->col_ind, cnt, s));
+  PP_TRY_HIP(ppk::launch_exclusive_scan(n, cnt, rp_t, tmp, s));
+  if (nnz > 0) {
+    if (A->dtype == PP_F64) {
+      PP_TRY_HIP(ppk::launch_scatter_transpose<double>(n, A->row_ptr, A->col_ind,
+                                                       (const double *)A->vals, rp_t, cursor,
+                                                       ci_t, (double *)vals_t, s));
+      PP_TRY_HIP(ppk::launch_sort_rows<double>(n, rp_t, ci_t, (double *)vals_t, s));
+    } else {
+      PP_TRY_HIP(ppk::launch_scatter_transpose<float>(n, A->row_ptr, A->col_ind,
+                                                      (const float *)A->vals, rp_t, cursor, ci_t,
+                                                      (float *)vals_t, s));
+      PP_TRY_HIP(ppk::launch_sort_rows<float>(n, rp_t, ci_t, (float *)vals_t, s));
+    }
+  }
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  return PP_OK;
+}
+
+int pp_csr_grad(const pp_csr *A, const double *lam, const double *x, double *g_vals,
+                void *stream) {
+  if (!A || A->n <= 0 || A->nnz < 0 || !A->row_ptr || !lam || !x ||
+      (A->nnz > 0 && (!A->col_ind || !g_vals)))
+    return PP_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_lock);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PP_TRY_HIP(ppk::launch_csr_grad((int)A->n, A->row_ptr, A->col_ind, lam, x, g_vals, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  return PP_OK;
+}
+
+void pp_release_workspace(void) {
+  std::lock_guard<std::mutex> lk(g_lock);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (size_t dev = 0; dev < g_arena.size(); ++dev) {
+    Arena &a = g_arena[dev];
+    if (!a.dev && !a.host) continue;
+    (void)hipSetDevice((int)dev);
+    (void)hipDeviceSynchronize();
+    if (a.dev) (void)hipFree(a.dev);
+    if (a.host) (void)hipHostFree(a.host);
+    a = Arena{};
+  }
+  (void)hipSetDevice(cur);
+}
+
+const char *pp_status_string(int code) {
+  switch (code) {
+    case PP_OK: return "ok";
+    case PP_ERR_ARG: return "invalid argument";
+    case PP_ERR_HIP: return "HIP runtime error";
+    case PP_ERR_NOMEM: return "out of memory";
+    case PP_ERR_EIG: return "Hessenberg QR did not converge";
+    case PP_ERR_SINGULAR: return "singular Hessenberg, zero start vector, or zero/non-finite root";
+    case PP_WARN_DEGREE_REDUCED: return "warning: Arnoldi breakdown, polynomial has fewer roots";
+    case PP_WARN_NOT_CONVERGED: return "warning: iteration cap reached before tolerance";
+    case PP_WARN_NONFINITE: return "warning: non-finite value met, last finite iterate returned";
+    default: return "unknown status";
+  }
+}
+
+const char *pp_version(void) { return "libpp 0.1.0 gfx950"; }
+
+}  // extern "C"
