@@ -117,10 +117,24 @@ typedef struct pp_stats {
   double relres_implicit;  /* last implicit (least-squares) estimate */
   double t_total;          /* seconds, wall clock of the call */
   double t_poly;           /* seconds building the polynomial (wall clock) */
-  double t_chain;          /* seconds in the p(A) chain kernels      (timing != 0) */
-  double t_spmv;           /* seconds in plain products / residuals  (timing != 0) */
-  double t_orth;           /* seconds in CGS2 kernels and reductions (timing != 0) */
-  double t_host;           /* seconds in host least squares and syncs (timing != 0) */
+  /* Phase times of the Arnoldi steps (the build's and the solve's), measured
+   * with HIP events on the stream when timing != 0: */
+  double t_chain;          /* seconds in the p(A) chain kernels */
+  double t_spmv;           /* seconds in the operator product A z */
+  double t_orth;           /* seconds in CGS2 kernels and reductions */
+  double t_host;           /* step wall time not covered by the three above: launch
+                              latency, the per-step copy and synchronisation, host
+                              least squares */
+  /* Algorithmic HBM bytes of the launches inside the timed phases above (the
+   * Arnoldi steps' chains, operator products and CGS2 sweeps), from the
+   * per-launch traffic model: a chain launch reads vals, col_ind, row_ptr and the
+   * gathered vector once and the accumulator / partner vectors once, and
+   * writes its outputs once (12 nnz + 36 n bytes for a middle real-root step in
+   * FP64).  Divided by t_chain / t_spmv / t_orth they give achieved bandwidth. */
+  double bytes_chain;
+  double bytes_spmv;
+  double bytes_orth;
+  int64_t launches_chain;  /* chain launches inside t_chain */
 } pp_stats;
 
 /* Build the polynomial for (A, v0) with d roots.

@@ -49,7 +49,9 @@ class pp_stats(ctypes.Structure):
                 ("relres_implicit", ctypes.c_double), ("t_total", ctypes.c_double),
                 ("t_poly", ctypes.c_double), ("t_chain", ctypes.c_double),
                 ("t_spmv", ctypes.c_double), ("t_orth", ctypes.c_double),
-                ("t_host", ctypes.c_double)]
+                ("t_host", ctypes.c_double), ("bytes_chain", ctypes.c_double),
+                ("bytes_spmv", ctypes.c_double), ("bytes_orth", ctypes.c_double),
+                ("launches_chain", ctypes.c_int64)]
 
 
 _lib = None
@@ -267,6 +269,10 @@ class Stats:
     t_spmv: float
     t_orth: float
     t_host: float
+    bytes_chain: float = 0.0
+    bytes_spmv: float = 0.0
+    bytes_orth: float = 0.0
+    launches_chain: int = 0
     history: Optional[np.ndarray] = None
 
 
@@ -305,7 +311,8 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
     _check(rc, "pp_gmres_solve")
     s = Stats(st.status, st.iters, st.cycles, st.outer, st.nroots, st.spmvs, st.dots,
               st.relres_true, st.relres_implicit, st.t_total, st.t_poly, st.t_chain, st.t_spmv,
-              st.t_orth, st.t_host, hist[: st.history_len].copy() if hist is not None else None)
+              st.t_orth, st.t_host, st.bytes_chain, st.bytes_spmv, st.bytes_orth,
+              st.launches_chain, hist[: st.history_len].copy() if hist is not None else None)
     return x, s
 
 

@@ -168,7 +168,10 @@ struct Timers {
   void mark(int k, hipStream_t s) {
     if (on) (void)hipEventRecord(ev[k], s);
   }
-  void collect() {
+  // Accumulate the event-timed phases of one Arnoldi step; the rest of the
+  // step's wall time (launch latency, the copy and synchronisation, host least
+  // squares) is counted as host time.
+  void collect(double wall) {
     if (!on) return;
     float a = 0, b = 0, c = 0;
     (void)hipEventElapsedTime(&a, ev[0], ev[1]);
@@ -177,12 +180,15 @@ struct Timers {
     chain += a * 1e-3;
     spmv += b * 1e-3;
     orth += c * 1e-3;
+    host += std::max(0.0, wall - (a + b + c) * 1e-3);
   }
 };
 
 struct Counters {
   int64_t spmvs = 0, dots = 0;
   int iters = 0;
+  double bytes_chain = 0, bytes_spmv = 0, bytes_orth = 0;
+  int64_t launches_chain = 0;
   double *history = nullptr;
   int history_cap = 0, history_len = 0;
   void push(double v) {
@@ -198,12 +204,27 @@ double now_s() {
 inline bool finite(double v) { return std::isfinite(v); }
 
 // ------------------------------------------------------------------ chain
+// Algorithmic HBM bytes of one sparse-product launch: the matrix (values,
+// column indices, row pointers) and the gathered vector once, plus `vec_rw`
+// further vector reads/writes of n entries.
+template <typename T>
+double product_bytes(const Csr<T> &A, int vec_rw) {
+  return (double)A.nnz * (sizeof(T) + sizeof(int32_t)) + 4.0 * (A.n + 1) +
+         (double)sizeof(T) * A.n * (1 + vec_rw);
+}
+
 // y_out = y_in + p(A) (gscale * g) for the step table; y_in may be nullptr
-// (zero) or equal y_out.  Uses P0, P1, Tb as chain temporaries.
+// (zero) or equal y_out.  Uses P0, P1, Tb as chain temporaries.  Adds the
+// launches and their algorithmic bytes to *bytes / *launches when given.
 template <typename T>
 int run_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
               const double *gscale, const T *y_in, T *y_out, T *P0, T *P1, T *Tb,
-              hipStream_t s, Counters *cnt) {
+              hipStream_t s, Counters *cnt, double *bytes = nullptr,
+              int64_t *launches = nullptr) {
+  auto account = [&](int vec_rw) {
+    if (bytes) *bytes += product_bytes(A, vec_rw);
+    if (launches) ++*launches;
+  };
   const int K = (int)steps.size();
   const T *cur = g;
   const double *cs = gscale;
@@ -224,6 +245,7 @@ int run_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
                           st.c1, 0.0, cf};
       PP_TRY_HIP(ppk::launch_chain<T>(A, 0, fold, false, a, s));
       if (cnt) cnt->spmvs++;
+      account((yi ? 1 : 0) + 1 + (fold ? 0 : 1));
       yi = y_out;
       if (fold) break;
       cur = bufs[pb];
@@ -234,12 +256,14 @@ int run_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
                           st.c1, st.c2, 0.0};
       PP_TRY_HIP(ppk::launch_chain<T>(A, 1, false, last, a, s));
       if (cnt) cnt->spmvs++;
+      account((yi ? 1 : 0) + 1 + (last ? 0 : 1));
       yi = y_out;
       if (last) break;
       ppk::ChainArgs<T> b{Tb, nullptr, cur, cs, fold ? nullptr : bufs[pb], yi, y_out,
                           st.c1, st.c2, cf};
       PP_TRY_HIP(ppk::launch_chain<T>(A, 2, fold, false, b, s));
       if (cnt) cnt->spmvs++;
+      account(1 + (fold ? 2 : 1));
       if (fold) break;
       cur = bufs[pb];
       cs = nullptr;
@@ -280,9 +304,11 @@ int arnoldi_step(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &
                  hipStream_t s, Timers &tm, Counters &cnt, double *hcol, double *w0) {
   const T *vj = w.V + (int64_t)j * w.ldv;
   const double *sj = w.colscale + j;
+  const double t_wall0 = tm.on ? now_s() : 0.0;
   tm.mark(0, s);
   if (steps && !steps->empty()) {
-    PP_TRY(run_chain<T>(A, *steps, vj, sj, nullptr, w.Z, w.P0, w.P1, w.Tb, s, &cnt));
+    PP_TRY(run_chain<T>(A, *steps, vj, sj, nullptr, w.Z, w.P0, w.P1, w.Tb, s, &cnt,
+                        &cnt.bytes_chain, &cnt.launches_chain));
     tm.mark(1, s);
     PP_TRY_HIP(ppk::launch_spmv<T>(A, w.Z, nullptr, w.W, s));
   } else {
@@ -290,6 +316,7 @@ int arnoldi_step(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &
     PP_TRY_HIP(ppk::launch_spmv<T>(A, vj, sj, w.W, s));
   }
   cnt.spmvs++;
+  cnt.bytes_spmv += product_bytes(A, 1);
   tm.mark(2, s);
   const int nc = j + 1;
   const int L = w.L;
@@ -311,12 +338,12 @@ int arnoldi_step(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &
   PP_TRY(update_any<T>(w, nc, w.coef2, w.W, vnext, true, s));
   PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, w.G, nrm, w.colscale + j + 1, s));
   cnt.dots += 3;
+  // three sweeps over nc basis columns; w read three times and written twice
+  cnt.bytes_orth += (double)sizeof(T) * w.n * (3.0 * nc + 5.0);
   tm.mark(3, s);
   PP_TRY_HIP(hipMemcpyAsync(w.host, w.hbuf, (2 * (size_t)L + 1) * sizeof(double),
                             hipMemcpyDeviceToHost, s));
-  const double t0 = tm.on ? now_s() : 0.0;
   PP_TRY_HIP(hipStreamSynchronize(s));
-  tm.collect();
   double a2 = 0.0;
   bool ok = true;
   for (int i = 0; i < nc; ++i) {
@@ -328,7 +355,7 @@ int arnoldi_step(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &
   const double hn = w.host[2 * L];
   hcol[j + 1] = hn;
   *w0 = std::sqrt(a2 + hn * hn);
-  if (tm.on) tm.host += now_s() - t0;
+  if (tm.on) tm.collect(now_s() - t_wall0);
   return (ok && finite(hn)) ? PP_OK : PP_WARN_NONFINITE;
 }
 
@@ -347,14 +374,13 @@ int start_from_vector(Work<T> &w, const double *src, hipStream_t s, double *beta
 // d Arnoldi steps on v0, harmonic Ritz values, Leja order, step table.
 template <typename T>
 int build_poly_impl(const Csr<T> &A, const double *v0, int d, Work<T> &w, hipStream_t s,
-                    Counters &cnt, pp_poly *out) {
+                    Counters &cnt, Timers &tm, pp_poly *out) {
   double beta = 0.0;
   PP_TRY(start_from_vector<T>(w, v0, s, &beta));
   cnt.dots += 1;
   if (!(beta > 0.0) || !finite(beta)) return PP_ERR_SINGULAR;
   const int ldh = d + 1;
   std::vector<double> Hbar((size_t)ldh * d, 0.0), hcol(d + 1);
-  Timers tm;
   int sdim = d;
   for (int j = 0; j < d; ++j) {
     double w0 = 0.0;
@@ -532,9 +558,10 @@ int build_impl(const pp_csr *A, const double *v0, int d, hipStream_t s, pp_poly 
   w.carve(c, n, d + 1);
   w.host = ar->host;
   Counters cnt;
+  Timers tm;
   pp_poly *p = new pp_poly();
   p->dtype = A->dtype;
-  int rc = build_poly_impl<T>(view<T>(A, A->vals), v0, d, w, s, cnt, p);
+  int rc = build_poly_impl<T>(view<T>(A, A->vals), v0, d, w, s, cnt, tm, p);
   if (rc < 0) {
     delete p;
     return rc;
@@ -623,6 +650,10 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
       st->t_spmv = tm.spmv;
       st->t_orth = tm.orth;
       st->t_host = tm.host;
+      st->bytes_chain = cnt.bytes_chain;
+      st->bytes_spmv = cnt.bytes_spmv;
+      st->bytes_orth = cnt.bytes_orth;
+      st->launches_chain = cnt.launches_chain;
       st->t_total = now_s() - t_start;
     }
   };
@@ -639,7 +670,7 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
     steps = &in.o.poly->steps;
   } else if (in.d > 0) {
     const double t0 = now_s();
-    int rc = build_poly_impl<double>(A, in.o.v0 ? in.o.v0 : in.b, in.d, w, s, cnt, &built);
+    int rc = build_poly_impl<double>(A, in.o.v0 ? in.o.v0 : in.b, in.d, w, s, cnt, tm, &built);
     if (rc < 0) return rc;
     status = worst(status, rc);
     steps = &built.steps;
@@ -744,6 +775,10 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
       st->t_spmv = tm.spmv;
       st->t_orth = tm.orth;
       st->t_host = tm.host;
+      st->bytes_chain = cnt.bytes_chain;
+      st->bytes_spmv = cnt.bytes_spmv;
+      st->bytes_orth = cnt.bytes_orth;
+      st->launches_chain = cnt.launches_chain;
       st->t_total = now_s() - t_start;
     }
   };
@@ -759,7 +794,7 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
     steps = &in.o.poly->steps;
   } else if (in.d > 0) {
     const double t0 = now_s();
-    int rc = build_poly_impl<float>(A32, in.o.v0 ? in.o.v0 : in.b, in.d, w, s, cnt, &built);
+    int rc = build_poly_impl<float>(A32, in.o.v0 ? in.o.v0 : in.b, in.d, w, s, cnt, tm, &built);
     if (rc < 0) return rc;
     status = worst(status, rc);
     steps = &built.steps;
@@ -813,8 +848,10 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
     }
     relimp = relres * res / beta_in;
     // d32 = p(A32) V32 (colscale o y), then x += beta * d32 in FP64
-    PP_TRY(cycle_update<float>(A32, steps, w, k, y, nullptr, w.Z, s, cnt));
-    PP_TRY_HIP(ppk::launch_axpy_f64<float>(n, w64.misc + 2, w.Z, in.x, s));
+    if (k > 0) {
+      PP_TRY(cycle_update<float>(A32, steps, w, k, y, nullptr, w.Z, s, cnt));
+      PP_TRY_HIP(ppk::launch_axpy_f64<float>(n, w64.misc + 2, w.Z, in.x, s));
+    }
   }
   finish(relres, relimp);
   return status;
