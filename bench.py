@@ -126,7 +126,7 @@ def main():
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(chain_gbps / HBM_PEAK_GBPS, 4) if chain_gbps else None,
-        "traffic": None,
+        "traffic": pmc_traffic(args.grid),
         "bytes_per_launch": bc / nl if nl else None,
         "avg_launch_us": tc / nl * 1e6 if nl else None,
         "launches": nl,
@@ -213,6 +213,25 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def pmc_traffic(grid):
+    """HBM bytes per middle chain launch from the committed rocprofv3 counter runs.
+
+    Only reported while kernels.hip is the source those counters were taken
+    from (its sha256 prefix is recorded with them); otherwise None.
+    """
+    import hashlib
+    if grid != 256:
+        return None
+    path = os.path.join(ROOT, "profiles", "k_chain_cd3d_256_pe100_traffic.json")
+    src = os.path.join(ROOT, "paper_1907_00072_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return rec["traffic_bytes_per_dispatch"] if rec.get("kernels_hip_sha256_16") == sha else None
 
 
 def copy_ceiling(torch, nbytes=2 << 30, reps=5):
