@@ -13,14 +13,17 @@
 //   partially-used cache line per row per lane.  The root update of the
 //   polynomial chain is fused into the epilogue of the same tile, so one launch
 //   reads A once and the chain vectors once.
-// * Tiles are remapped so that each of the 8 XCDs walks a contiguous range of
-//   rows (hardware dispatches workgroups round-robin over the XCDs): the
-//   vector entries a tile gathers from neighbouring rows / planes then tend to
-//   sit in that XCD's L2.
+//   Each thread issues all of its column-index and value loads for a chunk
+//   before any gather, so a tile costs two memory latencies, not one per
+//   nonzero; own-row operands are fetched before the reduction; streamed
+//   vectors use non-temporal loads and stores so the L2 keeps the gathered
+//   vector.
 // * The Gram-Schmidt kernels keep one basis row per thread in registers (a
-//   template bound on the column count), so each sweep reads every basis
-//   column once and updates the vector and accumulates the next pass's dot
-//   products in the same sweep.
+//   template bound on the column count, in steps of 8), so each sweep reads
+//   every basis column once and updates the vector and accumulates the next
+//   pass's dot products in the same sweep.  Column loads are branch-free (the
+//   index is clamped to the last live column and the extra products carry a
+//   zero coefficient), so all of a row's loads are in flight together.
 // * All reductions are two-stage in a fixed order (per-workgroup partials in
 //   memory, then a second kernel), with no floating-point atomics, so results
 //   are bitwise reproducible.
@@ -32,7 +35,6 @@ namespace ppk {
 
 namespace {
 
-constexpr int kXcd = 8;
 constexpr int kOrthRowsTarget = 2048;  // aim for about this many CGS2 workgroups
 
 template <typename T>
@@ -45,15 +47,6 @@ template <>
 struct LdsCap<float> {
   static constexpr int value = 4096;
 };
-
-// Logical tile of workgroup b when the hardware deals workgroups to the XCDs
-// round-robin: XCD x receives workgroups x, x+8, ... and is given the
-// contiguous tile range [start_x, start_x + count_x).  A bijection on [0, G).
-__device__ __forceinline__ int xcd_tile(int b, int G) {
-  const int per = G / kXcd, rem = G % kXcd;
-  const int x = b % kXcd, i = b / kXcd;
-  return x * per + min(x, rem) + i;
-}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -72,34 +65,47 @@ __device__ __forceinline__ double block_sum(double v, double *red4) {
   return r;
 }
 
-// Row sums of A * g for the tile's rows (thread t -> row r0 + t).  All threads of
-// the workgroup must call it.  Rows past n return 0.
+template <typename T>
+__device__ __forceinline__ T ldnt(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void stnt(T v, T *p) {
+  __builtin_nontemporal_store(v, p);
+}
+
+// Row sums of A * g for the tile [r0, r0 + nrows) (thread t -> row r0 + t).
+// All threads of the workgroup must call it; rows past the tile return 0.
+// rb/re are the calling thread's row bounds (0, 0 for threads past the tile).
 template <typename T>
 __device__ __forceinline__ T tile_row_sum(const Csr<T> &A, const T *__restrict__ g, int r0,
-                                          int nrows, int *s_rp, T *s_buf) {
+                                          int nrows, int rb, int re, T *s_buf) {
   constexpr int CAP = LdsCap<T>::value;
+  constexpr int PER = CAP / kBlock;
   const int t = threadIdx.x;
-  if (t < nrows) s_rp[t] = A.rp[r0 + t];
-  if (t == 0) s_rp[nrows] = A.rp[r0 + nrows];
-  __syncthreads();
-  const int kb = s_rp[0], ke = s_rp[nrows];
-  int rb = 0, re = 0;
-  if (t < nrows) {
-    rb = s_rp[t];
-    re = s_rp[t + 1];
-  }
+  const int kb = A.rp[r0], ke = A.rp[r0 + nrows];
   T acc = T(0);
   for (int c0 = kb; c0 < ke; c0 += CAP) {
     const int c1 = min(c0 + CAP, ke);
-    for (int k = c0 + t; k < c1; k += kBlock) {
-      const T v = __builtin_nontemporal_load(A.va + k);
-      const int c = __builtin_nontemporal_load(A.ci + k);
-      s_buf[k - c0] = v * g[c];
+    int cols[PER];
+    T vals[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = c0 + q * kBlock + t;
+      if (k < c1) {
+        vals[q] = ldnt(A.va + k);
+        cols[q] = ldnt(A.ci + k);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = c0 + q * kBlock + t;
+      if (k < c1) s_buf[k - c0] = vals[q] * g[cols[q]];
     }
     __syncthreads();
     const int lo = max(rb, c0), hi = min(re, c1);
     for (int k = lo; k < hi; ++k) acc += s_buf[k - c0];
-    __syncthreads();
+    if (c0 + CAP < ke) __syncthreads();
   }
   return acc;
 }
@@ -107,40 +113,49 @@ __device__ __forceinline__ T tile_row_sum(const Csr<T> &A, const T *__restrict__
 // ------------------------------------------------------------------ chain
 template <typename T, int KIND, bool FOLD, bool NOOUT>
 __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
-  __shared__ int s_rp[kBlock + 1];
   __shared__ T s_buf[LdsCap<T>::value];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int r0 = tile * kBlock;
+  const int r0 = blockIdx.x * kBlock;
   const int nrows = min(kBlock, A.n - r0);
-  const T gs = a.gscale ? (T)(*a.gscale) : T(1);
-  const T acc = tile_row_sum(A, a.g, r0, nrows, s_rp, s_buf);
   const int t = threadIdx.x;
-  if (t >= nrows) return;
   const int i = r0 + t;
+  const bool live = t < nrows;
+  // own-row operands first, so their latency overlaps the product
+  int rb = 0, re = 0;
+  T own = T(0), yv = T(0), sf = T(0);
+  if (live) {
+    rb = A.rp[i];
+    re = A.rp[i + 1];
+    own = a.g[i];
+    if (KIND != 2 || FOLD) yv = a.y_in ? ldnt(a.y_in + i) : T(0);
+    if (KIND == 2) sf = ldnt(a.self + i);
+  }
+  const T gs = a.gscale ? (T)(*a.gscale) : T(1);
+  const T acc = tile_row_sum(A, a.g, r0, nrows, rb, re, s_buf);
+  if (!live) return;
   const T c1 = (T)a.c1, c2 = (T)a.c2, cf = (T)a.cf;
   if constexpr (KIND == 0) {
-    const T p = gs * a.g[i];
+    const T p = gs * own;
     const T ap = gs * acc;
-    T y = (a.y_in ? a.y_in[i] : T(0)) + c1 * p;
+    T y = yv + c1 * p;
     const T pn = p - c1 * ap;
     if constexpr (FOLD) {
       y += cf * pn;
     } else {
-      a.out[i] = pn;
+      stnt(pn, a.out + i);
     }
-    a.y_out[i] = y;
+    stnt(y, a.y_out + i);
   } else if constexpr (KIND == 1) {
-    const T p = gs * a.g[i];
+    const T p = gs * own;
     const T tt = gs * acc;
-    a.y_out[i] = (a.y_in ? a.y_in[i] : T(0)) + c1 * p - c2 * tt;
-    if constexpr (!NOOUT) a.out[i] = tt;
+    stnt(yv + c1 * p - c2 * tt, a.y_out + i);
+    if constexpr (!NOOUT) stnt(tt, a.out + i);
   } else {
     const T ss = a.sscale ? (T)(*a.sscale) : T(1);
-    const T pn = ss * a.self[i] - c1 * (gs * a.g[i]) + c2 * (gs * acc);
+    const T pn = ss * sf - c1 * (gs * own) + c2 * (gs * acc);
     if constexpr (FOLD) {
-      a.y_out[i] = a.y_in[i] + cf * pn;
+      stnt(yv + cf * pn, a.y_out + i);
     } else {
-      a.out[i] = pn;
+      stnt(pn, a.out + i);
     }
   }
 }
@@ -148,34 +163,44 @@ __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_spmv(Csr<T> A, const T *__restrict__ g,
                                                  const double *gscale, T *__restrict__ out) {
-  __shared__ int s_rp[kBlock + 1];
   __shared__ T s_buf[LdsCap<T>::value];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int r0 = tile * kBlock;
+  const int r0 = blockIdx.x * kBlock;
   const int nrows = min(kBlock, A.n - r0);
-  const T acc = tile_row_sum(A, g, r0, nrows, s_rp, s_buf);
-  if (threadIdx.x < nrows) out[r0 + threadIdx.x] = (gscale ? (T)(*gscale) : T(1)) * acc;
+  const int i = r0 + threadIdx.x;
+  int rb = 0, re = 0;
+  if ((int)threadIdx.x < nrows) {
+    rb = A.rp[i];
+    re = A.rp[i + 1];
+  }
+  const T acc = tile_row_sum(A, g, r0, nrows, rb, re, s_buf);
+  if ((int)threadIdx.x < nrows) stnt((gscale ? (T)(*gscale) : T(1)) * acc, out + i);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_residual(Csr<T> A, const T *__restrict__ b,
                                                      const T *__restrict__ x, T *__restrict__ out,
                                                      double *__restrict__ partial) {
-  __shared__ int s_rp[kBlock + 1];
   __shared__ T s_buf[LdsCap<T>::value];
   __shared__ double red[4];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int r0 = tile * kBlock;
+  const int r0 = blockIdx.x * kBlock;
   const int nrows = min(kBlock, A.n - r0);
-  const T acc = tile_row_sum(A, x, r0, nrows, s_rp, s_buf);
+  const int i = r0 + threadIdx.x;
+  int rb = 0, re = 0;
+  T bi = T(0);
+  if ((int)threadIdx.x < nrows) {
+    rb = A.rp[i];
+    re = A.rp[i + 1];
+    bi = ldnt(b + i);
+  }
+  const T acc = tile_row_sum(A, x, r0, nrows, rb, re, s_buf);
   double sq = 0.0;
-  if (threadIdx.x < nrows) {
-    const T r = b[r0 + threadIdx.x] - acc;
-    out[r0 + threadIdx.x] = r;
+  if ((int)threadIdx.x < nrows) {
+    const T r = bi - acc;
+    stnt(r, out + i);
     sq = (double)r * (double)r;
   }
   sq = block_sum(sq, red);
-  if (threadIdx.x == 0) partial[tile] = sq;
+  if (threadIdx.x == 0) partial[blockIdx.x] = sq;
 }
 
 template <typename T>
@@ -202,10 +227,15 @@ __global__ __launch_bounds__(kBlock) void k_dots(int n, int rpt, const T *__rest
   for (int r = 0; r < rpt; ++r) {
     const int64_t i = base + (int64_t)r * kBlock;
     if (i < n) {
-      const T wi = w[i];
+      T v[NCB];
 #pragma unroll
-      for (int c = 0; c < NCB; ++c)
-        if (c < nc) acc[c] += __builtin_nontemporal_load(Vc + (int64_t)c * ldv + i) * wi;
+      for (int c = 0; c < NCB; ++c) v[c] = ldnt(Vc + (int64_t)min(c, nc - 1) * ldv + i);
+      const T wi = ldnt(w + i);
+      // keep every load of the row ahead of the arithmetic (the scheduler would
+      // otherwise interleave load/wait/fma to save registers)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) acc[c] += v[c] * wi;
     }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -233,11 +263,14 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, int rpt, const T *__re
   __shared__ T s_coef[NCB];
   __shared__ double red[4][DOTS ? NCB : 1];
   __shared__ double red4[4];
-  if ((int)threadIdx.x < nc) {
+  if ((int)threadIdx.x < NCB) {
     const int c = threadIdx.x;
-    s_coef[c] = (T)(sign * coef_a[c] * (coef_b ? coef_b[c] : 1.0));
+    s_coef[c] = c < nc ? (T)(sign * coef_a[c] * (coef_b ? coef_b[c] : 1.0)) : T(0);
   }
   __syncthreads();
+  T coef[NCB];
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) coef[c] = s_coef[c];
   T acc[DOTS ? NCB : 1];
 #pragma unroll
   for (int c = 0; c < (DOTS ? NCB : 1); ++c) acc[c] = T(0);
@@ -248,17 +281,15 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, int rpt, const T *__re
     if (i < n) {
       T v[NCB];
 #pragma unroll
-      for (int c = 0; c < NCB; ++c)
-        if (c < nc) v[c] = __builtin_nontemporal_load(V + (int64_t)c * ldv + i);
-      T wi = w_in ? w_in[i] : T(0);
+      for (int c = 0; c < NCB; ++c) v[c] = ldnt(V + (int64_t)min(c, nc - 1) * ldv + i);
+      T wi = w_in ? ldnt(w_in + i) : T(0);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int c = 0; c < NCB; ++c)
-        if (c < nc) wi -= v[c] * s_coef[c];
-      out[i] = wi;
+      for (int c = 0; c < NCB; ++c) wi -= v[c] * coef[c];
+      stnt(wi, out + i);
       if constexpr (DOTS) {
 #pragma unroll
-        for (int c = 0; c < NCB; ++c)
-          if (c < nc) acc[c] += v[c] * wi;
+        for (int c = 0; c < NCB; ++c) acc[c] += v[c] * wi;
       }
       if constexpr (NORM) nacc += (double)wi * (double)wi;
     }
@@ -550,23 +581,38 @@ int orth_grid(int n) {
   return (int)((n + per - 1) / per);
 }
 
+// Column-count buckets of the CGS2 kernels.
+#define PP_NCB_SWITCH(nc, CALL) \
+  do {                          \
+    if ((nc) <= 8) {            \
+      CALL(8);                  \
+    } else if ((nc) <= 16) {    \
+      CALL(16);                 \
+    } else if ((nc) <= 24) {    \
+      CALL(24);                 \
+    } else if ((nc) <= 32) {    \
+      CALL(32);                 \
+    } else if ((nc) <= 40) {    \
+      CALL(40);                 \
+    } else if ((nc) <= 48) {    \
+      CALL(48);                 \
+    } else if ((nc) <= 56) {    \
+      CALL(56);                 \
+    } else {                    \
+      CALL(64);                 \
+    }                           \
+  } while (0)
+
 template <typename T>
 hipError_t launch_dots(int n, const T *V, int64_t ldv, int c0, int nc, const T *w,
                        double *partial, hipStream_t stream) {
   if (nc < 1 || nc > kMaxCols) return hipErrorInvalidValue;
   const int rpt = orth_rpt(n), G = orth_grid(n);
-  const dim3 grid(G), block(kBlock);
-  if (nc <= 8)
-    hipLaunchKernelGGL((k_dots<T, 8>), grid, block, 0, stream, n, rpt, V, ldv, c0, nc, w, partial);
-  else if (nc <= 16)
-    hipLaunchKernelGGL((k_dots<T, 16>), grid, block, 0, stream, n, rpt, V, ldv, c0, nc, w,
-                       partial);
-  else if (nc <= 32)
-    hipLaunchKernelGGL((k_dots<T, 32>), grid, block, 0, stream, n, rpt, V, ldv, c0, nc, w,
-                       partial);
-  else
-    hipLaunchKernelGGL((k_dots<T, 64>), grid, block, 0, stream, n, rpt, V, ldv, c0, nc, w,
-                       partial);
+#define PP_DOTS_CALL(NCB)                                                                       \
+  hipLaunchKernelGGL((k_dots<T, NCB>), dim3(G), dim3(kBlock), 0, stream, n, rpt, V, ldv, c0, nc, \
+                     w, partial)
+  PP_NCB_SWITCH(nc, PP_DOTS_CALL);
+#undef PP_DOTS_CALL
   return hipGetLastError();
 }
 
@@ -575,19 +621,11 @@ static void update_dispatch(int n, const T *V, int64_t ldv, int nc, const double
                             const double *cb, double sign, const T *w_in, T *out, double *partial,
                             hipStream_t stream) {
   const int rpt = orth_rpt(n), G = orth_grid(n);
-  const dim3 grid(G), block(kBlock);
-  if (nc <= 8)
-    hipLaunchKernelGGL((k_update<T, 8, DOTS, NORM>), grid, block, 0, stream, n, rpt, V, ldv, nc,
-                       ca, cb, sign, w_in, out, partial);
-  else if (nc <= 16)
-    hipLaunchKernelGGL((k_update<T, 16, DOTS, NORM>), grid, block, 0, stream, n, rpt, V, ldv, nc,
-                       ca, cb, sign, w_in, out, partial);
-  else if (nc <= 32)
-    hipLaunchKernelGGL((k_update<T, 32, DOTS, NORM>), grid, block, 0, stream, n, rpt, V, ldv, nc,
-                       ca, cb, sign, w_in, out, partial);
-  else
-    hipLaunchKernelGGL((k_update<T, 64, DOTS, NORM>), grid, block, 0, stream, n, rpt, V, ldv, nc,
-                       ca, cb, sign, w_in, out, partial);
+#define PP_UPD_CALL(NCB)                                                                      \
+  hipLaunchKernelGGL((k_update<T, NCB, DOTS, NORM>), dim3(G), dim3(kBlock), 0, stream, n, rpt, \
+                     V, ldv, nc, ca, cb, sign, w_in, out, partial)
+  PP_NCB_SWITCH(nc, PP_UPD_CALL);
+#undef PP_UPD_CALL
 }
 
 template <typename T>
