@@ -68,6 +68,10 @@ extern "C" {
 #define PP_PREC_F64 0    /* everything in FP64 */
 #define PP_PREC_F32_IR 1 /* FP32 chain + CGS2 inside an FP64 refinement loop */
 
+/* ---- how an Arnoldi step applies the preconditioned operator ------------ */
+#define PP_OP_RESIDUAL_POLY 0 /* w = v - pi(A) v: d fused root updates (default) */
+#define PP_OP_PRODUCT 1       /* w = A (p(A) v): d-1 fused updates, then one product */
+
 /* Square sparse matrix in CSR form, all arrays in device memory.
  * row_ptr[n+1] int32, row_ptr[0] = 0, nondecreasing, row_ptr[n] = nnz < 2^31;
  * col_ind[nnz] int32 in [0, n) (any order inside a row; sorted is fastest);
@@ -100,6 +104,8 @@ typedef struct pp_opts {
   double *history;        /* host[history_cap]: implicit relative residual after each step */
   int32_t history_cap;
   int32_t timing;         /* nonzero: fill the per-phase times in pp_stats (adds events) */
+  int32_t op_form;        /* PP_OP_RESIDUAL_POLY (0) or PP_OP_PRODUCT; the same operator
+                             A p(A) in exact arithmetic (pi(alpha) = 1 - alpha p(alpha)) */
 } pp_opts;
 
 /* Solve statistics (all counts follow Section III: a "dot" is one block inner

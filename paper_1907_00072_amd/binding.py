@@ -22,6 +22,7 @@ PP_ERR_ARG, PP_ERR_HIP, PP_ERR_NOMEM, PP_ERR_EIG, PP_ERR_SINGULAR = -1, -2, -3, 
 PP_WARN_DEGREE_REDUCED, PP_WARN_NOT_CONVERGED, PP_WARN_NONFINITE = 1, 2, 3
 PP_F64, PP_F32 = 0, 1
 PP_PREC_F64, PP_PREC_F32_IR = 0, 1
+PP_OP_RESIDUAL_POLY, PP_OP_PRODUCT = 0, 1
 
 EXPORTS = ("pp_build_poly", "pp_apply", "pp_gmres_solve", "pp_poly_roots", "pp_poly_from_roots",
            "pp_poly_free", "pp_roots_from_hessenberg", "pp_csr_transpose", "pp_csr_grad",
@@ -38,7 +39,7 @@ class pp_opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("v0", ctypes.c_void_p), ("poly", ctypes.c_void_p), ("vals_f32", ctypes.c_void_p),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("op_form", ctypes.c_int32)]
 
 
 class pp_stats(ctypes.Structure):
@@ -279,8 +280,12 @@ class Stats:
 def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float = 1e-8,
                    v0=None, poly: Optional[Poly] = None, precision: str = "f64",
                    max_iters: int = 0, inner_tol: float = 0.0, max_outer: int = 0,
-                   vals_f32=None, history: int = 0, timing: bool = False, stream=None):
-    """Solve A x = b; returns (x, Stats).  ``x`` (if given) is the start guess and is overwritten."""
+                   vals_f32=None, history: int = 0, timing: bool = False, op_form: str = "pi",
+                   stream=None):
+    """Solve A x = b; returns (x, Stats).  ``x`` (if given) is the start guess and is overwritten.
+
+    ``op_form``: "pi" applies A p(A) v as v - pi(A) v (default), "p" as A (p(A) v).
+    """
     torch = _torch()
     _dev_vec(b, torch.float64, A.n, "b")
     if x is None:
@@ -305,6 +310,7 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
         o.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         o.history_cap = int(history)
     o.timing = 1 if timing else 0
+    o.op_form = {"pi": PP_OP_RESIDUAL_POLY, "p": PP_OP_PRODUCT}[op_form]
     st = pp_stats()
     rc = lib().pp_gmres_solve(ctypes.byref(A.c()), _ptr(b), _ptr(x), int(m), int(d), float(tol),
                               ctypes.byref(o), _stream(stream), ctypes.byref(st))

@@ -26,10 +26,15 @@ struct Csr {
 };
 
 // One launch of the fused product + root-update chain.
+// Accumulating form (y = p(A) v):
 //  kind 0 (real root): y = y_in + c1*p; p' = p - c1*A p  (fold: y += cf*p', p' not stored)
-//  kind 1 (pair, first half): t = A p; y = y_in + c1*p - c2*t (t stored unless last)
+//  kind 1 (pair, first half): t = A p; y = y_in + c1*p - c2*t (t stored unless `last`)
 //  kind 2 (pair, second half): p' = p - c1*t + c2*A t (fold: y = y_in + cf*p', p' not stored)
-// g is the gathered vector (p for kinds 0/1, t for kind 2), self is p for kind 2.
+// Operator form (w = A p(A) v = v - pi(A) v, no accumulator):
+//  kind 3 (real root): p' = p - c1*A p
+//  kind 2 with `last`: as above, then out = ys*y_in - p'
+//  kind 3 with `last`: out = ys*y_in - p'   (y_in is the chain's input vector v)
+// g is the gathered vector (p for kinds 0/1/3, t for kind 2), self is p for kind 2.
 template <typename T>
 struct ChainArgs {
   const T *g;
@@ -40,10 +45,12 @@ struct ChainArgs {
   const T *y_in;  // nullptr = zero
   T *y_out;
   double c1, c2, cf;
+  const double *yscale;  // scale of y_in in the operator form's last step (nullptr = 1)
 };
 
+// `fold` and `last` select the variants above (fold: kinds 0 and 2; last: kinds 1, 2, 3).
 template <typename T>
-hipError_t launch_chain(const Csr<T> &A, int kind, bool fold, bool noout, const ChainArgs<T> &a,
+hipError_t launch_chain(const Csr<T> &A, int kind, bool fold, bool last, const ChainArgs<T> &a,
                         hipStream_t stream);
 
 // y_out = y_in + c * (gscale * g) elementwise (a degree-0 polynomial step).

@@ -111,7 +111,7 @@ __device__ __forceinline__ T tile_row_sum(const Csr<T> &A, const T *__restrict__
 }
 
 // ------------------------------------------------------------------ chain
-template <typename T, int KIND, bool FOLD, bool NOOUT>
+template <typename T, int KIND, bool FOLD, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
   __shared__ T s_buf[LdsCap<T>::value];
   const int r0 = blockIdx.x * kBlock;
@@ -119,6 +119,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
   const int t = threadIdx.x;
   const int i = r0 + t;
   const bool live = t < nrows;
+  constexpr bool kReadY = (KIND == 0) || (KIND == 1) || (KIND == 2 && (FOLD || LAST)) ||
+                          (KIND == 3 && LAST);
   // own-row operands first, so their latency overlaps the product
   int rb = 0, re = 0;
   T own = T(0), yv = T(0), sf = T(0);
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
     rb = A.rp[i];
     re = A.rp[i + 1];
     own = a.g[i];
-    if (KIND != 2 || FOLD) yv = a.y_in ? ldnt(a.y_in + i) : T(0);
+    if (kReadY) yv = a.y_in ? ldnt(a.y_in + i) : T(0);
     if (KIND == 2) sf = ldnt(a.self + i);
   }
   const T gs = a.gscale ? (T)(*a.gscale) : T(1);
@@ -148,12 +150,23 @@ __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
     const T p = gs * own;
     const T tt = gs * acc;
     stnt(yv + c1 * p - c2 * tt, a.y_out + i);
-    if constexpr (!NOOUT) stnt(tt, a.out + i);
-  } else {
+    if constexpr (!LAST) stnt(tt, a.out + i);
+  } else if constexpr (KIND == 2) {
     const T ss = a.sscale ? (T)(*a.sscale) : T(1);
     const T pn = ss * sf - c1 * (gs * own) + c2 * (gs * acc);
     if constexpr (FOLD) {
       stnt(yv + cf * pn, a.y_out + i);
+    } else if constexpr (LAST) {
+      const T ys = a.yscale ? (T)(*a.yscale) : T(1);
+      stnt(ys * yv - pn, a.out + i);
+    } else {
+      stnt(pn, a.out + i);
+    }
+  } else {
+    const T pn = gs * own - c1 * (gs * acc);
+    if constexpr (LAST) {
+      const T ys = a.yscale ? (T)(*a.yscale) : T(1);
+      stnt(ys * yv - pn, a.out + i);
     } else {
       stnt(pn, a.out + i);
     }
@@ -528,25 +541,29 @@ inline int orth_rpt(int n) {
 
 // ------------------------------------------------------------- wrappers
 template <typename T>
-hipError_t launch_chain(const Csr<T> &A, int kind, bool fold, bool noout, const ChainArgs<T> &a,
+hipError_t launch_chain(const Csr<T> &A, int kind, bool fold, bool last, const ChainArgs<T> &a,
                         hipStream_t stream) {
   const dim3 grid(tiles_of(A.n)), block(kBlock);
-  if (kind == 0) {
-    if (fold)
-      hipLaunchKernelGGL((k_chain<T, 0, true, false>), grid, block, 0, stream, A, a);
-    else
-      hipLaunchKernelGGL((k_chain<T, 0, false, false>), grid, block, 0, stream, A, a);
-  } else if (kind == 1) {
-    if (noout)
-      hipLaunchKernelGGL((k_chain<T, 1, false, true>), grid, block, 0, stream, A, a);
-    else
-      hipLaunchKernelGGL((k_chain<T, 1, false, false>), grid, block, 0, stream, A, a);
-  } else {
-    if (fold)
-      hipLaunchKernelGGL((k_chain<T, 2, true, false>), grid, block, 0, stream, A, a);
-    else
-      hipLaunchKernelGGL((k_chain<T, 2, false, false>), grid, block, 0, stream, A, a);
+#define PP_CHAIN(K, F, L) hipLaunchKernelGGL((k_chain<T, K, F, L>), grid, block, 0, stream, A, a)
+  switch (kind) {
+    case 0:
+      if (fold) PP_CHAIN(0, true, false); else PP_CHAIN(0, false, false);
+      break;
+    case 1:
+      if (last) PP_CHAIN(1, false, true); else PP_CHAIN(1, false, false);
+      break;
+    case 2:
+      if (fold) PP_CHAIN(2, true, false);
+      else if (last) PP_CHAIN(2, false, true);
+      else PP_CHAIN(2, false, false);
+      break;
+    case 3:
+      if (last) PP_CHAIN(3, false, true); else PP_CHAIN(3, false, false);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
+#undef PP_CHAIN
   return hipGetLastError();
 }
 

@@ -273,6 +273,48 @@ int run_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
   return PP_OK;
 }
 
+// w_out = A p(A) (gscale * g), evaluated as v - pi(A) v with v = gscale * g:
+// one fused root-update launch per real root (p' = p - A p / theta) and two per
+// conjugate pair (t = A p, then p' = p - c1 t + c2 A t), the last launch writing
+// v - p' instead of p'.  d products, no accumulator vector.
+template <typename T>
+int run_op_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
+                 const double *gscale, T *w_out, T *P0, T *P1, T *Tb, hipStream_t s,
+                 Counters *cnt, double *bytes = nullptr, int64_t *launches = nullptr) {
+  auto account = [&](int vec_rw) {
+    if (bytes) *bytes += product_bytes(A, vec_rw);
+    if (launches) ++*launches;
+    if (cnt) cnt->spmvs++;
+  };
+  const int K = (int)steps.size();
+  const T *cur = g;
+  const double *cs = gscale;
+  T *bufs[2] = {P0, P1};
+  int pb = 0;
+  for (int k = 0; k < K; ++k) {
+    const ppn::Step &st = steps[k];
+    const bool last = (k == K - 1);
+    T *dst = last ? w_out : bufs[pb];
+    if (st.kind == 0) {
+      ppk::ChainArgs<T> a{cur, cs, nullptr, nullptr, dst, last ? g : nullptr, nullptr,
+                          st.c1, 0.0, 0.0, last ? gscale : nullptr};
+      PP_TRY_HIP(ppk::launch_chain<T>(A, 3, false, last, a, s));
+      account(1 + (last ? 1 : 0));
+    } else {
+      PP_TRY_HIP(ppk::launch_spmv<T>(A, cur, cs, Tb, s));
+      account(1);
+      ppk::ChainArgs<T> b{Tb, nullptr, cur, cs, dst, last ? g : nullptr, nullptr,
+                          st.c1, st.c2, 0.0, last ? gscale : nullptr};
+      PP_TRY_HIP(ppk::launch_chain<T>(A, 2, false, last, b, s));
+      account(2 + (last ? 1 : 0));
+    }
+    cur = dst;
+    cs = nullptr;
+    pb ^= 1;
+  }
+  return PP_OK;
+}
+
 // out = w_in - V(:, 0..nc) coef (chunks of kMaxCols columns); optional norm of out.
 template <typename T>
 int update_any(Work<T> &w, int nc, const double *coef, const T *w_in, T *out, bool norm,
@@ -300,23 +342,30 @@ int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s) {
 // hcol[0..j+1] receives column j of Hbar; *w0 an estimate of ||Op(V_j)||.
 // Returns PP_OK, or PP_WARN_NONFINITE when a coefficient is not finite.
 template <typename T>
-int arnoldi_step(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &w, int j,
-                 hipStream_t s, Timers &tm, Counters &cnt, double *hcol, double *w0) {
+int arnoldi_step(const Csr<T> &A, const std::vector<ppn::Step> *steps, int op_form, Work<T> &w,
+                 int j, hipStream_t s, Timers &tm, Counters &cnt, double *hcol, double *w0) {
   const T *vj = w.V + (int64_t)j * w.ldv;
   const double *sj = w.colscale + j;
   const double t_wall0 = tm.on ? now_s() : 0.0;
   tm.mark(0, s);
-  if (steps && !steps->empty()) {
-    PP_TRY(run_chain<T>(A, *steps, vj, sj, nullptr, w.Z, w.P0, w.P1, w.Tb, s, &cnt,
-                        &cnt.bytes_chain, &cnt.launches_chain));
+  const bool poly = steps && !steps->empty();
+  if (poly && op_form == PP_OP_RESIDUAL_POLY) {
+    PP_TRY(run_op_chain<T>(A, *steps, vj, sj, w.W, w.P0, w.P1, w.Tb, s, &cnt, &cnt.bytes_chain,
+                           &cnt.launches_chain));
     tm.mark(1, s);
-    PP_TRY_HIP(ppk::launch_spmv<T>(A, w.Z, nullptr, w.W, s));
   } else {
-    tm.mark(1, s);
-    PP_TRY_HIP(ppk::launch_spmv<T>(A, vj, sj, w.W, s));
+    if (poly) {
+      PP_TRY(run_chain<T>(A, *steps, vj, sj, nullptr, w.Z, w.P0, w.P1, w.Tb, s, &cnt,
+                          &cnt.bytes_chain, &cnt.launches_chain));
+      tm.mark(1, s);
+      PP_TRY_HIP(ppk::launch_spmv<T>(A, w.Z, nullptr, w.W, s));
+    } else {
+      tm.mark(1, s);
+      PP_TRY_HIP(ppk::launch_spmv<T>(A, vj, sj, w.W, s));
+    }
+    cnt.spmvs++;
+    cnt.bytes_spmv += product_bytes(A, 1);
   }
-  cnt.spmvs++;
-  cnt.bytes_spmv += product_bytes(A, 1);
   tm.mark(2, s);
   const int nc = j + 1;
   const int L = w.L;
@@ -384,7 +433,7 @@ int build_poly_impl(const Csr<T> &A, const double *v0, int d, Work<T> &w, hipStr
   int sdim = d;
   for (int j = 0; j < d; ++j) {
     double w0 = 0.0;
-    int rc = arnoldi_step<T>(A, nullptr, w, j, s, tm, cnt, hcol.data(), &w0);
+    int rc = arnoldi_step<T>(A, nullptr, 0, w, j, s, tm, cnt, hcol.data(), &w0);
     if (rc < 0) return rc;
     if (rc == PP_WARN_NONFINITE) return PP_ERR_SINGULAR;
     for (int i = 0; i <= j + 1; ++i) Hbar[i + (size_t)j * ldh] = hcol[i];
@@ -445,7 +494,8 @@ struct Lsq {
 // One GMRES(m) cycle from V(:,0) (colscale[0] set) with start residual norm beta.
 // Returns steps taken in *k and the solution coefficients in y.
 template <typename T>
-int gmres_cycle(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &w, int m,
+int gmres_cycle(const Csr<T> &A, const std::vector<ppn::Step> *steps, int op_form, Work<T> &w,
+                int m,
                 double beta, double tol_abs, double bscale, int max_steps, hipStream_t s,
                 Timers &tm, Counters &cnt, std::vector<double> &y, int *k, double *res,
                 bool *nonfinite) {
@@ -458,7 +508,7 @@ int gmres_cycle(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &w
   const int jmax = std::min(m, max_steps);
   for (int j = 0; j < jmax; ++j) {
     double w0 = 0.0;
-    int rc = arnoldi_step<T>(A, steps, w, j, s, tm, cnt, hcol.data(), &w0);
+    int rc = arnoldi_step<T>(A, steps, op_form, w, j, s, tm, cnt, hcol.data(), &w0);
     if (rc < 0) return rc;
     cnt.iters++;
     if (rc == PP_WARN_NONFINITE) {
@@ -696,7 +746,7 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
     int k = 0;
     double res = 0.0;
     bool nonfinite = false;
-    PP_TRY(gmres_cycle<double>(A, steps, w, in.m, beta, in.tol * bnorm, bnorm,
+    PP_TRY(gmres_cycle<double>(A, steps, in.o.op_form, w, in.m, beta, in.tol * bnorm, bnorm,
                                max_iters - cnt.iters, s, tm, cnt, y, &k, &res, &nonfinite));
     if (nonfinite) {
       status = worst(status, PP_WARN_NONFINITE);
@@ -839,7 +889,8 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
     int k = 0;
     double res = 0.0;
     bool nonfinite = false;
-    PP_TRY(gmres_cycle<float>(A32, steps, w, in.m, beta_in, inner_tol * beta_in, beta_in,
+    PP_TRY(gmres_cycle<float>(A32, steps, in.o.op_form, w, in.m, beta_in, inner_tol * beta_in,
+                              beta_in,
                               max_iters - cnt.iters, s, tm, cnt, y, &k, &res, &nonfinite));
     ++outer;
     if (nonfinite) {
@@ -891,6 +942,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
   SolveIn in{A, b, x, m, d, tol, pp_opts{}, static_cast<hipStream_t>(stream)};
   if (opt) in.o = *opt;
   if (in.o.precision != PP_PREC_F64 && in.o.precision != PP_PREC_F32_IR) return PP_ERR_ARG;
+  if (in.o.op_form != PP_OP_RESIDUAL_POLY && in.o.op_form != PP_OP_PRODUCT) return PP_ERR_ARG;
   if (in.o.poly) {
     if (in.o.poly->n != A->n) return PP_ERR_ARG;
   } else if (d > A->n) {

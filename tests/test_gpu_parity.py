@@ -152,9 +152,10 @@ def test_build_poly_degree_reduced(B):
     assert r.size == 3 and np.allclose(r, [1.0, 2.0, 4.0], rtol=1e-10)
 
 
-def _solve_both(B, Ah, b, v0, m, d, tol, max_iters=5000):
+def _solve_both(B, Ah, b, v0, m, d, tol, max_iters=5000, op_form="pi"):
     A = B.CSRMatrix.from_host(Ah)
-    x, st = B.pp_gmres_solve(A, _up(b), m=m, d=d, tol=tol, v0=_up(v0), max_iters=max_iters)
+    x, st = B.pp_gmres_solve(A, _up(b), m=m, d=d, tol=tol, v0=_up(v0), max_iters=max_iters,
+                             op_form=op_form)
     xo, so = ogmres.pp_gmres(Ah.to_scipy(), b, m, tol, v0=v0, d=d, max_iters=max_iters)
     return x.cpu().numpy(), st, xo, so
 
@@ -167,10 +168,11 @@ def _assert_parity(st, so, xg, xo, tol):
         assert st.spmvs == so.spmvs and st.dots == so.dots
 
 
-@pytest.mark.parametrize("d", [10, 0, 4])
-def test_solve_config1_full(B, d):
+@pytest.mark.parametrize("d,op_form", [(10, "pi"), (10, "p"), (0, "pi"), (4, "pi"), (1, "pi"),
+                                       (1, "p")])
+def test_solve_config1_full(B, d, op_form):
     P = W.config(1)
-    xg, st, xo, so = _solve_both(B, P.A, P.b, P.v0, P.m, d, P.tol)
+    xg, st, xo, so = _solve_both(B, P.A, P.b, P.v0, P.m, d, P.tol, op_form=op_form)
     _assert_parity(st, so, xg, xo, P.tol)
 
 
@@ -180,14 +182,24 @@ def test_solve_cd3d_ragged_tiles(B):
     _assert_parity(st, so, xg, xo, P.tol)
 
 
-def test_solve_complex_roots(B):
+@pytest.mark.parametrize("op_form", ["pi", "p"])
+def test_solve_complex_roots(B, op_form):
     Ah = W.random_csr(777, 12, seed=5, diag_shift=4.0)
     b = W.normal(777, 3)
     v0 = W.uniform(777, 4)
     roots, _ = opoly.build_poly(Ah.to_scipy(), v0, 6)
     assert np.any(roots.imag != 0)
-    xg, st, xo, so = _solve_both(B, Ah, b, v0, 20, 6, 1e-10)
+    xg, st, xo, so = _solve_both(B, Ah, b, v0, 20, 6, 1e-10, op_form=op_form)
     _assert_parity(st, so, xg, xo, 1e-10)
+
+
+@pytest.mark.parametrize("op_form", ["pi", "p"])
+def test_solve_all_complex_roots_cd3d(B, op_form):
+    P = W.config(2, N=24)   # mesh Peclet ~1: all but one of the 25 roots are complex
+    roots, _ = opoly.build_poly(P.A.to_scipy(), P.v0, 25)
+    assert np.sum(roots.imag != 0) == 24
+    xg, st, xo, so = _solve_both(B, P.A, P.b, P.v0, P.m, 25, P.tol, op_form=op_form)
+    _assert_parity(st, so, xg, xo, P.tol)
 
 
 def test_solve_is_bitwise_deterministic(B):
