@@ -1,0 +1,82 @@
+"""Write tests/golden/fullsize_refs.json: oracle results at the full workload sizes.
+
+Runs only the CPU oracle (oracle/) on the seeded workloads: the full solves are
+too slow to repeat inside a GPU test, so their iteration counts and sampled
+solution entries are stored here once.  Usage (from the repository root):
+
+    python tests/golden/make_fullsize_refs.py [--only NAME ...]
+
+Takes tens of minutes on an 8-core host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import gmres as og  # noqa: E402
+from oracle import poly as op  # noqa: E402
+from paper_1907_00072_amd import workloads as W  # noqa: E402
+
+OUT = os.path.join(ROOT, "tests", "golden", "fullsize_refs.json")
+NSAMPLE = 64
+
+
+def sample_idx(n, seed=11):
+    return np.sort(np.random.default_rng(seed).choice(n, size=NSAMPLE, replace=False))
+
+
+def record(name, P, d, x, st, t, extra=None):
+    idx = sample_idx(P.A.n)
+    rec = {"workload": P.name, "n": P.A.n, "nnz": P.A.nnz, "m": P.m, "d": d, "tol": P.tol,
+           "iters": st.iters, "cycles": st.cycles, "spmvs": st.spmvs, "dots": st.dots,
+           "relres_true": st.relres_true, "converged": st.converged,
+           "x_norm": float(np.linalg.norm(x)), "x_absmax": float(np.max(np.abs(x))),
+           "sample_idx": idx.tolist(), "x_sample": x[idx].tolist(),
+           "roots_re": [] if st.roots is None else np.real(st.roots).tolist(),
+           "roots_im": [] if st.roots is None else np.imag(st.roots).tolist(),
+           "seconds": t}
+    if extra:
+        rec.update(extra)
+    print(f"{name}: iters {st.iters} cycles {st.cycles} relres {st.relres_true:.3e} "
+          f"({t:.0f}s)", flush=True)
+    return rec
+
+
+def run(names):
+    refs = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    jobs = []
+    for d in (25, 10, 40, 0):
+        jobs.append((f"cd3d_128_pe50_d{d}", 2, d))
+    jobs.append(("stencil27_96_ir_d25", 3, 25))
+    jobs.append(("stencil27_96_f64_d25", 3, -25))
+    jobs.append(("cd3d_256_pe100_d40", 5, 40))
+    for name, cfg, d in jobs:
+        if names and name not in names:
+            continue
+        P = W.config(cfg)
+        A = P.A.to_scipy()
+        t0 = time.time()
+        if cfg == 3 and d > 0:
+            x, st = og.pp_gmres_ir(A, P.b, P.m, d, P.tol, P.v0,
+                                   inner_tol=P.extra["inner_tol"], max_outer=50)
+            rec = record(name, P, d, x, st, time.time() - t0, {"outer": st.outer})
+        else:
+            dd = abs(d)
+            x, st = og.pp_gmres(A, P.b, P.m, P.tol, v0=P.v0, d=dd, max_iters=20000)
+            rec = record(name, P, dd, x, st, time.time() - t0)
+        refs[name] = rec
+        json.dump(refs, open(OUT, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", nargs="*", default=None)
+    run(ap.parse_args().only)

@@ -1,0 +1,171 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py uses.
+
+* 128^3 convection-diffusion (n = 2.1M) and the 96^3 27-point stencil (n = 885k):
+  iteration counts, counters, roots and 64 sampled solution entries against
+  oracle runs stored in tests/golden/fullsize_refs.json (written by
+  tests/golden/make_fullsize_refs.py, which calls only the oracle).
+* 256^3 (n = 16.8M, the benchmark): p(A)v at sampled rows computed exactly by the
+  oracle on the sub-grid box of radius d-1 around each row (entries of p(A)v at a
+  row depend only on v within graph distance d-1), the true residual of the
+  solve recomputed by SciPy, and the stored oracle solve.
+* 512^2 adjoint (n = 262k): dL/dvals and dL/db against the oracle's direct
+  adjoint on every stored entry and Sherman-Morrison central differences on the
+  64 sampled entries.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj
+from oracle import poly as opoly
+from paper_1907_00072_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REFS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_refs.json")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1907_00072_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def refs():
+    return json.load(open(REFS))
+
+
+def _up(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda:0", dtype=dtype)
+
+
+def _match_sets(a, b):
+    a = sorted(np.asarray(a, complex), key=lambda t: (t.real, t.imag))
+    b = sorted(np.asarray(b, complex), key=lambda t: (t.real, t.imag))
+    return max(abs(x - y) / abs(y) for x, y in zip(a, b))
+
+
+def _check_against_ref(ref, st, x, tol):
+    xg = x.cpu().numpy()
+    assert st.relres_true < tol and ref["converged"]
+    assert abs(st.iters - ref["iters"]) <= max(1, round(0.02 * ref["iters"])), (st.iters,
+                                                                                 ref["iters"])
+    if st.iters == ref["iters"]:
+        idx = np.asarray(ref["sample_idx"])
+        err = np.max(np.abs(xg[idx] - np.asarray(ref["x_sample"])))
+        assert err <= 1e-8 * ref["x_absmax"], err
+        assert abs(np.linalg.norm(xg) - ref["x_norm"]) <= 1e-8 * ref["x_norm"]
+    return xg
+
+
+@pytest.fixture(scope="module")
+def cd3d_128(B):
+    P = W.config(2)
+    return P, B.CSRMatrix.from_host(P.A)
+
+
+@pytest.mark.parametrize("d", [25, 10, 40, 0])
+def test_cd3d_128_solve(B, refs, cd3d_128, d):
+    P, A = cd3d_128
+    ref = refs[f"cd3d_128_pe50_d{d}"]
+    x, st = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=d, tol=P.tol, v0=_up(P.v0))
+    _check_against_ref(ref, st, x, P.tol)
+    if st.iters == ref["iters"]:
+        assert st.spmvs == ref["spmvs"] and st.dots == ref["dots"]
+    if d:
+        p = B.pp_build_poly(A, _up(P.v0), d)
+        ref_roots = np.asarray(ref["roots_re"]) + 1j * np.asarray(ref["roots_im"])
+        assert _match_sets(p.roots(), ref_roots) <= 1e-8
+
+
+def test_cd3d_128_product_form_matches(B, refs, cd3d_128):
+    P, A = cd3d_128
+    ref = refs["cd3d_128_pe50_d25"]
+    x, st = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=25, tol=P.tol, v0=_up(P.v0), op_form="p")
+    _check_against_ref(ref, st, x, P.tol)
+
+
+def test_stencil27_96_fp64_and_refinement(B, refs):
+    P = W.config(3)
+    A = B.CSRMatrix.from_host(P.A)
+    x64, s64 = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=P.d, tol=P.tol, v0=_up(P.v0))
+    _check_against_ref(refs["stencil27_96_f64_d25"], s64, x64, P.tol)
+    ref = refs["stencil27_96_ir_d25"]
+    x, st = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=P.d, tol=P.tol, v0=_up(P.v0),
+                             precision="f32_ir", inner_tol=P.extra["inner_tol"])
+    assert st.relres_true < P.tol and ref["converged"]
+    assert abs(st.outer - ref["outer"]) <= 1
+    # both refinement solves are within cond * tol of the FP64 solution
+    xg, xf = x.cpu().numpy(), x64.cpu().numpy()
+    assert np.linalg.norm(xg - xf) <= 1e-8 * np.linalg.norm(xf)
+
+
+def _box_rows(N, center, r):
+    """Row indices of the sub-grid box of radius r around grid point `center` (x fastest)."""
+    cz, cy, cx = center
+    zs = np.arange(max(cz - r, 0), min(cz + r, N - 1) + 1)
+    ys = np.arange(max(cy - r, 0), min(cy + r, N - 1) + 1)
+    xs = np.arange(max(cx - r, 0), min(cx + r, N - 1) + 1)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    return (Z * N * N + Y * N + X).ravel()
+
+
+def test_cd3d_256_sampled_chain_rows_and_solve(B, refs):
+    P = W.config(5)
+    N = 256
+    A = B.CSRMatrix.from_host(P.A)
+    As = P.A.to_scipy()
+    d = P.d
+    p = B.pp_build_poly(A, _up(P.v0), d)
+    roots = p.roots()
+    v = W.uniform(P.A.n, 9)
+    y = B.pp_apply(A, p, _up(v)).cpu().numpy()
+    rng = np.random.default_rng(12)
+    centers = [(0, 0, 0), (N - 1, 17, 200)] + [tuple(rng.integers(0, N, 3)) for _ in range(2)]
+    yinf = np.max(np.abs(y))
+    for c in centers:
+        rows = _box_rows(N, c, d - 1)
+        sub = As[rows][:, rows]
+        yb = opoly.apply_poly(sub, roots, v[rows])
+        i_loc = int(np.searchsorted(rows, c[0] * N * N + c[1] * N + c[2]))
+        i_glob = rows[i_loc]
+        assert abs(y[i_glob] - yb[i_loc]) <= 1e-12 * yinf, (c, y[i_glob], yb[i_loc])
+    x, st = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=d, tol=P.tol, v0=_up(P.v0))
+    xg = x.cpu().numpy()
+    relres = np.linalg.norm(P.b - As @ xg) / np.linalg.norm(P.b)
+    assert relres < P.tol and abs(relres - st.relres_true) <= 1e-3 * relres
+    ref = refs.get("cd3d_256_pe100_d40")
+    assert ref is not None, "run tests/golden/make_fullsize_refs.py --only cd3d_256_pe100_d40"
+    _check_against_ref(ref, st, x, P.tol)
+
+
+def test_adjoint_512(B):
+    from paper_1907_00072_amd.autograd import SolveConfig, pp_solve
+    P = W.config(4)
+    Ah = P.A
+    xt = P.extra["x_target"]
+    pattern = B.CSRMatrix.from_host(Ah)
+    vals = _up(Ah.vals).requires_grad_(True)
+    b = _up(P.b).requires_grad_(True)
+    cfg = SolveConfig(m=P.m, d=P.d, tol=P.tol, v0=_up(P.v0), adj_v0=_up(P.extra["v0_adjoint"]))
+    x = pp_solve(pattern, vals, b, cfg)
+    loss = 0.5 * ((x - _up(xt)) ** 2).sum()
+    loss.backward()
+    gv = vals.grad.cpu().numpy()
+    gb = b.grad.cpu().numpy()
+    assert all(s.relres_true < P.tol for _, s in cfg.stats)
+    M = Ah.to_scipy()
+    S = oadj.DirectSolver(M)
+    xo, lam, gb_ref, gv_ref = oadj.adjoint_gradient(M, P.b, xt, solver=S)
+    assert np.max(np.abs(gv - gv_ref)) <= 1e-6 * np.max(np.abs(gv_ref))
+    assert np.max(np.abs(gb - gb_ref)) <= 1e-6 * np.max(np.abs(gb_ref))
+    ents = P.extra["fd_entries"]
+    fd = oadj.fd_gradient_vals(M, P.b, xt, ents, h=P.extra["fd_h"], solver=S, x=xo)
+    assert np.max(np.abs(gv[ents] - fd)) <= 1e-6 * np.max(np.abs(gv_ref))
