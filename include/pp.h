@@ -59,6 +59,7 @@ extern "C" {
 #define PP_WARN_DEGREE_REDUCED 1 /* Arnoldi on v0 broke down after s < d steps: s roots */
 #define PP_WARN_NOT_CONVERGED 2  /* iteration cap reached; x is the last iterate */
 #define PP_WARN_NONFINITE 3      /* NaN/Inf met; x is the last finite iterate */
+#define PP_WARN_CHOLESKY 4       /* power basis: Gram matrix not numerically positive definite */
 
 /* ---- value types ----------------------------------------------------- */
 #define PP_F64 0
@@ -183,9 +184,35 @@ int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *st
 int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, double tol,
                    const pp_opts *opt, void *stream, pp_stats *st);
 
+/* The paper's own construction of the polynomial (Section II, eqs. (1)-(2)):
+ * the power basis V = [v0, A v0, ..., A^deg v0] (left unnormalised), W = A V, and
+ * the normal equations (W^T W) y = W^T v0 solved by a Cholesky factorisation on
+ * the host; p(A) = sum_{k=0}^{deg} y_k A^k, applied by Horner's rule (deg fused
+ * product + axpy launches).  deg+1 products and two block inner products build it.
+ *   A, v0    : as for pp_build_poly (v0 device FP64, not normalised)
+ *   deg      : 0 <= deg <= 62 and deg + 1 <= n
+ *   auto_degree : nonzero -> Section IV's heuristic: factor the Gram matrices of
+ *              degrees 0, 1, ..., deg (leading blocks of one matrix) and keep the
+ *              highest degree before the first Cholesky failure; returns PP_OK.
+ *              zero -> use degree deg; a Cholesky failure at column k keeps the
+ *              coefficients of the leading (k-1) block with zeros above (the
+ *              plateau of Table I) and returns PP_WARN_CHOLESKY.
+ *   info_out : optional; the 1-based column where the Cholesky failed (POTRF's
+ *              info), 0 if none.
+ * The polynomial is usable in pp_apply and as pp_opts.poly of pp_gmres_solve.
+ * Returns PP_OK, PP_WARN_CHOLESKY, PP_ERR_ARG, PP_ERR_SINGULAR (A v0 = 0 or a
+ * non-finite Gram matrix), PP_ERR_HIP, PP_ERR_NOMEM. */
+int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_degree,
+                        void *stream, pp_poly **out, int *info_out);
+
+/* Copy a power-basis polynomial's coefficients (y_0 .. y_deg) to host c[cap];
+ * *n_out = deg + 1.  PP_ERR_ARG for a root-form polynomial or a short buffer. */
+int pp_poly_coeffs(const pp_poly *p, double *c, int cap, int *n_out);
+
 /* Copy the Leja-ordered roots to host arrays re[cap], im[cap]; *d_out = number
  * of roots.  A complex pair appears as (Im > 0, its conjugate) in adjacent slots.
- * Returns PP_ERR_ARG if cap is too small or a pointer is NULL. */
+ * Returns PP_ERR_ARG if cap is too small, a pointer is NULL, or p is a
+ * power-basis polynomial. */
 int pp_poly_roots(const pp_poly *p, double *re, double *im, int cap, int *d_out);
 
 /* Make a polynomial from given roots (host arrays), e.g. to resume a solve with

@@ -29,7 +29,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .poly import BREAKDOWN_RTOL, apply_poly, build_poly, matvec
+from .poly import BREAKDOWN_RTOL, apply_poly, apply_power, build_poly, matvec
 
 __all__ = ["GmresStats", "gmres_cycle", "pp_gmres", "pp_gmres_ir", "lsq_residual"]
 
@@ -59,7 +59,13 @@ def lsq_residual(Hbar, beta):
     return y, abs(g[k])
 
 
-def gmres_cycle(A, r0, roots, m, tol_abs, max_steps, st: GmresStats):
+def _precondition(A, roots, coeffs, v):
+    if coeffs is not None:
+        return apply_power(A, coeffs, v)
+    return apply_poly(A, roots, v)
+
+
+def gmres_cycle(A, r0, roots, m, tol_abs, max_steps, st: GmresStats, coeffs=None):
     """One GMRES cycle from residual r0 on the operator A p(A).
 
     Stops after m steps, after ``max_steps`` steps, on a happy breakdown, or
@@ -70,7 +76,7 @@ def gmres_cycle(A, r0, roots, m, tol_abs, max_steps, st: GmresStats):
     """
     n = r0.size
     dt = r0.dtype
-    d = 0 if roots is None else len(roots)
+    d = (len(coeffs) if coeffs is not None else 0) or (0 if roots is None else len(roots))
     beta = float(np.linalg.norm(r0))
     V = np.zeros((n, m + 1), dtype=dt, order="F")
     V[:, 0] = r0 / beta
@@ -79,7 +85,7 @@ def gmres_cycle(A, r0, roots, m, tol_abs, max_steps, st: GmresStats):
     y = np.zeros(0)
     res = beta
     for j in range(min(m, max_steps)):
-        z = apply_poly(A, roots, V[:, j]) if d else V[:, j]
+        z = _precondition(A, roots, coeffs, V[:, j]) if d else V[:, j]
         w = matvec(A, z)
         st.spmvs += max(d, 1)
         w0 = np.linalg.norm(w)
@@ -100,17 +106,20 @@ def gmres_cycle(A, r0, roots, m, tol_abs, max_steps, st: GmresStats):
             break
         V[:, j + 1] = w / hn
     u = V[:, :k] @ y.astype(dt)
-    dx = apply_poly(A, roots, u) if d else u
+    dx = _precondition(A, roots, coeffs, u) if d else u
     if d:
         st.spmvs += d - 1
     return dx, res
 
 
-def pp_gmres(A, b, m, tol, roots=None, x0=None, max_iters=100000, v0=None, d=None):
+def pp_gmres(A, b, m, tol, roots=None, x0=None, max_iters=100000, v0=None, d=None,
+             coeffs=None):
     """Restarted GMRES(m) with p(A) as right preconditioner.
 
     Either pass Leja-ordered ``roots`` (None or empty: no preconditioning), or
-    a start vector ``v0`` and the number of roots ``d`` to build them.
+    a start vector ``v0`` and the number of roots ``d`` to build them, or the
+    power-basis coefficients ``coeffs`` (p(A) = sum_k coeffs[k] A^k; degree
+    len(coeffs)-1, so d = len(coeffs) products per step).
     Works in b's dtype.  Returns (x, GmresStats).
     """
     st = GmresStats()
@@ -123,7 +132,7 @@ def pp_gmres(A, b, m, tol, roots=None, x0=None, max_iters=100000, v0=None, d=Non
     if roots is not None and len(roots) == 0:
         roots = None
     st.roots = roots
-    st.nroots = 0 if roots is None else len(roots)
+    st.nroots = len(coeffs) if coeffs is not None else (0 if roots is None else len(roots))
     st._bnorm = float(np.linalg.norm(b))
     x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=dt).copy()
     r = b - matvec(A, x)
@@ -134,7 +143,8 @@ def pp_gmres(A, b, m, tol, roots=None, x0=None, max_iters=100000, v0=None, d=Non
     st.true_history.append(st.relres_true)
     while st.relres_true >= tol and st.iters < max_iters:
         st.cycles += 1
-        dx, res = gmres_cycle(A, r, roots, m, tol * st._bnorm, max_iters - st.iters, st)
+        dx, res = gmres_cycle(A, r, roots, m, tol * st._bnorm, max_iters - st.iters, st,
+                              coeffs=coeffs)
         st.relres_implicit = res / st._bnorm
         x = x + dx
         r = b - matvec(A, x)

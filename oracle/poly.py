@@ -26,7 +26,7 @@ import numpy as np
 import scipy.linalg
 
 __all__ = ["matvec", "arnoldi", "harmonic_ritz", "leja_order", "build_poly",
-           "apply_poly", "power_basis_poly", "BREAKDOWN_RTOL"]
+           "apply_poly", "power_basis_poly", "apply_power", "auto_degree", "BREAKDOWN_RTOL"]
 
 # Happy breakdown of Arnoldi: the orthogonalised vector is at most this
 # fraction of ||A q_j|| (the Krylov space is numerically invariant).
@@ -178,26 +178,75 @@ def apply_poly(A, roots, v):
     return y.real.astype(v.dtype)
 
 
-def power_basis_poly(A, v0, deg):
-    """The paper's construction (Section II, eqs. (1)-(2)).
-
-    Builds V = [v0, A v0, ..., A^deg v0], W = A V, and solves the normal
-    equations (W^T W) y = W^T v0 with LAPACK POTRF/POTRS.  Returns
-    (y, info): y[k] multiplies A^k in p(A), and info is POTRF's status
-    (info > 0: the Gram matrix is not numerically positive definite; as in the
-    paper the coefficients are still computed, from the partial factor,
-    and may be inaccurate or NaN).
-    """
+def _power_gram(A, v0, deg):
+    """W = [A v0, ..., A^(deg+1) v0]; returns (W^T W, W^T v0)."""
     v0 = np.asarray(v0, dtype=np.float64)
-    V = np.zeros((v0.size, deg + 1), order="F")
-    V[:, 0] = v0
-    for k in range(1, deg + 1):
-        V[:, k] = matvec(A, V[:, k - 1])
-    W = np.column_stack([matvec(A, V[:, k]) for k in range(deg + 1)])
-    G = W.T @ W
-    rhs = W.T @ v0
+    cols = []
+    v = v0
+    for _ in range(deg + 1):
+        v = matvec(A, v)
+        cols.append(v)
+    W = np.column_stack(cols)
+    return W.T @ W, W.T @ v0
+
+
+def _cholesky_solve(G, rhs):
+    """Solve G y = rhs by LAPACK POTRF/POTRS; on POTRF failure at column k (info = k)
+    solve with the leading (k-1) x (k-1) block and set the other coefficients to 0."""
     c, info = scipy.linalg.lapack.dpotrf(G, lower=0)
     if info < 0:
         raise ValueError("dpotrf argument error")
-    y, info2 = scipy.linalg.lapack.dpotrs(c, rhs, lower=0)
+    k = G.shape[0] if info == 0 else info - 1
+    y = np.zeros(G.shape[0])
+    if k > 0:
+        ck, info_k = scipy.linalg.lapack.dpotrf(G[:k, :k], lower=0)
+        y[:k], _ = scipy.linalg.lapack.dpotrs(ck, rhs[:k], lower=0)
     return y, int(info)
+
+
+def power_basis_poly(A, v0, deg):
+    """The paper's construction (Section II, eqs. (1)-(2)).
+
+    Builds V = [v0, A v0, ..., A^deg v0] and W = A V, and solves the normal
+    equations (W^T W) y = W^T v0 with LAPACK POTRF/POTRS.  Returns (y, info):
+    y[k] multiplies A^k in p(A) (degree deg), and info is POTRF's status.
+    When POTRF reports that the Gram matrix is not numerically positive definite
+    at column k (info = k > 0), the coefficients are still returned, as in the
+    paper (Section IV): those of the leading (k-1) x (k-1) block, with zeros above
+    -- the plateau of Table I, where the coefficients past the warning degree are
+    negligible (below 1e-200).
+    """
+    G, rhs = _power_gram(A, v0, deg)
+    return _cholesky_solve(G, rhs)
+
+
+def auto_degree(A, v0, deg_max):
+    """Section IV's heuristic: the highest degree whose Gram matrix factors without a
+    POTRF warning.  The Gram matrices of degrees 0..deg_max are the leading blocks of
+    the deg_max one; they are factored in increasing order and the scan stops at the
+    first warning.  Returns (deg, y, info) with info the POTRF status of the first
+    degree that warned (0 if none up to deg_max)."""
+    G, rhs = _power_gram(A, v0, deg_max)
+    last_ok, info_fail = 0, 0
+    for k in range(1, deg_max + 2):
+        c, info = scipy.linalg.lapack.dpotrf(G[:k, :k], lower=0)
+        if info != 0:
+            info_fail = int(info)
+            break
+        last_ok = k
+    if last_ok == 0:
+        raise np.linalg.LinAlgError("A v0 = 0: no polynomial")
+    c, _ = scipy.linalg.lapack.dpotrf(G[:last_ok, :last_ok], lower=0)
+    y, _ = scipy.linalg.lapack.dpotrs(c, rhs[:last_ok], lower=0)
+    return last_ok - 1, y, info_fail
+
+
+def apply_power(A, coeffs, v):
+    """y = sum_k coeffs[k] A^k v, the powers formed one after the other (eq. (2))."""
+    v = np.asarray(v)
+    y = coeffs[0] * v
+    pk = v
+    for ck in coeffs[1:]:
+        pk = matvec(A, pk)
+        y = y + ck * pk
+    return y

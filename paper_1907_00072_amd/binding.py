@@ -19,14 +19,15 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "lib
 
 PP_OK = 0
 PP_ERR_ARG, PP_ERR_HIP, PP_ERR_NOMEM, PP_ERR_EIG, PP_ERR_SINGULAR = -1, -2, -3, -4, -5
-PP_WARN_DEGREE_REDUCED, PP_WARN_NOT_CONVERGED, PP_WARN_NONFINITE = 1, 2, 3
+PP_WARN_DEGREE_REDUCED, PP_WARN_NOT_CONVERGED, PP_WARN_NONFINITE, PP_WARN_CHOLESKY = 1, 2, 3, 4
 PP_F64, PP_F32 = 0, 1
 PP_PREC_F64, PP_PREC_F32_IR = 0, 1
 PP_OP_RESIDUAL_POLY, PP_OP_PRODUCT = 0, 1
 
 EXPORTS = ("pp_build_poly", "pp_apply", "pp_gmres_solve", "pp_poly_roots", "pp_poly_from_roots",
            "pp_poly_free", "pp_roots_from_hessenberg", "pp_csr_transpose", "pp_csr_grad",
-           "pp_release_workspace", "pp_status_string", "pp_version")
+           "pp_release_workspace", "pp_status_string", "pp_version", "pp_build_poly_power",
+           "pp_poly_coeffs")
 
 
 class pp_csr(ctypes.Structure):
@@ -71,6 +72,8 @@ def lib():
                         ctypes.c_void_p)
     CSRP = P(pp_csr)
     L.pp_build_poly.argtypes = [CSRP, VP, I, VP, P(VP)]
+    L.pp_build_poly_power.argtypes = [CSRP, VP, I, I, VP, P(VP), P(I)]
+    L.pp_poly_coeffs.argtypes = [VP, P(D), I, P(I)]
     L.pp_apply.argtypes = [CSRP, VP, VP, VP, VP]
     L.pp_gmres_solve.argtypes = [CSRP, VP, VP, I, I, D, P(pp_opts), VP, P(pp_stats)]
     L.pp_poly_roots.argtypes = [VP, P(D), P(D), I, P(I)]
@@ -86,7 +89,8 @@ def lib():
     L.pp_status_string.restype = ctypes.c_char_p
     L.pp_version.argtypes = []
     L.pp_version.restype = ctypes.c_char_p
-    for name in ("pp_build_poly", "pp_apply", "pp_gmres_solve", "pp_poly_roots",
+    for name in ("pp_build_poly", "pp_build_poly_power", "pp_poly_coeffs", "pp_apply",
+                 "pp_gmres_solve", "pp_poly_roots",
                  "pp_poly_from_roots", "pp_roots_from_hessenberg", "pp_csr_transpose",
                  "pp_csr_grad"):
         getattr(L, name).restype = ctypes.c_int
@@ -241,6 +245,26 @@ def pp_build_poly(A: CSRMatrix, v0, d: int, stream=None) -> Poly:
     _check(lib().pp_build_poly(ctypes.byref(A.c()), _ptr(v0), int(d), _stream(stream),
                                ctypes.byref(h)), "pp_build_poly")
     return Poly(h, A.n)
+
+
+def pp_build_poly_power(A: CSRMatrix, v0, deg: int, auto_degree: bool = False, stream=None):
+    """The paper's power-basis polynomial; returns (Poly, info) with info = POTRF's status."""
+    torch = _torch()
+    _dev_vec(v0, torch.float64, A.n, "v0")
+    h = ctypes.c_void_p()
+    info = ctypes.c_int()
+    _check(lib().pp_build_poly_power(ctypes.byref(A.c()), _ptr(v0), int(deg),
+                                     1 if auto_degree else 0, _stream(stream), ctypes.byref(h),
+                                     ctypes.byref(info)), "pp_build_poly_power")
+    return Poly(h, A.n), info.value
+
+
+def pp_poly_coeffs(poly: Poly) -> np.ndarray:
+    c = np.zeros(64)
+    k = ctypes.c_int()
+    _check(lib().pp_poly_coeffs(poly.handle, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 64,
+                                ctypes.byref(k)), "pp_poly_coeffs")
+    return c[: k.value].copy()
 
 
 def pp_apply(A: CSRMatrix, poly: Poly, v, y=None, stream=None):

@@ -300,4 +300,35 @@ int step_table(const std::vector<double> &re, const std::vector<double> &im,
   return 0;
 }
 
+int cholesky_upper(const double *G, int ldg, int k, std::vector<double> &R) {
+  R.assign((size_t)k * k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    for (int i = 0; i <= j; ++i) {
+      double acc = G[i + (size_t)j * ldg];
+      for (int q = 0; q < i; ++q) acc -= R[q + (size_t)i * k] * R[q + (size_t)j * k];
+      if (i < j) {
+        R[i + (size_t)j * k] = acc / R[i + (size_t)i * k];
+      } else {
+        if (!(acc > 0.0)) return j + 1;
+        R[j + (size_t)j * k] = std::sqrt(acc);
+      }
+    }
+  }
+  return 0;
+}
+
+void cholesky_solve(const std::vector<double> &R, int k, const double *rhs, double *y) {
+  std::vector<double> z(k);
+  for (int i = 0; i < k; ++i) {  // R^T z = rhs
+    double acc = rhs[i];
+    for (int q = 0; q < i; ++q) acc -= R[q + (size_t)i * k] * z[q];
+    z[i] = acc / R[i + (size_t)i * k];
+  }
+  for (int i = k - 1; i >= 0; --i) {  // R y = z
+    double acc = z[i];
+    for (int q = i + 1; q < k; ++q) acc -= R[i + (size_t)q * k] * y[q];
+    y[i] = acc / R[i + (size_t)i * k];
+  }
+}
+
 }  // namespace ppn

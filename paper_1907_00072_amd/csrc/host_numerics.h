@@ -36,4 +36,13 @@ int leja_order(const std::vector<double> &wr, const std::vector<double> &wi,
 int step_table(const std::vector<double> &re, const std::vector<double> &im,
                std::vector<Step> &steps);
 
+// Cholesky factor R (upper, k x k, column-major) of the leading k x k block of the
+// symmetric matrix G (column-major, leading dimension ldg), column by column.
+// Returns 0, or the 1-based column of the first pivot that is not positive
+// (LAPACK POTRF's `info`), in which case R is unspecified.
+int cholesky_upper(const double *G, int ldg, int k, std::vector<double> &R);
+
+// Solve R^T R y = rhs (R from cholesky_upper, k x k).
+void cholesky_solve(const std::vector<double> &R, int k, const double *rhs, double *y);
+
 }  // namespace ppn

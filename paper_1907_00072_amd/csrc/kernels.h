@@ -34,6 +34,8 @@ struct Csr {
 //  kind 3 (real root): p' = p - c1*A p
 //  kind 2 with `last`: as above, then out = ys*y_in - p'
 //  kind 3 with `last`: out = ys*y_in - p'   (y_in is the chain's input vector v)
+// Power-basis (Horner) form:
+//  kind 4: out = c2*gs*A g + c1*ss*self   (one Horner step z <- A z + y_k v)
 // g is the gathered vector (p for kinds 0/1/3, t for kind 2), self is p for kind 2.
 template <typename T>
 struct ChainArgs {

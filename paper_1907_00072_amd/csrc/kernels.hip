@@ -121,6 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
   const bool live = t < nrows;
   constexpr bool kReadY = (KIND == 0) || (KIND == 1) || (KIND == 2 && (FOLD || LAST)) ||
                           (KIND == 3 && LAST);
+  constexpr bool kReadSelf = (KIND == 2) || (KIND == 4);
   // own-row operands first, so their latency overlaps the product
   int rb = 0, re = 0;
   T own = T(0), yv = T(0), sf = T(0);
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
     re = A.rp[i + 1];
     own = a.g[i];
     if (kReadY) yv = a.y_in ? ldnt(a.y_in + i) : T(0);
-    if (KIND == 2) sf = ldnt(a.self + i);
+    if (kReadSelf) sf = ldnt(a.self + i);
   }
   const T gs = a.gscale ? (T)(*a.gscale) : T(1);
   const T acc = tile_row_sum(A, a.g, r0, nrows, rb, re, s_buf);
@@ -162,6 +163,9 @@ __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
     } else {
       stnt(pn, a.out + i);
     }
+  } else if constexpr (KIND == 4) {
+    const T ss = a.sscale ? (T)(*a.sscale) : T(1);
+    stnt(c2 * (gs * acc) + c1 * (ss * sf), a.out + i);
   } else {
     const T pn = gs * own - c1 * (gs * acc);
     if constexpr (LAST) {
@@ -559,6 +563,9 @@ hipError_t launch_chain(const Csr<T> &A, int kind, bool fold, bool last, const C
       break;
     case 3:
       if (last) PP_CHAIN(3, false, true); else PP_CHAIN(3, false, false);
+      break;
+    case 4:
+      PP_CHAIN(4, false, false);
       break;
     default:
       return hipErrorInvalidValue;

@@ -27,8 +27,11 @@
 struct pp_poly {
   int64_t n;
   int dtype;
-  std::vector<double> re, im;
-  std::vector<ppn::Step> steps;
+  int kind = 0;                 // 0: Leja-ordered roots; 1: power-basis coefficients
+  std::vector<double> re, im;   // kind 0
+  std::vector<ppn::Step> steps; // kind 0
+  std::vector<double> coeffs;   // kind 1: p(A) = sum_k coeffs[k] A^k
+  int info = 0;                 // kind 1: POTRF status of the Gram matrix
 };
 
 namespace {
@@ -203,6 +206,22 @@ double now_s() {
 
 inline bool finite(double v) { return std::isfinite(v); }
 
+// The polynomial a solve applies: none, Leja-ordered roots, or power coefficients.
+struct PolyRef {
+  const std::vector<ppn::Step> *steps = nullptr;
+  const std::vector<double> *coeffs = nullptr;
+  bool active() const {
+    return (steps && !steps->empty()) || (coeffs && !coeffs->empty());
+  }
+  bool power() const { return coeffs && !coeffs->empty(); }
+  static PolyRef of(const pp_poly *p) {
+    PolyRef r;
+    if (p && p->kind == 1) r.coeffs = &p->coeffs;
+    else if (p) r.steps = &p->steps;
+    return r;
+  }
+};
+
 // ------------------------------------------------------------------ chain
 // Algorithmic HBM bytes of one sparse-product launch: the matrix (values,
 // column indices, row pointers) and the gathered vector once, plus `vec_rw`
@@ -269,6 +288,38 @@ int run_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
       cs = nullptr;
       pb ^= 1;
     }
+  }
+  return PP_OK;
+}
+
+// out = p(A) (gscale * g) for p(A) = sum_k c[k] A^k by Horner's rule,
+// z <- A z + c[k] v from the top coefficient down: deg fused product + axpy
+// launches (one axpy launch for a constant polynomial).
+template <typename T>
+int run_horner(const Csr<T> &A, const std::vector<double> &c, const T *g, const double *gscale,
+               T *out, T *P0, T *P1, hipStream_t s, Counters *cnt, double *bytes = nullptr,
+               int64_t *launches = nullptr) {
+  const int deg = (int)c.size() - 1;
+  if (deg < 0) return PP_ERR_ARG;
+  if (deg == 0) {
+    PP_TRY_HIP(ppk::launch_axpy<T>(A.n, c[0], g, gscale, nullptr, out, s));
+    return PP_OK;
+  }
+  T *bufs[2] = {P0, P1};
+  int pb = 0;
+  const T *z = g;
+  const double *zs = gscale;
+  for (int k = deg - 1; k >= 0; --k) {
+    T *dst = (k == 0) ? out : bufs[pb];
+    ppk::ChainArgs<T> a{z, zs, g, gscale, dst, nullptr, nullptr, c[k],
+                        k == deg - 1 ? c[deg] : 1.0, 0.0, nullptr};
+    PP_TRY_HIP(ppk::launch_chain<T>(A, 4, false, false, a, s));
+    if (bytes) *bytes += product_bytes(A, 2);
+    if (launches) ++*launches;
+    if (cnt) cnt->spmvs++;
+    z = dst;
+    zs = nullptr;
+    pb ^= 1;
   }
   return PP_OK;
 }
@@ -342,21 +393,24 @@ int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s) {
 // hcol[0..j+1] receives column j of Hbar; *w0 an estimate of ||Op(V_j)||.
 // Returns PP_OK, or PP_WARN_NONFINITE when a coefficient is not finite.
 template <typename T>
-int arnoldi_step(const Csr<T> &A, const std::vector<ppn::Step> *steps, int op_form, Work<T> &w,
-                 int j, hipStream_t s, Timers &tm, Counters &cnt, double *hcol, double *w0) {
+int arnoldi_step(const Csr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int j,
+                 hipStream_t s, Timers &tm, Counters &cnt, double *hcol, double *w0) {
   const T *vj = w.V + (int64_t)j * w.ldv;
   const double *sj = w.colscale + j;
   const double t_wall0 = tm.on ? now_s() : 0.0;
   tm.mark(0, s);
-  const bool poly = steps && !steps->empty();
-  if (poly && op_form == PP_OP_RESIDUAL_POLY) {
-    PP_TRY(run_op_chain<T>(A, *steps, vj, sj, w.W, w.P0, w.P1, w.Tb, s, &cnt, &cnt.bytes_chain,
-                           &cnt.launches_chain));
+  if (pr.active() && !pr.power() && op_form == PP_OP_RESIDUAL_POLY) {
+    PP_TRY(run_op_chain<T>(A, *pr.steps, vj, sj, w.W, w.P0, w.P1, w.Tb, s, &cnt,
+                           &cnt.bytes_chain, &cnt.launches_chain));
     tm.mark(1, s);
   } else {
-    if (poly) {
-      PP_TRY(run_chain<T>(A, *steps, vj, sj, nullptr, w.Z, w.P0, w.P1, w.Tb, s, &cnt,
-                          &cnt.bytes_chain, &cnt.launches_chain));
+    if (pr.active()) {
+      if (pr.power())
+        PP_TRY(run_horner<T>(A, *pr.coeffs, vj, sj, w.Z, w.P0, w.P1, s, &cnt, &cnt.bytes_chain,
+                             &cnt.launches_chain));
+      else
+        PP_TRY(run_chain<T>(A, *pr.steps, vj, sj, nullptr, w.Z, w.P0, w.P1, w.Tb, s, &cnt,
+                            &cnt.bytes_chain, &cnt.launches_chain));
       tm.mark(1, s);
       PP_TRY_HIP(ppk::launch_spmv<T>(A, w.Z, nullptr, w.W, s));
     } else {
@@ -433,7 +487,7 @@ int build_poly_impl(const Csr<T> &A, const double *v0, int d, Work<T> &w, hipStr
   int sdim = d;
   for (int j = 0; j < d; ++j) {
     double w0 = 0.0;
-    int rc = arnoldi_step<T>(A, nullptr, 0, w, j, s, tm, cnt, hcol.data(), &w0);
+    int rc = arnoldi_step<T>(A, PolyRef{}, 0, w, j, s, tm, cnt, hcol.data(), &w0);
     if (rc < 0) return rc;
     if (rc == PP_WARN_NONFINITE) return PP_ERR_SINGULAR;
     for (int i = 0; i <= j + 1; ++i) Hbar[i + (size_t)j * ldh] = hcol[i];
@@ -452,6 +506,71 @@ int build_poly_impl(const Csr<T> &A, const double *v0, int d, Work<T> &w, hipStr
   out->im = li;
   out->steps = steps;
   return sdim < d ? PP_WARN_DEGREE_REDUCED : PP_OK;
+}
+
+// The paper's construction (Section II, eqs. (1)-(2)): V = [v0, A v0, ...,
+// A^(deg+1) v0] (deg+1 products, columns left unnormalised as the power basis
+// is), the Gram matrix W^T W and right-hand side W^T v0 of W = A V(:, 0..deg)
+// from one multi-dot per column, then a host Cholesky.  With auto_degree the
+// leading blocks are factored in increasing order and the highest degree
+// without a Cholesky failure is kept (Section IV); otherwise a failure at column
+// k keeps the solution of the leading (k-1) block, zeros above, and warns.
+template <typename T>
+int build_power_impl(const Csr<T> &A, const double *v0, int deg, bool auto_deg, Work<T> &w,
+                     double *gram, hipStream_t s, Counters &cnt, pp_poly *out, int *info_out) {
+  const int L = deg + 2;
+  PP_TRY_HIP(ppk::launch_copy_from_f64<T>(w.n, v0, w.V, s));
+  for (int k = 1; k < L; ++k) {
+    PP_TRY_HIP(ppk::launch_spmv<T>(A, w.V + (int64_t)(k - 1) * w.ldv, nullptr,
+                                   w.V + (int64_t)k * w.ldv, s));
+    cnt.spmvs++;
+  }
+  for (int j = 1; j < L; ++j) {
+    PP_TRY(dots_any<T>(w, j + 1, w.V + (int64_t)j * w.ldv, s));
+    PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, w.G, 0, j + 1, nullptr, gram + (size_t)j * L,
+                                       nullptr, s));
+  }
+  cnt.dots += 2;  // the paper's two block inner products
+  std::vector<double> g((size_t)L * L);
+  PP_TRY_HIP(hipMemcpyAsync(g.data(), gram, g.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  // G(a, b) = V(:, a+1) . V(:, b+1), rhs(a) = V(:, a+1) . V(:, 0), a, b = 0..deg
+  const int K = deg + 1;
+  std::vector<double> G((size_t)K * K), rhs(K);
+  for (int b = 0; b < K; ++b) {
+    rhs[b] = g[(size_t)(b + 1) * L];
+    for (int a = 0; a <= b; ++a) {
+      G[a + (size_t)b * K] = G[b + (size_t)a * K] = g[(a + 1) + (size_t)(b + 1) * L];
+    }
+  }
+  for (double v : G)
+    if (!finite(v)) return PP_ERR_SINGULAR;
+  std::vector<double> R;
+  int keep = K, info = 0;
+  if (auto_deg) {
+    keep = 0;
+    for (int k = 1; k <= K; ++k) {
+      const int rc = ppn::cholesky_upper(G.data(), K, k, R);
+      if (rc) {
+        info = rc;
+        break;
+      }
+      keep = k;
+    }
+  } else {
+    info = ppn::cholesky_upper(G.data(), K, K, R);
+    if (info) keep = info - 1;
+  }
+  if (keep == 0) return PP_ERR_SINGULAR;
+  PP_TRY(ppn::cholesky_upper(G.data(), K, keep, R) ? PP_ERR_SINGULAR : PP_OK);
+  out->kind = 1;
+  out->n = A.n;
+  out->coeffs.assign(auto_deg ? keep : K, 0.0);
+  ppn::cholesky_solve(R, keep, rhs.data(), out->coeffs.data());
+  out->info = info;
+  if (info_out) *info_out = info;
+  return (!auto_deg && info) ? PP_WARN_CHOLESKY : PP_OK;
 }
 
 // Givens least squares state of one cycle.
@@ -494,8 +613,7 @@ struct Lsq {
 // One GMRES(m) cycle from V(:,0) (colscale[0] set) with start residual norm beta.
 // Returns steps taken in *k and the solution coefficients in y.
 template <typename T>
-int gmres_cycle(const Csr<T> &A, const std::vector<ppn::Step> *steps, int op_form, Work<T> &w,
-                int m,
+int gmres_cycle(const Csr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int m,
                 double beta, double tol_abs, double bscale, int max_steps, hipStream_t s,
                 Timers &tm, Counters &cnt, std::vector<double> &y, int *k, double *res,
                 bool *nonfinite) {
@@ -508,7 +626,7 @@ int gmres_cycle(const Csr<T> &A, const std::vector<ppn::Step> *steps, int op_for
   const int jmax = std::min(m, max_steps);
   for (int j = 0; j < jmax; ++j) {
     double w0 = 0.0;
-    int rc = arnoldi_step<T>(A, steps, op_form, w, j, s, tm, cnt, hcol.data(), &w0);
+    int rc = arnoldi_step<T>(A, pr, op_form, w, j, s, tm, cnt, hcol.data(), &w0);
     if (rc < 0) return rc;
     cnt.iters++;
     if (rc == PP_WARN_NONFINITE) {
@@ -536,14 +654,14 @@ int gmres_cycle(const Csr<T> &A, const std::vector<ppn::Step> *steps, int op_for
 
 // x_out = x_in + p(A) V(:,0..k) (colscale o y)   [x_in may equal x_out, or be nullptr]
 template <typename T>
-int cycle_update(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &w, int k,
+int cycle_update(const Csr<T> &A, const PolyRef &pr, Work<T> &w, int k,
                  const std::vector<double> &y, const T *x_in, T *x_out, hipStream_t s,
                  Counters &cnt) {
   if (k <= 0) return PP_OK;
   std::memcpy(w.host + 2 * w.L + 8, y.data(), k * sizeof(double));
   PP_TRY_HIP(hipMemcpyAsync(w.ybuf, w.host + 2 * w.L + 8, k * sizeof(double),
                             hipMemcpyHostToDevice, s));
-  const bool poly = steps && !steps->empty();
+  const bool poly = pr.active();
   for (int c0 = 0; c0 < k; c0 += ppk::kMaxCols) {
     const int cc = std::min(ppk::kMaxCols, k - c0);
     T *dst = poly ? w.U : x_out;
@@ -552,7 +670,12 @@ int cycle_update(const Csr<T> &A, const std::vector<ppn::Step> *steps, Work<T> &
                                      w.colscale + c0, -1.0, src, dst, false, false, w.partial,
                                      s));
   }
-  if (poly) PP_TRY(run_chain<T>(A, *steps, w.U, nullptr, x_in, x_out, w.P0, w.P1, w.Tb, s, &cnt));
+  if (poly && pr.power()) {
+    PP_TRY(run_horner<T>(A, *pr.coeffs, w.U, nullptr, w.Z, w.P0, w.P1, s, &cnt));
+    PP_TRY_HIP(ppk::launch_axpy<T>(A.n, 1.0, w.Z, nullptr, x_in, x_out, s));
+  } else if (poly) {
+    PP_TRY(run_chain<T>(A, *pr.steps, w.U, nullptr, x_in, x_out, w.P0, w.P1, w.Tb, s, &cnt));
+  }
   // the host staging of y must not be reused before the copy has run
   PP_TRY_HIP(hipStreamSynchronize(s));
   return PP_OK;
@@ -585,7 +708,9 @@ int apply_impl(const pp_csr *A, const pp_poly *p, const void *v, void *y, hipStr
   const Csr<T> M = view<T>(A, A->vals);
   const T *vv = static_cast<const T *>(v);
   T *yy = static_cast<T *>(y);
-  if (p->steps.empty()) {
+  if (p->kind == 1) {
+    PP_TRY(run_horner<T>(M, p->coeffs, vv, nullptr, yy, bufs[0], bufs[1], s, nullptr));
+  } else if (p->steps.empty()) {
     PP_TRY_HIP(ppk::launch_fill<T>(n, T(0), yy, s));
   } else {
     PP_TRY(run_chain<T>(M, p->steps, vv, nullptr, nullptr, yy, bufs[0], bufs[1], bufs[2], s,
@@ -630,6 +755,11 @@ struct SolveIn {
   pp_opts o;
   hipStream_t s;
 };
+
+// Products with A per application of the preconditioned operator A p(A).
+int poly_size(const pp_poly *p) {
+  return p->kind == 1 ? (int)p->coeffs.size() : (int)p->re.size();
+}
 
 int worst(int a, int b) {
   if (a < 0 || b < 0) return std::min(a, b);
@@ -715,18 +845,18 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
   }
   // the polynomial
   pp_poly built;
-  const std::vector<ppn::Step> *steps = nullptr;
+  PolyRef steps;
   if (in.o.poly) {
-    steps = &in.o.poly->steps;
+    steps = PolyRef::of(in.o.poly);
   } else if (in.d > 0) {
     const double t0 = now_s();
     int rc = build_poly_impl<double>(A, in.o.v0 ? in.o.v0 : in.b, in.d, w, s, cnt, tm, &built);
     if (rc < 0) return rc;
     status = worst(status, rc);
-    steps = &built.steps;
+    steps = PolyRef::of(&built);
     if (st) st->t_poly = now_s() - t0;
   }
-  const int nroots = in.o.poly ? (int)in.o.poly->re.size() : (in.d > 0 ? (int)built.re.size() : 0);
+  const int nroots = in.o.poly ? poly_size(in.o.poly) : (in.d > 0 ? (int)built.re.size() : 0);
   if (st) st->nroots = nroots;
   const int max_iters = in.o.max_iters > 0 ? in.o.max_iters : 100000;
   double beta = 0.0;
@@ -839,19 +969,18 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
     return PP_OK;
   }
   pp_poly built;
-  const std::vector<ppn::Step> *steps = nullptr;
+  PolyRef steps;
   if (in.o.poly) {
-    steps = &in.o.poly->steps;
+    steps = PolyRef::of(in.o.poly);
   } else if (in.d > 0) {
     const double t0 = now_s();
     int rc = build_poly_impl<float>(A32, in.o.v0 ? in.o.v0 : in.b, in.d, w, s, cnt, tm, &built);
     if (rc < 0) return rc;
     status = worst(status, rc);
-    steps = &built.steps;
+    steps = PolyRef::of(&built);
     if (st) st->t_poly = now_s() - t0;
   }
-  if (st)
-    st->nroots = in.o.poly ? (int)in.o.poly->re.size() : (in.d > 0 ? (int)built.re.size() : 0);
+  if (st) st->nroots = in.o.poly ? poly_size(in.o.poly) : (in.d > 0 ? (int)built.re.size() : 0);
   const int max_iters = in.o.max_iters > 0 ? in.o.max_iters : 100000;
   const int max_outer = in.o.max_outer > 0 ? in.o.max_outer : 100;
   const double inner_tol = in.o.inner_tol > 0 ? in.o.inner_tol : 1e-5;
@@ -954,8 +1083,55 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
   return rc;
 }
 
+int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_degree,
+                        void *stream, pp_poly **out, int *info_out) {
+  if (!out || !v0) return PP_ERR_ARG;
+  *out = nullptr;
+  if (info_out) *info_out = 0;
+  PP_TRY(check_csr(A));
+  if (deg < 0 || deg > ppk::kMaxCols - 2 || deg + 1 > A->n) return PP_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_lock);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Arena *ar = nullptr;
+  PP_TRY(current_arena(&ar));
+  const int n = (int)A->n, L = deg + 2;
+  auto go = [&](auto tag) -> int {
+    using T = decltype(tag);
+    Work<T> w;
+    Carver meas(nullptr);
+    w.carve(meas, n, L);
+    meas.take<double>((size_t)L * L);
+    PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
+    Carver c(ar->dev);
+    w.carve(c, n, L);
+    double *gram = c.take<double>((size_t)L * L);
+    w.host = ar->host;
+    Counters cnt;
+    pp_poly *p = new pp_poly();
+    p->dtype = A->dtype;
+    int rc = build_power_impl<T>(view<T>(A, A->vals), v0, deg, auto_degree != 0, w, gram, s, cnt,
+                                 p, info_out);
+    if (rc < 0) {
+      delete p;
+      return rc;
+    }
+    *out = p;
+    return rc;
+  };
+  return A->dtype == PP_F64 ? go(double{}) : go(float{});
+}
+
+int pp_poly_coeffs(const pp_poly *p, double *c, int cap, int *n_out) {
+  if (!p || !n_out || p->kind != 1) return PP_ERR_ARG;
+  const int k = (int)p->coeffs.size();
+  *n_out = k;
+  if (!c || cap < k) return PP_ERR_ARG;
+  for (int i = 0; i < k; ++i) c[i] = p->coeffs[i];
+  return PP_OK;
+}
+
 int pp_poly_roots(const pp_poly *p, double *re, double *im, int cap, int *d_out) {
-  if (!p || !d_out) return PP_ERR_ARG;
+  if (!p || !d_out || p->kind != 0) return PP_ERR_ARG;
   const int d = (int)p->re.size();
   *d_out = d;
   if (d > 0 && (!re || !im || cap < d)) return PP_ERR_ARG;
@@ -1076,6 +1252,8 @@ const char *pp_status_string(int code) {
     case PP_WARN_DEGREE_REDUCED: return "warning: Arnoldi breakdown, polynomial has fewer roots";
     case PP_WARN_NOT_CONVERGED: return "warning: iteration cap reached before tolerance";
     case PP_WARN_NONFINITE: return "warning: non-finite value met, last finite iterate returned";
+    case PP_WARN_CHOLESKY:
+      return "warning: power-basis Gram matrix not positive definite (POTRF info > 0)";
     default: return "unknown status";
   }
 }

@@ -289,3 +289,61 @@ def test_adjoint_gradient_reduced_config4(B):
     fd = oadj.fd_gradient_vals(M, P.b, xt, ents, h=1e-6)
     assert np.max(np.abs(gv[ents] - fd)) <= 1e-6 * np.max(np.abs(gv_ref))
     assert [ph for ph, _ in cfg.stats] == ["forward", "adjoint"]
+
+
+# ---- the paper's power-basis construction (Section II eqs. (1)-(2), Section IV)
+# Coefficient agreement is limited by the conditioning of the Gram matrix
+# (cond 5e2, 2e5, 4e7, 2e12 at degrees 1, 2, 3, 5 on the 64^2 problem): rounding
+# in the Gram entries moves the coefficients by about u * cond.
+@pytest.mark.parametrize("deg,coef_tol", [(1, 1e-10), (2, 1e-9), (3, 1e-8), (5, 1e-6)])
+def test_power_basis_build_and_apply(B, deg, coef_tol):
+    P = W.config(1)
+    As = P.A.to_scipy()
+    A = B.CSRMatrix.from_host(P.A)
+    p, info = B.pp_build_poly_power(A, _up(P.v0), deg)
+    c = B.pp_poly_coeffs(p)
+    ref, info_ref = opoly.power_basis_poly(As, P.v0, deg)
+    assert info == info_ref == 0 and c.size == deg + 1
+    assert np.max(np.abs(c - ref) / np.abs(ref)) <= coef_tol
+    v = W.uniform(P.A.n, 31)
+    y = B.pp_apply(A, p, _up(v)).cpu().numpy()
+    assert _rel(y, opoly.apply_power(As, c, v)) <= 1e-10   # Horner vs explicit powers
+    obj = np.linalg.norm(P.v0 - As @ opoly.apply_power(As, c, P.v0))
+    obj_ref = np.linalg.norm(P.v0 - As @ opoly.apply_power(As, ref, P.v0))
+    assert abs(obj - obj_ref) <= 1e-10 * obj_ref
+
+
+def test_power_basis_auto_degree_bidiag(B):
+    Ac = W.bidiag2()
+    As = Ac.to_scipy()
+    b = As @ np.random.default_rng(1).random(Ac.n)
+    p, info = B.pp_build_poly_power(B.CSRMatrix.from_host(Ac), _up(b), 18, auto_degree=True)
+    deg_ref, y_ref, info_ref = opoly.auto_degree(As, b, 18)
+    c = B.pp_poly_coeffs(p)
+    # the onset sits where the Gram matrix loses definiteness in the last digits, so
+    # the two Gram matrices (different summation orders) may disagree by one degree
+    assert abs((c.size - 1) - deg_ref) <= 1 and abs(info - info_ref) <= 1
+    with pytest.warns(B.PPWarning):
+        p2, info2 = B.pp_build_poly_power(B.CSRMatrix.from_host(Ac), _up(b), 16)
+    c2 = B.pp_poly_coeffs(p2)
+    assert info2 > 0 and np.all(c2[info2 - 1:] == 0)
+
+
+def test_power_basis_solve_parity(B):
+    P = W.config(1)
+    As = P.A.to_scipy()
+    A = B.CSRMatrix.from_host(P.A)
+    p, info = B.pp_build_poly_power(A, _up(P.v0), 5)
+    c = B.pp_poly_coeffs(p)
+    x, st = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=0, tol=P.tol, poly=p)
+    xo, so = ogmres.pp_gmres(As, P.b, P.m, P.tol, coeffs=c, max_iters=3000)
+    assert st.nroots == 6
+    xg = x.cpu().numpy()
+    assert st.relres_true < P.tol and so.converged
+    assert abs(st.iters - so.iters) <= max(1, round(0.02 * so.iters))
+    if st.iters == so.iters:
+        assert _rel(xg, xo) <= 1e-8
+    p0, _ = B.pp_build_poly_power(A, _up(P.v0), 0)
+    v = W.uniform(P.A.n, 32)
+    c0 = B.pp_poly_coeffs(p0)
+    assert np.allclose(B.pp_apply(A, p0, _up(v)).cpu().numpy(), c0[0] * v, rtol=1e-15)

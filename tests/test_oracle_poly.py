@@ -292,3 +292,58 @@ def test_bidiag_definitions(golden_dir):
     assert np.allclose(d2[:9], np.arange(1, 10) / 10) and np.array_equal(d2[9:], np.arange(1, 4992))
     assert np.all(b1.vals[b1.row_ptr[:-2] + 1] == 0.05)
     assert np.all(b2.vals[b2.row_ptr[:-2] + 1] == 0.2)
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 5])
+def test_power_series_apply_equals_root_form(d):
+    """The paper's coefficients applied as sum y_k A^k v equal the Leja product form (d <= 5)."""
+    A = W.convection_diffusion(10, 2, 40.0, (1.0, 1.0)).to_scipy()
+    v0 = W.uniform(A.shape[0], 7)
+    y, info = poly.power_basis_poly(A, v0, d - 1)
+    assert info == 0 and y.size == d
+    roots, _ = poly.build_poly(A, v0, d)
+    v = W.uniform(A.shape[0], 8)
+    ref = poly.apply_poly(A, roots, v)
+    assert np.linalg.norm(poly.apply_power(A, y, v) - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_auto_degree_is_last_degree_without_warning():
+    """Section IV: the highest degree whose Gram matrix factors (onset of warnings at 10-12)."""
+    import scipy.linalg
+    for f in (W.bidiag1, W.bidiag2):
+        Ac = f()
+        A = Ac.to_scipy()
+        b = A @ np.random.default_rng(1).random(Ac.n)
+        deg, y, info = poly.auto_degree(A, b, 18)
+        assert info > 0 and 8 <= deg <= 13 and y.size == deg + 1
+        G, rhs = poly._power_gram(A, b, deg + 1)
+        assert scipy.linalg.lapack.dpotrf(G[: deg + 2, : deg + 2], lower=0)[1] > 0
+        assert scipy.linalg.lapack.dpotrf(G[: deg + 1, : deg + 1], lower=0)[1] == 0
+        # the selected polynomial preconditions: GMRES(50) converges with it
+        from oracle import gmres
+        _, st = gmres.pp_gmres(A, b, 50, 1e-8, coeffs=y, max_iters=3000)
+        assert st.converged
+
+
+def test_warned_degree_keeps_lower_coefficients():
+    """Reading of a POTRF warning: coefficients of the leading factorable block, zeros above
+    (the plateau of Table I)."""
+    Ac = W.bidiag2()
+    A = Ac.to_scipy()
+    b = A @ np.random.default_rng(1).random(Ac.n)
+    y, info = poly.power_basis_poly(A, b, 16)
+    assert info > 0
+    k = info - 1
+    assert np.all(y[k:] == 0) and np.all(np.isfinite(y[:k])) and np.any(y[:k] != 0)
+
+
+def test_power_form_gmres_matches_root_form():
+    from oracle import gmres
+    P = W.config(1)
+    A = P.A.to_scipy()
+    y, info = poly.power_basis_poly(A, P.v0, 5)
+    assert info == 0
+    _, s_pow = gmres.pp_gmres(A, P.b, P.m, P.tol, coeffs=y, max_iters=2000)
+    _, s_root = gmres.pp_gmres(A, P.b, P.m, P.tol, v0=P.v0, d=6, max_iters=2000)
+    assert s_pow.converged and s_root.converged
+    assert abs(s_pow.iters - s_root.iters) <= max(1, round(0.02 * s_root.iters))
