@@ -8,7 +8,7 @@
  * A p(A) y = b, then x = p(A) y.
  *
  * Degree convention.  d = number of roots of the residual polynomial
- * pi(alpha) = 1 - alpha p(alpha); p has degree d-1.  The paper's "deg" is d-1
+ * pi(alpha) = 1 - alpha p(alpha); p has degree d-1.  The paper's degree deg is d-1
  * (its power basis has deg+1 columns and costs deg+1 products, Sections II-III).
  * Applying p costs d-1 sparse products; one preconditioned step A p(A) v costs d.
  *
@@ -109,7 +109,7 @@ typedef struct pp_opts {
                              A p(A) in exact arithmetic (pi(alpha) = 1 - alpha p(alpha)) */
 } pp_opts;
 
-/* Solve statistics (all counts follow Section III: a "dot" is one block inner
+/* Solve statistics (all counts follow Section III: a dot is one block inner
  * product or norm, three per Arnoldi step with CGS2). */
 typedef struct pp_stats {
   int32_t status;          /* same as the return value */
@@ -158,7 +158,7 @@ typedef struct pp_stats {
  * (H_d singular, zero v0, or a zero/non-finite root), PP_ERR_EIG, PP_ERR_HIP, PP_ERR_NOMEM. */
 int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_poly **out);
 
-/* y = p(A) v.  Passage: Section II ("apply p(A) to a given vector").
+/* y = p(A) v.  Passage: Section II (the polynomial object applies p(A) to a vector).
  * Product form in Leja order: for a real root theta, y += prod/theta and
  * prod -= A prod / theta; a pair a +- ib is one real quadratic step with
  * c1 = 2a/|theta|^2, c2 = 1/|theta|^2.  d-1 fused CSR-product + update kernels.

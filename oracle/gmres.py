@@ -11,8 +11,8 @@ Readings taken where the paper is silent:
   early; convergence is decided by the true residual recomputed after the
   cycle's solution update (a cycle that stops on the implicit estimate but
   fails the true test restarts);
-* iterations are counted as Arnoldi steps (Section V counts "2550
-  iterations of GMRES(50)");
+* iterations are counted as Arnoldi steps (Section V counts the iterations
+  of GMRES(50) this way);
 * counters: per Arnoldi step d products with A (d-1 for p, one for A) and 3
   dots; per cycle end d-1 products for the update p(A) u, one for the new
   residual and one norm; the initial residual costs one product and one

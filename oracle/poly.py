@@ -1,7 +1,7 @@
 """Oracle: the GMRES minimum-residual polynomial p(A) (test infrastructure).
 
 Notation.  d = number of roots = degree of phi(alpha) = alpha*p(alpha);
-p itself has degree d-1.  The paper's "deg" is d-1: it builds a power basis
+p itself has degree d-1.  The paper's degree deg is d-1: it builds a power basis
 with deg+1 columns (Section II) and needs deg+1 matrix-vector products to do
 so (Section III).  The residual polynomial is pi(alpha) = 1 - alpha*p(alpha),
 pi(0) = 1, and its zeros are the harmonic Ritz values theta_1..theta_d of A
