@@ -57,7 +57,9 @@ extern "C" {
 #define PP_ERR_EIG (-4)       /* Hessenberg QR iteration did not converge */
 #define PP_ERR_SINGULAR (-5)  /* H_d singular, or a zero / non-finite root */
 #define PP_WARN_DEGREE_REDUCED 1 /* Arnoldi on v0 broke down after s < d steps: s roots */
-#define PP_WARN_NOT_CONVERGED 2  /* iteration cap reached; x is the last iterate */
+#define PP_WARN_NOT_CONVERGED 2  /* iteration cap reached, or the true residual stagnated
+                                    within 100 x tol (the attainable accuracy); x is the
+                                    last iterate */
 #define PP_WARN_NONFINITE 3      /* NaN/Inf met; x is the last finite iterate */
 #define PP_WARN_CHOLESKY 4       /* power basis: Gram matrix not numerically positive definite */
 
@@ -107,6 +109,12 @@ typedef struct pp_opts {
   int32_t timing;         /* nonzero: fill the per-phase times in pp_stats (adds events) */
   int32_t op_form;        /* PP_OP_RESIDUAL_POLY (0) or PP_OP_PRODUCT; the same operator
                              A p(A) in exact arithmetic (pi(alpha) = 1 - alpha p(alpha)) */
+  int32_t left_jacobi;    /* nonzero: compose with a left Jacobi preconditioner (Section II:
+                             the polynomial is built for the preconditioned operator).
+                             GMRES runs on D^-1 A p(D^-1 A) y = D^-1 b, x = p(D^-1 A) y, and
+                             stops on ||D^-1 (b - A x)|| / ||D^-1 b|| < tol; D = diag(A)
+                             (zero or missing diagonal -> PP_ERR_SINGULAR).  The scaled
+                             copy of A's values is made once per call. */
 } pp_opts;
 
 /* Solve statistics (all counts follow Section III: a dot is one block inner
@@ -142,6 +150,8 @@ typedef struct pp_stats {
   double bytes_spmv;
   double bytes_orth;
   int64_t launches_chain;  /* chain launches inside t_chain */
+  double relres_original;  /* ||b - A x|| / ||b|| of the unpreconditioned system (equals
+                              relres_true unless left_jacobi is set) */
 } pp_stats;
 
 /* Build the polynomial for (A, v0) with d roots.
@@ -167,6 +177,9 @@ int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_pol
 int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *stream);
 
 /* Solve A x = b with GMRES(m) right-preconditioned by the d-root polynomial.
+ * Stopping: the true relative residual below tol, the iteration cap, or, once it
+ * is below 100 * tol, three consecutive restart cycles that each fail to reduce
+ * it by 10% (FP64 rounding floor; PP_WARN_NOT_CONVERGED).
  * Passage: Section III (GMRES(m), two-pass classical Gram-Schmidt, relative
  * residual ||b - A x|| / ||b|| < tol, polynomial on the right), Section V
  * (start vector), Section II (the polynomial).  d = 0 runs plain GMRES(m).

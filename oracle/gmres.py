@@ -13,6 +13,9 @@ Readings taken where the paper is silent:
   fails the true test restarts);
 * iterations are counted as Arnoldi steps (Section V counts the iterations
   of GMRES(50) this way);
+* attainable accuracy: once the true relative residual is below 100 * tol,
+  three consecutive cycles that each fail to reduce it by 10% end the solve
+  unconverged (the rounding floor of the true residual has been reached);
 * counters: per Arnoldi step d products with A (d-1 for p, one for A) and 3
   dots; per cycle end d-1 products for the update p(A) u, one for the new
   residual and one norm; the initial residual costs one product and one
@@ -31,7 +34,12 @@ import numpy as np
 
 from .poly import BREAKDOWN_RTOL, apply_poly, apply_power, build_poly, matvec
 
-__all__ = ["GmresStats", "gmres_cycle", "pp_gmres", "pp_gmres_ir", "lsq_residual"]
+STAGNATION_BAND = 100.0    # the stagnation test applies below this multiple of tol
+STAGNATION_FACTOR = 0.9    # a cycle must reduce the true residual at least this much
+STAGNATION_CYCLES = 3      # consecutive failing cycles that end the solve
+
+__all__ = ["GmresStats", "gmres_cycle", "pp_gmres", "pp_gmres_ir", "lsq_residual",
+           "jacobi_left", "pp_gmres_left_jacobi"]
 
 
 @dataclass
@@ -141,7 +149,9 @@ def pp_gmres(A, b, m, tol, roots=None, x0=None, max_iters=100000, v0=None, d=Non
     beta = float(np.linalg.norm(r))
     st.relres_true = beta / st._bnorm
     st.true_history.append(st.relres_true)
-    while st.relres_true >= tol and st.iters < max_iters:
+    stagnant = 0
+    while st.relres_true >= tol and st.iters < max_iters and stagnant < STAGNATION_CYCLES:
+        prev = st.relres_true
         st.cycles += 1
         dx, res = gmres_cycle(A, r, roots, m, tol * st._bnorm, max_iters - st.iters, st,
                               coeffs=coeffs)
@@ -154,6 +164,11 @@ def pp_gmres(A, b, m, tol, roots=None, x0=None, max_iters=100000, v0=None, d=Non
         st.true_history.append(st.relres_true)
         if not np.isfinite(st.relres_true):
             break
+        if (st.relres_true < STAGNATION_BAND * tol
+                and st.relres_true > STAGNATION_FACTOR * prev):
+            stagnant += 1
+        else:
+            stagnant = 0
     st.restarts = max(st.cycles - 1, 0)
     st.converged = bool(st.relres_true < tol)
     return x, st
@@ -207,4 +222,29 @@ def pp_gmres_ir(A, b, m, d, tol, v0, inner_tol=1e-5, max_outer=200, x0=None):
     st.history = inner.history
     st.cycles = st.outer
     st.converged = bool(st.relres_true < tol)
+    return x, st
+
+
+def jacobi_left(A, b):
+    """The left-preconditioned system D^{-1} A x = D^{-1} b with D = diag(A)."""
+    import scipy.sparse as sp
+    d = np.asarray(A.diagonal(), dtype=np.float64)
+    if np.any(d == 0) or not np.all(np.isfinite(d)):
+        raise np.linalg.LinAlgError("zero or non-finite diagonal")
+    Dinv = sp.diags(1.0 / d)
+    return sp.csr_matrix(Dinv @ A), np.asarray(b, dtype=np.float64) / d
+
+
+def pp_gmres_left_jacobi(A, b, m, tol, v0=None, d=None, max_iters=100000):
+    """Polynomial preconditioning composed with a left Jacobi preconditioner.
+
+    Section II: with a preconditioned system M A x = M b the polynomial is built
+    for the operator M A.  Here M = D^{-1}: GMRES(m) runs on D^{-1} A p(D^{-1} A) y
+    = D^{-1} b, x = p(D^{-1} A) y, and stops on the preconditioned relative residual
+    ||D^{-1}(b - A x)|| / ||D^{-1} b|| < tol.  Returns (x, stats) with
+    ``stats.relres_original`` = ||b - A x|| / ||b||.
+    """
+    As, bs = jacobi_left(A, b)
+    x, st = pp_gmres(As, bs, m, tol, v0=v0, d=d, max_iters=max_iters)
+    st.relres_original = float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
     return x, st

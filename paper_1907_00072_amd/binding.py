@@ -40,7 +40,8 @@ class pp_opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("v0", ctypes.c_void_p), ("poly", ctypes.c_void_p), ("vals_f32", ctypes.c_void_p),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("op_form", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("op_form", ctypes.c_int32),
+                ("left_jacobi", ctypes.c_int32)]
 
 
 class pp_stats(ctypes.Structure):
@@ -53,7 +54,7 @@ class pp_stats(ctypes.Structure):
                 ("t_spmv", ctypes.c_double), ("t_orth", ctypes.c_double),
                 ("t_host", ctypes.c_double), ("bytes_chain", ctypes.c_double),
                 ("bytes_spmv", ctypes.c_double), ("bytes_orth", ctypes.c_double),
-                ("launches_chain", ctypes.c_int64)]
+                ("launches_chain", ctypes.c_int64), ("relres_original", ctypes.c_double)]
 
 
 _lib = None
@@ -298,6 +299,7 @@ class Stats:
     bytes_spmv: float = 0.0
     bytes_orth: float = 0.0
     launches_chain: int = 0
+    relres_original: float = float("nan")
     history: Optional[np.ndarray] = None
 
 
@@ -305,7 +307,7 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
                    v0=None, poly: Optional[Poly] = None, precision: str = "f64",
                    max_iters: int = 0, inner_tol: float = 0.0, max_outer: int = 0,
                    vals_f32=None, history: int = 0, timing: bool = False, op_form: str = "pi",
-                   stream=None):
+                   left_jacobi: bool = False, stream=None):
     """Solve A x = b; returns (x, Stats).  ``x`` (if given) is the start guess and is overwritten.
 
     ``op_form``: "pi" applies A p(A) v as v - pi(A) v (default), "p" as A (p(A) v).
@@ -335,6 +337,7 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
         o.history_cap = int(history)
     o.timing = 1 if timing else 0
     o.op_form = {"pi": PP_OP_RESIDUAL_POLY, "p": PP_OP_PRODUCT}[op_form]
+    o.left_jacobi = 1 if left_jacobi else 0
     st = pp_stats()
     rc = lib().pp_gmres_solve(ctypes.byref(A.c()), _ptr(b), _ptr(x), int(m), int(d), float(tol),
                               ctypes.byref(o), _stream(stream), ctypes.byref(st))
@@ -342,7 +345,8 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
     s = Stats(st.status, st.iters, st.cycles, st.outer, st.nroots, st.spmvs, st.dots,
               st.relres_true, st.relres_implicit, st.t_total, st.t_poly, st.t_chain, st.t_spmv,
               st.t_orth, st.t_host, st.bytes_chain, st.bytes_spmv, st.bytes_orth,
-              st.launches_chain, hist[: st.history_len].copy() if hist is not None else None)
+              st.launches_chain, st.relres_original,
+              hist[: st.history_len].copy() if hist is not None else None)
     return x, s
 
 

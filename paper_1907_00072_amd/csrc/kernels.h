@@ -134,4 +134,11 @@ hipError_t launch_sort_rows(int n, const int32_t *rp, int32_t *ci, T *va, hipStr
 hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const double *lam,
                            const double *x, double *g, hipStream_t stream);
 
+// Left Jacobi scaling: va_out[k] = va[k] / a_ii and b_out[i] = b[i] / a_ii for the
+// row i of entry k (a_ii the sum of the row's diagonal entries); *bad is set to 1
+// when a row has a zero or missing diagonal.
+hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, const double *va,
+                               const double *b, double *va_out, double *b_out, int32_t *bad,
+                               hipStream_t stream);
+
 }  // namespace ppk

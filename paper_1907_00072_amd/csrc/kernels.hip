@@ -45,7 +45,7 @@ struct LdsCap<double> {
 };
 template <>
 struct LdsCap<float> {
-  static constexpr int value = 4096;
+  static constexpr int value = 2048;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -532,6 +532,28 @@ __global__ __launch_bounds__(kBlock) void k_csr_grad(int n, const int32_t *__res
   for (int k = rp[i]; k < rp[i + 1]; ++k) g[k] = -li * x[ci[k]];
 }
 
+__global__ __launch_bounds__(kBlock) void k_jacobi_scale(int n, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci,
+                                                         const double *__restrict__ va,
+                                                         const double *__restrict__ b,
+                                                         double *__restrict__ va_out,
+                                                         double *__restrict__ b_out,
+                                                         int32_t *bad) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int lo = rp[i], hi = rp[i + 1];
+  double dg = 0.0;
+  for (int k = lo; k < hi; ++k)
+    if (ci[k] == i) dg += va[k];
+  if (dg == 0.0 || !isfinite(dg)) {
+    *bad = 1;
+    dg = 1.0;
+  }
+  const double inv = 1.0 / dg;
+  for (int k = lo; k < hi; ++k) va_out[k] = va[k] * inv;
+  b_out[i] = b[i] * inv;
+}
+
 inline int tiles_of(int n) { return (n + kBlock - 1) / kBlock; }
 inline unsigned blocks_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -759,6 +781,14 @@ hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const do
                            const double *x, double *g, hipStream_t stream) {
   hipLaunchKernelGGL(k_csr_grad, dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, rp, ci, lam, x,
                      g);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, const double *va,
+                               const double *b, double *va_out, double *b_out, int32_t *bad,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(k_jacobi_scale, dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, rp, ci, va, b,
+                     va_out, b_out, bad);
   return hipGetLastError();
 }
 

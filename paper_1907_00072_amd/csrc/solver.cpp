@@ -41,6 +41,12 @@ using ppk::Csr;
 constexpr int kMaxM = 256;
 constexpr int kMaxD = 256;
 constexpr double kBreakdownRtol = 1e-12;
+// Attainable accuracy: below kStagnationBand * tol, kStagnationCycles consecutive
+// restart cycles that each leave the true residual above kStagnationFactor times
+// its previous value end the solve (PP_WARN_NOT_CONVERGED).
+constexpr double kStagnationBand = 100.0;
+constexpr double kStagnationFactor = 0.9;
+constexpr int kStagnationCycles = 3;
 
 #define PP_TRY_HIP(expr)                              \
   do {                                                \
@@ -58,6 +64,8 @@ std::mutex g_lock;
 struct Arena {
   char *dev = nullptr;
   size_t dev_cap = 0;
+  char *aux = nullptr;  // composed operator (scaled copy of A, scaled b); outlives `dev` carving
+  size_t aux_cap = 0;
   double *host = nullptr;  // pinned
   size_t host_cap = 0;     // in doubles
 };
@@ -96,6 +104,22 @@ int ensure_arena(Arena *a, size_t dev_bytes, size_t host_doubles) {
     }
     a->host_cap = host_doubles;
   }
+  return PP_OK;
+}
+
+int ensure_aux(Arena *a, size_t bytes) {
+  if (bytes <= a->aux_cap) return PP_OK;
+  if (a->aux) {
+    if (hipDeviceSynchronize() != hipSuccess) return PP_ERR_HIP;
+    (void)hipFree(a->aux);
+    a->aux = nullptr;
+    a->aux_cap = 0;
+  }
+  if (hipMalloc((void **)&a->aux, bytes) != hipSuccess) {
+    a->aux = nullptr;
+    return PP_ERR_NOMEM;
+  }
+  a->aux_cap = bytes;
   return PP_OK;
 }
 
@@ -870,7 +894,9 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
     finish(relres, relres, 0);
     return worst(status, PP_WARN_NONFINITE);
   }
-  while (relres >= in.tol && cnt.iters < max_iters) {
+  int stagnant = 0;
+  while (relres >= in.tol && cnt.iters < max_iters && stagnant < kStagnationCycles) {
+    const double prev = relres;
     ++cycles;
     PP_TRY_HIP(hipMemcpyAsync(xsave, in.x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     int k = 0;
@@ -896,6 +922,9 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
     }
     beta = nb;
     relres = beta / bnorm;
+    stagnant = (relres < kStagnationBand * in.tol && relres > kStagnationFactor * prev)
+                   ? stagnant + 1
+                   : 0;
   }
   if (status != PP_WARN_NONFINITE && relres >= in.tol) status = worst(status, PP_WARN_NOT_CONVERGED);
   finish(relres, relimp, cycles);
@@ -1069,6 +1098,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
   if (!b || !x || m < 1 || m > kMaxM || !(tol > 0) || d < 0 || d > kMaxD || A->dtype != PP_F64)
     return PP_ERR_ARG;
   SolveIn in{A, b, x, m, d, tol, pp_opts{}, static_cast<hipStream_t>(stream)};
+  pp_csr scaled;
   if (opt) in.o = *opt;
   if (in.o.precision != PP_PREC_F64 && in.o.precision != PP_PREC_F32_IR) return PP_ERR_ARG;
   if (in.o.op_form != PP_OP_RESIDUAL_POLY && in.o.op_form != PP_OP_PRODUCT) return PP_ERR_ARG;
@@ -1078,8 +1108,54 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
     return PP_ERR_ARG;
   }
   std::lock_guard<std::mutex> lk(g_lock);
+  Arena *ar = nullptr;
+  if (in.o.left_jacobi) {
+    // Section II composition: run the unchanged solver on (D^-1 A, D^-1 b).
+    if (in.o.vals_f32) return PP_ERR_ARG;
+    PP_TRY(current_arena(&ar));
+    const int64_t n = A->n, nnz = A->nnz;
+    Carver meas(nullptr);
+    meas.take<double>(nnz > 0 ? nnz : 1);
+    meas.take<double>(n);
+    meas.take<int32_t>(64);
+    PP_TRY(ensure_aux(ar, meas.off + 256));
+    Carver c(ar->aux);
+    double *va = c.take<double>(nnz > 0 ? nnz : 1);
+    double *bs = c.take<double>(n);
+    int32_t *bad = c.take<int32_t>(64);
+    hipStream_t s = in.s;
+    PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, bad, s));
+    PP_TRY_HIP(ppk::launch_jacobi_scale((int)n, A->row_ptr, A->col_ind,
+                                        static_cast<const double *>(A->vals), b, va, bs, bad, s));
+    int32_t hbad = 0;
+    PP_TRY_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PP_TRY_HIP(hipStreamSynchronize(s));
+    if (hbad) return PP_ERR_SINGULAR;
+    scaled = *A;
+    scaled.vals = va;
+    in.A = &scaled;
+    in.b = bs;
+  }
   int rc = in.o.precision == PP_PREC_F64 ? solve_f64(in, st) : solve_f32_ir(in, st);
-  if (st) st->status = rc;
+  if (st) {
+    st->status = rc;
+    st->relres_original = st->relres_true;
+  }
+  if (in.o.left_jacobi && rc >= 0 && st) {
+    // ||b - A x|| / ||b|| of the original system, in the (re-carved) main arena
+    const int n = (int)A->n;
+    Work<double> w;
+    Carver meas(nullptr);
+    w.carve(meas, n, 1);
+    PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
+    Carver c(ar->dev);
+    w.carve(c, n, 1);
+    w.host = ar->host;
+    double bn = 0.0, rn = 0.0;
+    PP_TRY(norm_f64(w, b, in.s, &bn));
+    PP_TRY(residual_f64(view<double>(A, A->vals), w, b, x, in.s, &rn));
+    st->relres_original = bn > 0 ? rn / bn : 0.0;
+  }
   return rc;
 }
 
@@ -1235,6 +1311,7 @@ void pp_release_workspace(void) {
     (void)hipSetDevice((int)dev);
     (void)hipDeviceSynchronize();
     if (a.dev) (void)hipFree(a.dev);
+    if (a.aux) (void)hipFree(a.aux);
     if (a.host) (void)hipHostFree(a.host);
     a = Arena{};
   }

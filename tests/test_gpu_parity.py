@@ -347,3 +347,42 @@ def test_power_basis_solve_parity(B):
     v = W.uniform(P.A.n, 32)
     c0 = B.pp_poly_coeffs(p0)
     assert np.allclose(B.pp_apply(A, p0, _up(v)).cpu().numpy(), c0[0] * v, rtol=1e-15)
+
+
+# ---- composition with a left Jacobi preconditioner (Section II: polynomial of M A)
+def _varied_diagonal_matrix(n, seed):
+    Ah = W.random_csr(n, 8, seed=seed, diag_shift=0.0)
+    A = Ah.to_scipy()
+    dg = np.random.default_rng(seed + 1).uniform(2.0, 400.0, n)
+    A = sp.csr_matrix(A + sp.diags(dg - A.diagonal()))
+    A.sort_indices()
+    return A
+
+
+def test_left_jacobi_composition_parity(B):
+    A = _varied_diagonal_matrix(777, 60)
+    b = W.normal(777, 61)
+    v0 = W.uniform(777, 62)
+    Ad = B.CSRMatrix.from_host(A)
+    x, st = B.pp_gmres_solve(Ad, _up(b), m=20, d=6, tol=1e-10, v0=_up(v0), left_jacobi=True)
+    xo, so = ogmres.pp_gmres_left_jacobi(A, b, 20, 1e-10, v0=v0, d=6, max_iters=2000)
+    xg = x.cpu().numpy()
+    assert st.relres_true < 1e-10 and so.converged
+    assert abs(st.iters - so.iters) <= max(1, round(0.02 * so.iters))
+    if st.iters == so.iters:
+        assert _rel(xg, xo) <= 1e-8
+    assert abs(st.relres_original - so.relres_original) <= 1e-3 * so.relres_original + 1e-15
+    # without the row scaling the same problem needs more iterations
+    _, s0 = B.pp_gmres_solve(Ad, _up(b), m=20, d=6, tol=1e-10, v0=_up(v0), max_iters=2000)
+    assert st.iters < s0.iters
+
+
+def test_left_jacobi_rejects_zero_diagonal(B):
+    A = _varied_diagonal_matrix(300, 63).tolil()
+    A[5, 5] = 0.0
+    A = sp.csr_matrix(A)
+    A.eliminate_zeros()
+    with pytest.raises(B.PPError) as e:
+        B.pp_gmres_solve(B.CSRMatrix.from_host(A), _up(W.normal(300, 1)), m=10, d=3, tol=1e-8,
+                         v0=_up(W.uniform(300, 2)), left_jacobi=True)
+    assert e.value.code == B.PP_ERR_SINGULAR

@@ -149,3 +149,32 @@ def test_iterative_refinement_fp32_inner():
     # the float32 polynomial is close to (but not the same as) the float64 one
     r64, _ = poly.build_poly(A, P.v0, P.d)
     assert np.max(np.abs(np.sort(st.roots.real) - np.sort(r64.real)) / np.abs(np.sort(r64.real))) < 1e-3
+
+
+def test_left_jacobi_composition():
+    """Section II composition: the polynomial built for D^-1 A; solution equals A^-1 b."""
+    import scipy.sparse as sp
+    Ah = W.random_csr(300, 8, seed=50, diag_shift=0.0)
+    A = Ah.to_scipy()
+    dg = np.random.default_rng(51).uniform(2.0, 400.0, 300)      # widely varying diagonal
+    A = sp.csr_matrix(A + sp.diags(dg - A.diagonal()))
+    b = W.normal(300, 52)
+    As, bs = gmres.jacobi_left(A, b)
+    assert np.allclose(As.diagonal(), 1.0)
+    x, st = gmres.pp_gmres_left_jacobi(A, b, 20, 1e-12, v0=W.uniform(300, 53), d=6, max_iters=500)
+    ref = np.linalg.solve(A.toarray(), b)
+    assert st.converged and np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+    # the row scaling makes this problem far easier than the unscaled one
+    _, st0 = gmres.pp_gmres(A, b, 20, 1e-12, v0=W.uniform(300, 53), d=6, max_iters=500)
+    assert st.iters < st0.iters
+
+
+def test_stagnation_at_attainable_accuracy_ends_the_solve():
+    """A tolerance below the FP64 floor ends on the stagnation test, not the iteration cap."""
+    P = W.config(1, N=32)
+    A = P.A.to_scipy()
+    x, st = gmres.pp_gmres(A, P.b, 20, 1e-16, v0=P.v0, d=6, max_iters=5000)
+    assert not st.converged and st.iters < 1000
+    assert st.relres_true < 1e-14
+    th = np.asarray(st.true_history)
+    assert np.all(th[-3:] > 0.9 * th[-4:-1])
