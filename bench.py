@@ -52,7 +52,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=256, help="grid points per axis (256 = headline)")
-    ap.add_argument("--legs", default="ir,plain", help="comma list of extra legs: ir, plain, none")
+    ap.add_argument("--legs", default="ir,plain,power",
+                    help="comma list of extra legs: ir, plain, power, none")
     ap.add_argument("--plain-max-iters", type=int, default=30000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-check", type=int, default=1,
@@ -184,6 +185,29 @@ def main():
         roofline["frac_of_copy"] = (round(chain_gbps / roofline["copy_ceiling_GBps"], 4)
                                     if chain_gbps else None)
         log(f"copy ceiling {roofline['copy_ceiling_GBps']:.0f} GB/s")
+
+    if "power" in wanted:
+        # the paper's own construction: power basis + normal equations, degree chosen by
+        # Section IV's heuristic (highest degree whose Gram matrix factors), then the solve
+        import warnings
+        def power_solve():
+            ts = time.perf_counter()
+            p, info = B.pp_build_poly_power(A, v0, 30, auto_degree=True)
+            x.zero_()
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore")
+                _, s4 = B.pp_gmres_solve(A, b, x, m=P.m, d=0, tol=P.tol, poly=p,
+                                         max_iters=args.plain_max_iters)
+            torch.cuda.synchronize()
+            return time.perf_counter() - ts, p, info, s4
+        power_solve()
+        tpw, p, info, s4 = power_solve()
+        legs["pp_power_auto"] = {"time_s": tpw, "degree": len(B.pp_poly_coeffs(p)) - 1,
+                                 "potrf_info": info, "iters": s4.iters, "cycles": s4.cycles,
+                                 "relres": s4.relres_true,
+                                 "converged": bool(s4.relres_true < P.tol)}
+        log(f"power-basis auto degree {legs['pp_power_auto']['degree']}: {tpw:.3f}s "
+            f"iters {s4.iters} relres {s4.relres_true:.2e}")
 
     cpu = None
     if args.cpu_baseline:
