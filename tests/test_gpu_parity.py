@@ -386,3 +386,49 @@ def test_left_jacobi_rejects_zero_diagonal(B):
         B.pp_gmres_solve(B.CSRMatrix.from_host(A), _up(W.normal(300, 1)), m=10, d=3, tol=1e-8,
                          v0=_up(W.uniform(300, 2)), left_jacobi=True)
     assert e.value.code == B.PP_ERR_SINGULAR
+
+
+# ---- basis wider than one fused CGS2 sweep (64 columns): the chunked paths
+def test_gmres_with_more_than_64_basis_columns(B):
+    P = W.config(1)
+    xg, st, xo, so = _solve_both(B, P.A, P.b, P.v0, 100, 0, P.tol)
+    assert st.iters > 64          # the Arnoldi basis outgrew one sweep
+    _assert_parity(st, so, xg, xo, P.tol)
+
+
+def test_build_with_more_than_64_roots(B):
+    Ah = W.convection_diffusion(20, 2, 10.0, (1.0, 1.0))   # n = 400
+    v0 = W.uniform(Ah.n, 70)
+    ref, s = opoly.build_poly(Ah.to_scipy(), v0, 72)
+    got = B.pp_build_poly(B.CSRMatrix.from_host(Ah), _up(v0), 72).roots()
+    assert got.size == ref.size == 72
+    assert _match_sets(got, ref) <= 1e-6
+
+
+# ---- streams and workspace
+def test_solve_on_a_side_stream_and_after_workspace_release(B):
+    P = W.config(1, N=40)
+    A = B.CSRMatrix.from_host(P.A)
+    x0, s0 = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=P.d, tol=P.tol, v0=_up(P.v0))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        b = _up(P.b)
+        v0 = _up(P.v0)
+        x1, s1 = B.pp_gmres_solve(A, b, m=P.m, d=P.d, tol=P.tol, v0=v0, stream=side)
+    side.synchronize()
+    B.pp_release_workspace()
+    x2, s2 = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=P.d, tol=P.tol, v0=_up(P.v0))
+    assert s0.iters == s1.iters == s2.iters
+    assert np.array_equal(x0.cpu().numpy(), x1.cpu().numpy())
+    assert np.array_equal(x0.cpu().numpy(), x2.cpu().numpy())
+
+
+def test_history_and_timing_fields(B):
+    P = W.config(1, N=40)
+    A = B.CSRMatrix.from_host(P.A)
+    x, st = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=P.d, tol=P.tol, v0=_up(P.v0), history=500,
+                             timing=True)
+    h = st.history
+    assert h.size == st.iters and h[-1] < P.tol and np.all(np.diff(h) <= 1e-12 * h[:-1])
+    assert st.t_chain > 0 and st.t_orth > 0 and st.bytes_chain > 0 and st.launches_chain > 0
+    assert st.t_total >= st.t_poly > 0
