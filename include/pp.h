@@ -75,17 +75,33 @@ extern "C" {
 #define PP_OP_RESIDUAL_POLY 0 /* w = v - pi(A) v: d fused root updates (default) */
 #define PP_OP_PRODUCT 1       /* w = A (p(A) v): d-1 fused updates, then one product */
 
+/* ---- storage of A for the sparse products --------------------------- */
+#define PP_LAYOUT_AUTO 0 /* sliced ELL unless its padding is large (below), else CSR */
+#define PP_LAYOUT_CSR 1  /* run the products on the caller's CSR arrays */
+#define PP_LAYOUT_SELL 2 /* always sliced ELL (unless its offsets would overflow int32) */
+
 /* Square sparse matrix in CSR form, all arrays in device memory.
  * row_ptr[n+1] int32, row_ptr[0] = 0, nondecreasing, row_ptr[n] = nnz < 2^31;
  * col_ind[nnz] int32 in [0, n) (any order inside a row; sorted is fastest);
- * vals[nnz] of type dtype.  Duplicate (row, col) entries are summed. */
+ * vals[nnz] of type dtype.  Duplicate (row, col) entries are summed.
+ *
+ * layout: with PP_LAYOUT_AUTO (0, the zero-initialised default) or
+ * PP_LAYOUT_SELL, each call first copies A, in library memory, into sliced
+ * ELL: slices of 64 consecutive rows, each stored column-major and padded to its
+ * longest row (padding = column -1, value 0).  The products then run on the
+ * copy: one wavefront owns a slice, and each gather reads one entry of 64
+ * consecutive rows (for a stencil, 64 neighbouring values of one diagonal).
+ * The copy costs one pass over A per call.  AUTO keeps CSR when the copy would
+ * hold more than nnz + nnz/4 + 64 * (longest row) entries.  Both layouts give
+ * the same products up to the rounding of the summation. */
 typedef struct pp_csr {
   int64_t n;
   int64_t nnz;
   const int32_t *row_ptr;
   const int32_t *col_ind;
   const void *vals;
-  int32_t dtype; /* PP_F64 or PP_F32 */
+  int32_t dtype;  /* PP_F64 or PP_F32 */
+  int32_t layout; /* PP_LAYOUT_AUTO (0), PP_LAYOUT_CSR or PP_LAYOUT_SELL */
 } pp_csr;
 
 /* Opaque polynomial: n, the Leja-ordered roots (host, FP64) and the dtype it was
@@ -142,16 +158,20 @@ typedef struct pp_stats {
                               least squares */
   /* Algorithmic HBM bytes of the launches inside the timed phases above (the
    * Arnoldi steps' chains, operator products and CGS2 sweeps), from the
-   * per-launch traffic model: a chain launch reads vals, col_ind, row_ptr and the
-   * gathered vector once and the accumulator / partner vectors once, and
-   * writes its outputs once (12 nnz + 36 n bytes for a middle real-root step in
-   * FP64).  Divided by t_chain / t_spmv / t_orth they give achieved bandwidth. */
+   * per-launch traffic model: a chain launch reads the matrix once (CSR: vals,
+   * col_ind, row_ptr, 12 nnz + 4 n bytes in FP64; sliced ELL: the stored values
+   * and columns and the slice offsets, 12 nnz_stored + n/16 bytes), the gathered
+   * vector once and the accumulator / partner vectors once, and writes its
+   * outputs once.  Divided by t_chain / t_spmv / t_orth they give achieved
+   * bandwidth. */
   double bytes_chain;
   double bytes_spmv;
   double bytes_orth;
   int64_t launches_chain;  /* chain launches inside t_chain */
   double relres_original;  /* ||b - A x|| / ||b|| of the unpreconditioned system (equals
                               relres_true unless left_jacobi is set) */
+  int32_t layout_used;     /* PP_LAYOUT_CSR or PP_LAYOUT_SELL: what the products ran on */
+  int64_t nnz_stored;      /* entries one product streams: nnz (CSR) or nnz + padding */
 } pp_stats;
 
 /* Build the polynomial for (A, v0) with d roots.

@@ -23,6 +23,8 @@ PP_WARN_DEGREE_REDUCED, PP_WARN_NOT_CONVERGED, PP_WARN_NONFINITE, PP_WARN_CHOLES
 PP_F64, PP_F32 = 0, 1
 PP_PREC_F64, PP_PREC_F32_IR = 0, 1
 PP_OP_RESIDUAL_POLY, PP_OP_PRODUCT = 0, 1
+PP_LAYOUT_AUTO, PP_LAYOUT_CSR, PP_LAYOUT_SELL = 0, 1, 2
+LAYOUTS = {"auto": PP_LAYOUT_AUTO, "csr": PP_LAYOUT_CSR, "sell": PP_LAYOUT_SELL}
 
 EXPORTS = ("pp_build_poly", "pp_apply", "pp_gmres_solve", "pp_poly_roots", "pp_poly_from_roots",
            "pp_poly_free", "pp_roots_from_hessenberg", "pp_csr_transpose", "pp_csr_grad",
@@ -32,7 +34,8 @@ EXPORTS = ("pp_build_poly", "pp_apply", "pp_gmres_solve", "pp_poly_roots", "pp_p
 
 class pp_csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
-                ("col_ind", ctypes.c_void_p), ("vals", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+                ("col_ind", ctypes.c_void_p), ("vals", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("layout", ctypes.c_int32)]
 
 
 class pp_opts(ctypes.Structure):
@@ -54,7 +57,8 @@ class pp_stats(ctypes.Structure):
                 ("t_spmv", ctypes.c_double), ("t_orth", ctypes.c_double),
                 ("t_host", ctypes.c_double), ("bytes_chain", ctypes.c_double),
                 ("bytes_spmv", ctypes.c_double), ("bytes_orth", ctypes.c_double),
-                ("launches_chain", ctypes.c_int64), ("relres_original", ctypes.c_double)]
+                ("launches_chain", ctypes.c_int64), ("relres_original", ctypes.c_double),
+                ("layout_used", ctypes.c_int32), ("nnz_stored", ctypes.c_int64)]
 
 
 _lib = None
@@ -155,9 +159,14 @@ def _dev_vec(t, dtype, n, name):
 
 
 class CSRMatrix:
-    """Square CSR matrix whose arrays live in device memory (torch tensors)."""
+    """Square CSR matrix whose arrays live in device memory (torch tensors).
 
-    def __init__(self, row_ptr, col_ind, vals):
+    ``layout`` ("auto", "csr" or "sell") is the storage the library uses for its
+    sparse products (``pp_csr.layout``): "auto" builds a sliced-ELL copy per call
+    unless its padding would be large.
+    """
+
+    def __init__(self, row_ptr, col_ind, vals, layout: str = "auto"):
         torch = _torch()
         if row_ptr.dtype != torch.int32 or col_ind.dtype != torch.int32:
             raise ValueError("row_ptr and col_ind must be int32")
@@ -168,7 +177,10 @@ class CSRMatrix:
                 raise ValueError("CSR arrays must be contiguous CUDA tensors")
         if col_ind.numel() != vals.numel():
             raise ValueError("col_ind and vals differ in length")
+        if layout not in LAYOUTS:
+            raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
         self.row_ptr, self.col_ind, self.vals = row_ptr, col_ind, vals
+        self.layout = layout
         self.n = row_ptr.numel() - 1
         self.nnz = vals.numel()
 
@@ -177,7 +189,7 @@ class CSRMatrix:
         return self.vals.dtype
 
     @classmethod
-    def from_host(cls, A, device="cuda", dtype=None, validate=True):
+    def from_host(cls, A, device="cuda", dtype=None, validate=True, layout="auto"):
         """Upload a host CSR (``workloads.CSR`` or scipy csr_matrix).
 
         ``validate`` checks the structure on the host first (row pointers
@@ -196,15 +208,19 @@ class CSRMatrix:
             check_csr_host(rp, ci, n)
         dt = dtype or torch.float64
         return cls(torch.from_numpy(rp).to(device), torch.from_numpy(ci).to(device),
-                   torch.from_numpy(va).to(device=device, dtype=dt))
+                   torch.from_numpy(va).to(device=device, dtype=dt), layout=layout)
 
     def with_vals(self, vals):
-        return CSRMatrix(self.row_ptr, self.col_ind, vals)
+        return CSRMatrix(self.row_ptr, self.col_ind, vals, layout=self.layout)
+
+    def with_layout(self, layout: str):
+        return CSRMatrix(self.row_ptr, self.col_ind, self.vals, layout=layout)
 
     def c(self) -> pp_csr:
         torch = _torch()
         return pp_csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_ind.data_ptr(),
-                      self.vals.data_ptr(), PP_F64 if self.vals.dtype == torch.float64 else PP_F32)
+                      self.vals.data_ptr(), PP_F64 if self.vals.dtype == torch.float64 else PP_F32,
+                      LAYOUTS[self.layout])
 
 
 def check_csr_host(rp: np.ndarray, ci: np.ndarray, n: int) -> None:
@@ -301,6 +317,8 @@ class Stats:
     launches_chain: int = 0
     relres_original: float = float("nan")
     history: Optional[np.ndarray] = None
+    layout_used: str = ""
+    nnz_stored: int = 0
 
 
 def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float = 1e-8,
@@ -346,7 +364,9 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
               st.relres_true, st.relres_implicit, st.t_total, st.t_poly, st.t_chain, st.t_spmv,
               st.t_orth, st.t_host, st.bytes_chain, st.bytes_spmv, st.bytes_orth,
               st.launches_chain, st.relres_original,
-              hist[: st.history_len].copy() if hist is not None else None)
+              hist[: st.history_len].copy() if hist is not None else None,
+              {PP_LAYOUT_CSR: "csr", PP_LAYOUT_SELL: "sell"}.get(st.layout_used, ""),
+              st.nnz_stored)
     return x, s
 
 
@@ -395,7 +415,7 @@ def pp_csr_transpose(A: CSRMatrix, stream=None) -> CSRMatrix:
     va = torch.empty(A.nnz, dtype=A.vals.dtype, device=A.vals.device)
     _check(lib().pp_csr_transpose(ctypes.byref(A.c()), _ptr(rp), _ptr(ci), _ptr(va),
                                   _stream(stream)), "pp_csr_transpose")
-    return CSRMatrix(rp, ci, va)
+    return CSRMatrix(rp, ci, va, layout=A.layout)
 
 
 def pp_csr_grad(A: CSRMatrix, lam, x, g=None, stream=None):

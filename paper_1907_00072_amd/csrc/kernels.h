@@ -14,15 +14,25 @@ namespace ppk {
 
 constexpr int kBlock = 256;   // threads per workgroup (4 wavefronts of 64)
 constexpr int kMaxCols = 64;  // columns handled by one fused CGS2 sweep
+constexpr int kSlice = 64;    // rows per sliced-ELL slice (one wavefront)
 
-// CSR matrix view on the device.
+// Sparse matrix view on the device: CSR, plus an optional sliced-ELL copy.
+// Sliced ELL groups the rows in slices of kSlice; slice s stores
+// w_s = (sp[s+1] - sp[s]) / kSlice entries per row column-major (entry j of
+// row kSlice*s + l at sp[s] + kSlice*j + l), rows shorter than w_s padded with
+// column -1 and value 0.  When sp != nullptr the product kernels read only the
+// sliced-ELL arrays (sp, sci, sva) and never rp/ci/va.
 template <typename T>
-struct Csr {
+struct SpMat {
   int n;
   int nnz;
   const int32_t *rp;
   const int32_t *ci;
   const T *va;
+  const int32_t *sp = nullptr;  // [ceil(n / kSlice) + 1]
+  const int32_t *sci = nullptr; // [snnz]
+  const T *sva = nullptr;       // [snnz]
+  int snnz = 0;                 // stored entries including padding
 };
 
 // One launch of the fused product + root-update chain.
@@ -52,7 +62,7 @@ struct ChainArgs {
 
 // `fold` and `last` select the variants above (fold: kinds 0 and 2; last: kinds 1, 2, 3).
 template <typename T>
-hipError_t launch_chain(const Csr<T> &A, int kind, bool fold, bool last, const ChainArgs<T> &a,
+hipError_t launch_chain(const SpMat<T> &A, int kind, bool fold, bool last, const ChainArgs<T> &a,
                         hipStream_t stream);
 
 // y_out = y_in + c * (gscale * g) elementwise (a degree-0 polynomial step).
@@ -62,37 +72,52 @@ hipError_t launch_axpy(int n, double c, const T *g, const double *gscale, const 
 
 // out = A * (gscale * g).
 template <typename T>
-hipError_t launch_spmv(const Csr<T> &A, const T *g, const double *gscale, T *out,
+hipError_t launch_spmv(const SpMat<T> &A, const T *g, const double *gscale, T *out,
                        hipStream_t stream);
 
 // out = b - A x (out may be a T-typed vector of the same type as A), and
 // partial[tile] = sum over the tile of out^2 (double).  Returns the tile count.
 template <typename T>
-hipError_t launch_residual(const Csr<T> &A, const T *b, const T *x, T *out, double *partial,
+hipError_t launch_residual(const SpMat<T> &A, const T *b, const T *x, T *out, double *partial,
                            int *ntiles, hipStream_t stream);
 
-// Number of workgroups of the CGS2 kernels for a vector of length n.
-int orth_grid(int n);
+// Sweep kinds of the Gram-Schmidt kernels, for the choice of rows per thread.
+constexpr int kOrthRead = 0;        // k_dots, k_norm2 without the FP32 copy (read-only)
+constexpr int kOrthUpdateDots = 1;  // k_update fused with the next pass's dots
+constexpr int kOrthWrite = 2;       // k_update with the norm or alone, k_norm2 with the copy
+constexpr int kOrthMinRpt = 2;      // the smallest value orth_rpt returns
 
-// partial[(c0+c) * G + g] = sum over block g's rows of V(i, c0+c) * w(i), c < nc <= kMaxCols.
+// Rows per thread (each workgroup owns a contiguous block of 256 * rpt rows) of
+// a CGS2 sweep over nc <= kMaxCols basis columns.  Read-only sweeps run long
+// workgroups; sweeps that write run short ones, so the resident workgroups'
+// stores stay within a narrow window of HBM, as in a flat copy; the update +
+// dots sweep sits between because each workgroup must also reduce nc partial
+// dots.  Measured on gfx950 at n = 16.8M (FP64 update + norm: 5.2 -> 6.0 TB/s).
+int orth_rpt(int kind, int nc, bool f32);
+// Workgroups G of a sweep of n rows at rpt rows per thread; its partials are
+// laid out [column][G].
+int orth_grid(int n, int rpt);
+
+// partial[(c0+c) * G + g] = sum over block g's rows of V(i, c0+c) * w(i), c < nc <= kMaxCols,
+// G = orth_grid(n, rpt).
 template <typename T>
-hipError_t launch_dots(int n, const T *V, int64_t ldv, int c0, int nc, const T *w,
+hipError_t launch_dots(int n, int rpt, const T *V, int64_t ldv, int c0, int nc, const T *w,
                        double *partial, hipStream_t stream);
 
 // out = w_in - sum_c V(:, c) * coef(c),  coef(c) = sign * a(c) * (b ? b(c) : 1), nc <= kMaxCols.
 // w_in may be nullptr (zero) and may equal out.  With dots: partial dots of the
 // new vector with V(:, 0..nc) as in launch_dots.  With norm: partial[g] = sum of
-// out^2 over block g (double).
+// out^2 over block g (double).  G = orth_grid(n, rpt).
 template <typename T>
-hipError_t launch_update(int n, const T *V, int64_t ldv, int nc, const double *coef_a,
+hipError_t launch_update(int n, int rpt, const T *V, int64_t ldv, int nc, const double *coef_a,
                          const double *coef_b, double sign, const T *w_in, T *out, bool dots,
                          bool norm, double *partial, hipStream_t stream);
 
 // partial[g] = sum over block g of (scale*x(i))^2 in double; optionally also
 // writes out32 = (float)(scale * x) when out32 != nullptr (the refinement cast).
 template <typename T>
-hipError_t launch_norm2(int n, const T *x, const double *scale, float *out32, double *partial,
-                        hipStream_t stream);
+hipError_t launch_norm2(int n, int rpt, const T *x, const double *scale, float *out32,
+                        double *partial, hipStream_t stream);
 
 // Second stage of the column reductions:
 //   h[c] = colscale[c0+c] * sum_g partial[(c0+c)*G + g];  coef[c] = colscale[c0+c] * h[c].
@@ -133,6 +158,22 @@ template <typename T>
 hipError_t launch_sort_rows(int n, const int32_t *rp, int32_t *ci, T *va, hipStream_t stream);
 hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const double *lam,
                            const double *x, double *g, hipStream_t stream);
+
+// Sliced-ELL construction from CSR (ns = ceil(n / kSlice) slices).
+// widths: wlen[s] = kSlice * (longest row of slice s), wrapping modulo 2^32;
+//         *maxlen = max(*maxlen, longest row) (caller zeroes it first; the
+//         caller rejects the layout when kSlice * maxlen * ns >= 2^31, which
+//         also covers any wrap).
+// Then sp = exclusive scan of wlen (launch_exclusive_scan), and the fills write
+// every stored entry, padding included.
+hipError_t launch_sell_widths(int n, int ns, const int32_t *rp, int32_t *wlen, int32_t *maxlen,
+                              hipStream_t stream);
+hipError_t launch_sell_fill_cols(int n, int ns, const int32_t *rp, const int32_t *ci,
+                                 const int32_t *sp, int32_t *sci, hipStream_t stream);
+// sva = (D) va in sliced-ELL order (S, D in {float, double}).
+template <typename S, typename D>
+hipError_t launch_sell_fill_vals(int n, int ns, const int32_t *rp, const S *va, const int32_t *sp,
+                                 D *sva, hipStream_t stream);
 
 // Left Jacobi scaling: va_out[k] = va[k] / a_ii and b_out[i] = b[i] / a_ii for the
 // row i of entry k (a_ii the sum of the row's diagonal entries); *bad is set to 1

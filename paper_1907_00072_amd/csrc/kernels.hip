@@ -18,6 +18,14 @@
 //   nonzero; own-row operands are fetched before the reduction; streamed
 //   vectors use non-temporal loads and stores so the L2 keeps the gathered
 //   vector.
+// * When the view carries a sliced-ELL copy (64-row slices, column-major inside a
+//   slice) the same kernels run on it instead: lane l of a wavefront owns row
+//   64 s + l, loads of entry j of the slice's 64 rows are one contiguous burst,
+//   and the gather for entry j touches one diagonal of 64 consecutive rows (a
+//   few cache lines) rather than every diagonal of a handful of rows as in the
+//   CSR-stream tile.  No row pointers, no LDS and no barrier are needed.  This
+//   is what lets the FP32 chain reach the copy bandwidth; the CSR path is kept
+//   for matrices whose slices would need heavy padding.
 // * The Gram-Schmidt kernels keep one basis row per thread in registers (a
 //   template bound on the column count, in steps of 8), so each sweep reads
 //   every basis column once and updates the vector and accumulates the next
@@ -34,8 +42,6 @@
 namespace ppk {
 
 namespace {
-
-constexpr int kOrthRowsTarget = 2048;  // aim for about this many CGS2 workgroups
 
 template <typename T>
 struct LdsCap;
@@ -78,7 +84,7 @@ __device__ __forceinline__ void stnt(T v, T *p) {
 // All threads of the workgroup must call it; rows past the tile return 0.
 // rb/re are the calling thread's row bounds (0, 0 for threads past the tile).
 template <typename T>
-__device__ __forceinline__ T tile_row_sum(const Csr<T> &A, const T *__restrict__ g, int r0,
+__device__ __forceinline__ T tile_row_sum(const SpMat<T> &A, const T *__restrict__ g, int r0,
                                           int nrows, int rb, int re, T *s_buf) {
   constexpr int CAP = LdsCap<T>::value;
   constexpr int PER = CAP / kBlock;
@@ -110,10 +116,57 @@ __device__ __forceinline__ T tile_row_sum(const Csr<T> &A, const T *__restrict__
   return acc;
 }
 
+constexpr int kSellBatch = 8;  // sliced-ELL entries per row whose loads are in flight together
+
+// Row sum of A * g for `row` from the sliced-ELL copy (thread -> row, lanes of
+// a wavefront -> the 64 rows of one slice).  Rows past n return 0; padding
+// entries (column -1) contribute nothing.
+template <typename T>
+__device__ __forceinline__ T sell_row_sum(const SpMat<T> &A, const T *__restrict__ g, int row) {
+  const int s = row / kSlice;  // uniform across the wavefront
+  const int lane = row - s * kSlice;
+  T acc = T(0);
+  if (s * kSlice >= A.n) return acc;
+  const int base = A.sp[s];
+  const int w = (A.sp[s + 1] - base) / kSlice;
+  for (int j0 = 0; j0 < w; j0 += kSellBatch) {
+    int cols[kSellBatch];
+    T vals[kSellBatch];
+#pragma unroll
+    for (int q = 0; q < kSellBatch; ++q) {
+      cols[q] = -1;
+      vals[q] = T(0);
+      if (j0 + q < w) {
+        const int k = base + (j0 + q) * kSlice + lane;
+        vals[q] = ldnt(A.sva + k);
+        cols[q] = ldnt(A.sci + k);
+      }
+    }
+    T gv[kSellBatch];
+#pragma unroll
+    for (int q = 0; q < kSellBatch; ++q) gv[q] = cols[q] >= 0 ? g[cols[q]] : T(0);
+#pragma unroll
+    for (int q = 0; q < kSellBatch; ++q) acc += vals[q] * gv[q];
+  }
+  return acc;
+}
+
+// Row sum of A * g for the calling thread's row r0 + threadIdx.x from the view's
+// layout.  All threads of the workgroup must call it.
+template <typename T, bool SELL>
+__device__ __forceinline__ T row_product(const SpMat<T> &A, const T *__restrict__ g, int r0,
+                                         int nrows, int rb, int re) {
+  if constexpr (SELL) {
+    return sell_row_sum(A, g, r0 + (int)threadIdx.x);
+  } else {
+    __shared__ T s_buf[LdsCap<T>::value];
+    return tile_row_sum(A, g, r0, nrows, rb, re, s_buf);
+  }
+}
+
 // ------------------------------------------------------------------ chain
-template <typename T, int KIND, bool FOLD, bool LAST>
-__global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
-  __shared__ T s_buf[LdsCap<T>::value];
+template <typename T, int KIND, bool FOLD, bool LAST, bool SELL>
+__global__ __launch_bounds__(kBlock) void k_chain(SpMat<T> A, ChainArgs<T> a) {
   const int r0 = blockIdx.x * kBlock;
   const int nrows = min(kBlock, A.n - r0);
   const int t = threadIdx.x;
@@ -126,14 +179,16 @@ __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
   int rb = 0, re = 0;
   T own = T(0), yv = T(0), sf = T(0);
   if (live) {
-    rb = A.rp[i];
-    re = A.rp[i + 1];
+    if constexpr (!SELL) {
+      rb = A.rp[i];
+      re = A.rp[i + 1];
+    }
     own = a.g[i];
     if (kReadY) yv = a.y_in ? ldnt(a.y_in + i) : T(0);
     if (kReadSelf) sf = ldnt(a.self + i);
   }
   const T gs = a.gscale ? (T)(*a.gscale) : T(1);
-  const T acc = tile_row_sum(A, a.g, r0, nrows, rb, re, s_buf);
+  const T acc = row_product<T, SELL>(A, a.g, r0, nrows, rb, re);
   if (!live) return;
   const T c1 = (T)a.c1, c2 = (T)a.c2, cf = (T)a.cf;
   if constexpr (KIND == 0) {
@@ -177,27 +232,27 @@ __global__ __launch_bounds__(kBlock) void k_chain(Csr<T> A, ChainArgs<T> a) {
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spmv(Csr<T> A, const T *__restrict__ g,
+template <typename T, bool SELL>
+__global__ __launch_bounds__(kBlock) void k_spmv(SpMat<T> A, const T *__restrict__ g,
                                                  const double *gscale, T *__restrict__ out) {
-  __shared__ T s_buf[LdsCap<T>::value];
   const int r0 = blockIdx.x * kBlock;
   const int nrows = min(kBlock, A.n - r0);
   const int i = r0 + threadIdx.x;
   int rb = 0, re = 0;
-  if ((int)threadIdx.x < nrows) {
-    rb = A.rp[i];
-    re = A.rp[i + 1];
+  if constexpr (!SELL) {
+    if ((int)threadIdx.x < nrows) {
+      rb = A.rp[i];
+      re = A.rp[i + 1];
+    }
   }
-  const T acc = tile_row_sum(A, g, r0, nrows, rb, re, s_buf);
+  const T acc = row_product<T, SELL>(A, g, r0, nrows, rb, re);
   if ((int)threadIdx.x < nrows) stnt((gscale ? (T)(*gscale) : T(1)) * acc, out + i);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_residual(Csr<T> A, const T *__restrict__ b,
+template <typename T, bool SELL>
+__global__ __launch_bounds__(kBlock) void k_residual(SpMat<T> A, const T *__restrict__ b,
                                                      const T *__restrict__ x, T *__restrict__ out,
                                                      double *__restrict__ partial) {
-  __shared__ T s_buf[LdsCap<T>::value];
   __shared__ double red[4];
   const int r0 = blockIdx.x * kBlock;
   const int nrows = min(kBlock, A.n - r0);
@@ -205,11 +260,13 @@ __global__ __launch_bounds__(kBlock) void k_residual(Csr<T> A, const T *__restri
   int rb = 0, re = 0;
   T bi = T(0);
   if ((int)threadIdx.x < nrows) {
-    rb = A.rp[i];
-    re = A.rp[i + 1];
+    if constexpr (!SELL) {
+      rb = A.rp[i];
+      re = A.rp[i + 1];
+    }
     bi = ldnt(b + i);
   }
-  const T acc = tile_row_sum(A, x, r0, nrows, rb, re, s_buf);
+  const T acc = row_product<T, SELL>(A, x, r0, nrows, rb, re);
   double sq = 0.0;
   if ((int)threadIdx.x < nrows) {
     const T r = bi - acc;
@@ -358,13 +415,25 @@ __global__ __launch_bounds__(kBlock) void k_norm2(int n, int rpt, const T *__res
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
+// Fixed-order sum of x[0..G) over the workgroup's threads (thread t takes
+// t, t + 256, ...), with four loads in flight per thread.
+__device__ __forceinline__ double strided_sum(const double *__restrict__ x, int G) {
+  double s = 0.0;
+  int g = threadIdx.x;
+  for (; g + 3 * kBlock < G; g += 4 * kBlock) {
+    const double a0 = x[g], a1 = x[g + kBlock], a2 = x[g + 2 * kBlock], a3 = x[g + 3 * kBlock];
+    s += (a0 + a1) + (a2 + a3);
+  }
+  for (; g < G; g += kBlock) s += x[g];
+  return s;
+}
+
 __global__ __launch_bounds__(kBlock) void k_reduce_cols(const double *__restrict__ partial, int G,
                                                         int c0, const double *colscale, double *h,
                                                         double *coef) {
   __shared__ double red4[4];
   const int c = c0 + blockIdx.x;
-  double s = 0.0;
-  for (int g = threadIdx.x; g < G; g += kBlock) s += partial[(int64_t)c * G + g];
+  double s = strided_sum(partial + (int64_t)c * G, G);
   s = block_sum(s, red4);
   if (threadIdx.x == 0) {
     const double sc = colscale ? colscale[c] : 1.0;
@@ -377,8 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_cols(const double *__restrict
 __global__ __launch_bounds__(kBlock) void k_reduce_norm(const double *__restrict__ partial, int G,
                                                         double *nrm, double *inv) {
   __shared__ double red4[4];
-  double s = 0.0;
-  for (int g = threadIdx.x; g < G; g += kBlock) s += partial[g];
+  double s = strided_sum(partial, G);
   s = block_sum(s, red4);
   if (threadIdx.x == 0) {
     const double r = sqrt(s);
@@ -532,6 +600,63 @@ __global__ __launch_bounds__(kBlock) void k_csr_grad(int n, const int32_t *__res
   for (int k = rp[i]; k < rp[i + 1]; ++k) g[k] = -li * x[ci[k]];
 }
 
+// ------------------------------------------------------- sliced ELL
+__global__ __launch_bounds__(kBlock) void k_sell_widths(int n, int ns,
+                                                        const int32_t *__restrict__ rp,
+                                                        int32_t *__restrict__ wlen,
+                                                        int32_t *maxlen) {
+  __shared__ int32_t red[kBlock / 64];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  int len = (i < n) ? rp[i + 1] - rp[i] : 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+  const int s = i / kSlice;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    if (s < ns) wlen[s] = (int32_t)((uint32_t)kSlice * (uint32_t)len);
+    red[wv] = len;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(maxlen, max(max(red[0], red[1]), max(red[2], red[3])));
+}
+
+__global__ __launch_bounds__(kBlock) void k_sell_fill_cols(int n, int ns,
+                                                           const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const int32_t *__restrict__ sp,
+                                                           int32_t *__restrict__ sci) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int s = i / kSlice;
+  if (s >= ns) return;
+  const int lane = i - s * kSlice;
+  const int base = sp[s], w = (sp[s + 1] - base) / kSlice;
+  int rb = 0, len = 0;
+  if (i < n) {
+    rb = rp[i];
+    len = rp[i + 1] - rb;
+  }
+  for (int j = 0; j < w; ++j) sci[base + j * kSlice + lane] = j < len ? ci[rb + j] : -1;
+}
+
+template <typename S, typename D>
+__global__ __launch_bounds__(kBlock) void k_sell_fill_vals(int n, int ns,
+                                                           const int32_t *__restrict__ rp,
+                                                           const S *__restrict__ va,
+                                                           const int32_t *__restrict__ sp,
+                                                           D *__restrict__ sva) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int s = i / kSlice;
+  if (s >= ns) return;
+  const int lane = i - s * kSlice;
+  const int base = sp[s], w = (sp[s + 1] - base) / kSlice;
+  int rb = 0, len = 0;
+  if (i < n) {
+    rb = rp[i];
+    len = rp[i + 1] - rb;
+  }
+  for (int j = 0; j < w; ++j) sva[base + j * kSlice + lane] = j < len ? (D)va[rb + j] : D(0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_jacobi_scale(int n, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ ci,
                                                          const double *__restrict__ va,
@@ -557,20 +682,20 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_scale(int n, const int32_t *_
 inline int tiles_of(int n) { return (n + kBlock - 1) / kBlock; }
 inline unsigned blocks_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-inline int orth_rpt(int n) {
-  const int64_t per = (int64_t)kBlock * kOrthRowsTarget;
-  int rpt = (int)((n + per - 1) / per);
-  return rpt < 1 ? 1 : rpt;
-}
-
 }  // namespace
 
 // ------------------------------------------------------------- wrappers
 template <typename T>
-hipError_t launch_chain(const Csr<T> &A, int kind, bool fold, bool last, const ChainArgs<T> &a,
+hipError_t launch_chain(const SpMat<T> &A, int kind, bool fold, bool last, const ChainArgs<T> &a,
                         hipStream_t stream) {
   const dim3 grid(tiles_of(A.n)), block(kBlock);
-#define PP_CHAIN(K, F, L) hipLaunchKernelGGL((k_chain<T, K, F, L>), grid, block, 0, stream, A, a)
+#define PP_CHAIN(K, F, L)                                                                     \
+  do {                                                                                        \
+    if (A.sp)                                                                                 \
+      hipLaunchKernelGGL((k_chain<T, K, F, L, true>), grid, block, 0, stream, A, a);          \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_chain<T, K, F, L, false>), grid, block, 0, stream, A, a);         \
+  } while (0)
   switch (kind) {
     case 0:
       if (fold) PP_CHAIN(0, true, false); else PP_CHAIN(0, false, false);
@@ -605,24 +730,42 @@ hipError_t launch_axpy(int n, double c, const T *g, const double *gscale, const 
 }
 
 template <typename T>
-hipError_t launch_spmv(const Csr<T> &A, const T *g, const double *gscale, T *out,
+hipError_t launch_spmv(const SpMat<T> &A, const T *g, const double *gscale, T *out,
                        hipStream_t stream) {
-  hipLaunchKernelGGL((k_spmv<T>), dim3(tiles_of(A.n)), dim3(kBlock), 0, stream, A, g, gscale,
-                     out);
+  if (A.sp)
+    hipLaunchKernelGGL((k_spmv<T, true>), dim3(tiles_of(A.n)), dim3(kBlock), 0, stream, A, g,
+                       gscale, out);
+  else
+    hipLaunchKernelGGL((k_spmv<T, false>), dim3(tiles_of(A.n)), dim3(kBlock), 0, stream, A, g,
+                       gscale, out);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_residual(const Csr<T> &A, const T *b, const T *x, T *out, double *partial,
+hipError_t launch_residual(const SpMat<T> &A, const T *b, const T *x, T *out, double *partial,
                            int *ntiles, hipStream_t stream) {
   *ntiles = tiles_of(A.n);
-  hipLaunchKernelGGL((k_residual<T>), dim3(*ntiles), dim3(kBlock), 0, stream, A, b, x, out,
-                     partial);
+  if (A.sp)
+    hipLaunchKernelGGL((k_residual<T, true>), dim3(*ntiles), dim3(kBlock), 0, stream, A, b, x,
+                       out, partial);
+  else
+    hipLaunchKernelGGL((k_residual<T, false>), dim3(*ntiles), dim3(kBlock), 0, stream, A, b, x,
+                       out, partial);
   return hipGetLastError();
 }
 
-int orth_grid(int n) {
-  const int rpt = orth_rpt(n);
+int orth_rpt(int kind, int nc, bool f32) {
+  if (kind == kOrthRead) return (f32 && nc <= 24) ? 4 : 32;
+  if (kind == kOrthUpdateDots) {
+    if (nc <= 8) return f32 ? 4 : 2;
+    if (nc <= 24) return 4;
+    if (nc <= 40) return 8;
+    return 32;
+  }
+  return (!f32 && nc > 40) ? 8 : kOrthMinRpt;
+}
+
+int orth_grid(int n, int rpt) {
   const int64_t per = (int64_t)kBlock * rpt;
   return (int)((n + per - 1) / per);
 }
@@ -650,10 +793,10 @@ int orth_grid(int n) {
   } while (0)
 
 template <typename T>
-hipError_t launch_dots(int n, const T *V, int64_t ldv, int c0, int nc, const T *w,
+hipError_t launch_dots(int n, int rpt, const T *V, int64_t ldv, int c0, int nc, const T *w,
                        double *partial, hipStream_t stream) {
-  if (nc < 1 || nc > kMaxCols) return hipErrorInvalidValue;
-  const int rpt = orth_rpt(n), G = orth_grid(n);
+  if (nc < 1 || nc > kMaxCols || rpt < 1) return hipErrorInvalidValue;
+  const int G = orth_grid(n, rpt);
 #define PP_DOTS_CALL(NCB)                                                                       \
   hipLaunchKernelGGL((k_dots<T, NCB>), dim3(G), dim3(kBlock), 0, stream, n, rpt, V, ldv, c0, nc, \
                      w, partial)
@@ -663,10 +806,10 @@ hipError_t launch_dots(int n, const T *V, int64_t ldv, int c0, int nc, const T *
 }
 
 template <typename T, bool DOTS, bool NORM>
-static void update_dispatch(int n, const T *V, int64_t ldv, int nc, const double *ca,
+static void update_dispatch(int n, int rpt, const T *V, int64_t ldv, int nc, const double *ca,
                             const double *cb, double sign, const T *w_in, T *out, double *partial,
                             hipStream_t stream) {
-  const int rpt = orth_rpt(n), G = orth_grid(n);
+  const int G = orth_grid(n, rpt);
 #define PP_UPD_CALL(NCB)                                                                      \
   hipLaunchKernelGGL((k_update<T, NCB, DOTS, NORM>), dim3(G), dim3(kBlock), 0, stream, n, rpt, \
                      V, ldv, nc, ca, cb, sign, w_in, out, partial)
@@ -675,26 +818,27 @@ static void update_dispatch(int n, const T *V, int64_t ldv, int nc, const double
 }
 
 template <typename T>
-hipError_t launch_update(int n, const T *V, int64_t ldv, int nc, const double *coef_a,
+hipError_t launch_update(int n, int rpt, const T *V, int64_t ldv, int nc, const double *coef_a,
                          const double *coef_b, double sign, const T *w_in, T *out, bool dots,
                          bool norm, double *partial, hipStream_t stream) {
-  if (nc < 1 || nc > kMaxCols || (dots && norm)) return hipErrorInvalidValue;
+  if (nc < 1 || nc > kMaxCols || (dots && norm) || rpt < 1) return hipErrorInvalidValue;
   if (dots)
-    update_dispatch<T, true, false>(n, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
+    update_dispatch<T, true, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
                                     stream);
   else if (norm)
-    update_dispatch<T, false, true>(n, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
+    update_dispatch<T, false, true>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
                                     stream);
   else
-    update_dispatch<T, false, false>(n, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
-                                     stream);
+    update_dispatch<T, false, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
+                                     partial, stream);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_norm2(int n, const T *x, const double *scale, float *out32, double *partial,
-                        hipStream_t stream) {
-  hipLaunchKernelGGL((k_norm2<T>), dim3(orth_grid(n)), dim3(kBlock), 0, stream, n, orth_rpt(n), x,
+hipError_t launch_norm2(int n, int rpt, const T *x, const double *scale, float *out32,
+                        double *partial, hipStream_t stream) {
+  if (rpt < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_norm2<T>), dim3(orth_grid(n, rpt)), dim3(kBlock), 0, stream, n, rpt, x,
                      scale, out32, partial);
   return hipGetLastError();
 }
@@ -784,6 +928,39 @@ hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const do
   return hipGetLastError();
 }
 
+hipError_t launch_sell_widths(int n, int ns, const int32_t *rp, int32_t *wlen, int32_t *maxlen,
+                              hipStream_t stream) {
+  if (ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sell_widths, dim3(blocks_of((int64_t)ns * kSlice)), dim3(kBlock), 0, stream,
+                     n, ns, rp, wlen, maxlen);
+  return hipGetLastError();
+}
+
+hipError_t launch_sell_fill_cols(int n, int ns, const int32_t *rp, const int32_t *ci,
+                                 const int32_t *sp, int32_t *sci, hipStream_t stream) {
+  if (ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sell_fill_cols, dim3(blocks_of((int64_t)ns * kSlice)), dim3(kBlock), 0,
+                     stream, n, ns, rp, ci, sp, sci);
+  return hipGetLastError();
+}
+
+template <typename S, typename D>
+hipError_t launch_sell_fill_vals(int n, int ns, const int32_t *rp, const S *va, const int32_t *sp,
+                                 D *sva, hipStream_t stream) {
+  if (ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sell_fill_vals<S, D>), dim3(blocks_of((int64_t)ns * kSlice)), dim3(kBlock),
+                     0, stream, n, ns, rp, va, sp, sva);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sell_fill_vals<double, double>(int, int, const int32_t *,
+                                                          const double *, const int32_t *,
+                                                          double *, hipStream_t);
+template hipError_t launch_sell_fill_vals<double, float>(int, int, const int32_t *, const double *,
+                                                         const int32_t *, float *, hipStream_t);
+template hipError_t launch_sell_fill_vals<float, float>(int, int, const int32_t *, const float *,
+                                                        const int32_t *, float *, hipStream_t);
+
 hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, const double *va,
                                const double *b, double *va_out, double *b_out, int32_t *bad,
                                hipStream_t stream) {
@@ -794,20 +971,20 @@ hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, cons
 
 // explicit instantiations
 #define PP_INST(T)                                                                              \
-  template hipError_t launch_chain<T>(const Csr<T> &, int, bool, bool, const ChainArgs<T> &,    \
+  template hipError_t launch_chain<T>(const SpMat<T> &, int, bool, bool, const ChainArgs<T> &,    \
                                       hipStream_t);                                             \
   template hipError_t launch_axpy<T>(int, double, const T *, const double *, const T *, T *,    \
                                      hipStream_t);                                              \
-  template hipError_t launch_spmv<T>(const Csr<T> &, const T *, const double *, T *,           \
+  template hipError_t launch_spmv<T>(const SpMat<T> &, const T *, const double *, T *,           \
                                      hipStream_t);                                              \
-  template hipError_t launch_residual<T>(const Csr<T> &, const T *, const T *, T *, double *,  \
+  template hipError_t launch_residual<T>(const SpMat<T> &, const T *, const T *, T *, double *,  \
                                          int *, hipStream_t);                                   \
-  template hipError_t launch_dots<T>(int, const T *, int64_t, int, int, const T *, double *,    \
+  template hipError_t launch_dots<T>(int, int, const T *, int64_t, int, int, const T *, double *, \
                                      hipStream_t);                                              \
-  template hipError_t launch_update<T>(int, const T *, int64_t, int, const double *,            \
+  template hipError_t launch_update<T>(int, int, const T *, int64_t, int, const double *,       \
                                        const double *, double, const T *, T *, bool, bool,      \
                                        double *, hipStream_t);                                  \
-  template hipError_t launch_norm2<T>(int, const T *, const double *, float *, double *,        \
+  template hipError_t launch_norm2<T>(int, int, const T *, const double *, float *, double *,   \
                                       hipStream_t);                                             \
   template hipError_t launch_fill<T>(int64_t, T, T *, hipStream_t);                             \
   template hipError_t launch_axpy_f64<T>(int, const double *, const T *, double *,              \

@@ -36,7 +36,7 @@ struct pp_poly {
 
 namespace {
 
-using ppk::Csr;
+using ppk::SpMat;
 
 constexpr int kMaxM = 256;
 constexpr int kMaxD = 256;
@@ -66,6 +66,8 @@ struct Arena {
   size_t dev_cap = 0;
   char *aux = nullptr;  // composed operator (scaled copy of A, scaled b); outlives `dev` carving
   size_t aux_cap = 0;
+  char *mat = nullptr;  // sliced-ELL copy of the call's matrix; outlives `dev` carving
+  size_t mat_cap = 0;
   double *host = nullptr;  // pinned
   size_t host_cap = 0;     // in doubles
 };
@@ -107,21 +109,24 @@ int ensure_arena(Arena *a, size_t dev_bytes, size_t host_doubles) {
   return PP_OK;
 }
 
-int ensure_aux(Arena *a, size_t bytes) {
-  if (bytes <= a->aux_cap) return PP_OK;
-  if (a->aux) {
+// Grow one of the arena's side buffers (aux, mat) to at least `bytes`.
+int ensure_side(char **buf, size_t *cap, size_t bytes) {
+  if (bytes <= *cap) return PP_OK;
+  if (*buf) {
     if (hipDeviceSynchronize() != hipSuccess) return PP_ERR_HIP;
-    (void)hipFree(a->aux);
-    a->aux = nullptr;
-    a->aux_cap = 0;
+    (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
   }
-  if (hipMalloc((void **)&a->aux, bytes) != hipSuccess) {
-    a->aux = nullptr;
+  if (hipMalloc((void **)buf, bytes) != hipSuccess) {
+    *buf = nullptr;
     return PP_ERR_NOMEM;
   }
-  a->aux_cap = bytes;
+  *cap = bytes;
   return PP_OK;
 }
+
+int ensure_aux(Arena *a, size_t bytes) { return ensure_side(&a->aux, &a->aux_cap, bytes); }
 
 // Sequential 256-byte aligned carving of the device arena.  With base == nullptr
 // it only measures.
@@ -143,7 +148,7 @@ inline int64_t pad_ld(int64_t n) { return (n + 63) / 64 * 64; }
 // Device workspace of one solve in compute type T.
 template <typename T>
 struct Work {
-  int n = 0, L = 0, G = 0;  // L = basis columns, G = CGS2 workgroups
+  int n = 0, L = 0;  // L = basis columns
   int64_t ldv = 0;
   T *V = nullptr, *P0 = nullptr, *P1 = nullptr, *Tb = nullptr, *Z = nullptr, *W = nullptr,
     *U = nullptr;
@@ -158,7 +163,6 @@ struct Work {
   void carve(C &c, int n_, int L_) {
     n = n_;
     L = L_;
-    G = ppk::orth_grid(n_);
     ldv = pad_ld(n_);
     V = c.template take<T>((size_t)ldv * L);
     P0 = c.template take<T>(ldv);
@@ -168,7 +172,9 @@ struct Work {
     W = c.template take<T>(ldv);
     U = c.template take<T>(ldv);
     const size_t tiles = (size_t)(n_ + ppk::kBlock - 1) / ppk::kBlock;
-    partial = c.template take<double>(std::max((size_t)L * G, tiles) + 64);
+    // CGS2 partials: up to L columns at the largest workgroup count of any sweep
+    const size_t gmax = (size_t)ppk::orth_grid(n_, ppk::kOrthMinRpt);
+    partial = c.template take<double>(std::max((size_t)L * gmax, tiles) + 64);
     colscale = c.template take<double>(L);
     hbuf = c.template take<double>(2 * (size_t)L + 8);
     coef1 = c.template take<double>(L);
@@ -251,16 +257,19 @@ struct PolyRef {
 // column indices, row pointers) and the gathered vector once, plus `vec_rw`
 // further vector reads/writes of n entries.
 template <typename T>
-double product_bytes(const Csr<T> &A, int vec_rw) {
-  return (double)A.nnz * (sizeof(T) + sizeof(int32_t)) + 4.0 * (A.n + 1) +
-         (double)sizeof(T) * A.n * (1 + vec_rw);
+double product_bytes(const SpMat<T> &A, int vec_rw) {
+  const double vecs = (double)sizeof(T) * A.n * (1 + vec_rw);
+  if (A.sp)  // sliced ELL: stored entries (padding included) and slice offsets
+    return (double)A.snnz * (sizeof(T) + sizeof(int32_t)) +
+           4.0 * ((A.n + ppk::kSlice - 1) / ppk::kSlice + 1) + vecs;
+  return (double)A.nnz * (sizeof(T) + sizeof(int32_t)) + 4.0 * (A.n + 1) + vecs;
 }
 
 // y_out = y_in + p(A) (gscale * g) for the step table; y_in may be nullptr
 // (zero) or equal y_out.  Uses P0, P1, Tb as chain temporaries.  Adds the
 // launches and their algorithmic bytes to *bytes / *launches when given.
 template <typename T>
-int run_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
+int run_chain(const SpMat<T> &A, const std::vector<ppn::Step> &steps, const T *g,
               const double *gscale, const T *y_in, T *y_out, T *P0, T *P1, T *Tb,
               hipStream_t s, Counters *cnt, double *bytes = nullptr,
               int64_t *launches = nullptr) {
@@ -320,7 +329,7 @@ int run_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
 // z <- A z + c[k] v from the top coefficient down: deg fused product + axpy
 // launches (one axpy launch for a constant polynomial).
 template <typename T>
-int run_horner(const Csr<T> &A, const std::vector<double> &c, const T *g, const double *gscale,
+int run_horner(const SpMat<T> &A, const std::vector<double> &c, const T *g, const double *gscale,
                T *out, T *P0, T *P1, hipStream_t s, Counters *cnt, double *bytes = nullptr,
                int64_t *launches = nullptr) {
   const int deg = (int)c.size() - 1;
@@ -353,7 +362,7 @@ int run_horner(const Csr<T> &A, const std::vector<double> &c, const T *g, const 
 // conjugate pair (t = A p, then p' = p - c1 t + c2 A t), the last launch writing
 // v - p' instead of p'.  d products, no accumulator vector.
 template <typename T>
-int run_op_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
+int run_op_chain(const SpMat<T> &A, const std::vector<ppn::Step> &steps, const T *g,
                  const double *gscale, T *w_out, T *P0, T *P1, T *Tb, hipStream_t s,
                  Counters *cnt, double *bytes = nullptr, int64_t *launches = nullptr) {
   auto account = [&](int vec_rw) {
@@ -390,26 +399,37 @@ int run_op_chain(const Csr<T> &A, const std::vector<ppn::Step> &steps, const T *
   return PP_OK;
 }
 
-// out = w_in - V(:, 0..nc) coef (chunks of kMaxCols columns); optional norm of out.
+template <typename T>
+constexpr bool is_f32() {
+  return sizeof(T) == sizeof(float);
+}
+
+// out = w_in - V(:, 0..nc) coef (chunks of kMaxCols columns); optional norm of out,
+// whose partials' workgroup count is returned in *G.
 template <typename T>
 int update_any(Work<T> &w, int nc, const double *coef, const T *w_in, T *out, bool norm,
-               hipStream_t s) {
+               hipStream_t s, int *G) {
+  const int rpt = ppk::orth_rpt(ppk::kOrthWrite, std::min(nc, ppk::kMaxCols), is_f32<T>());
   for (int c0 = 0; c0 < nc; c0 += ppk::kMaxCols) {
     const int cc = std::min(ppk::kMaxCols, nc - c0);
     const bool lastc = (c0 + cc >= nc);
-    PP_TRY_HIP(ppk::launch_update<T>(w.n, w.V + (int64_t)c0 * w.ldv, w.ldv, cc, coef + c0,
+    PP_TRY_HIP(ppk::launch_update<T>(w.n, rpt, w.V + (int64_t)c0 * w.ldv, w.ldv, cc, coef + c0,
                                      nullptr, 1.0, c0 == 0 ? w_in : out, out, false,
                                      norm && lastc, w.partial, s));
   }
+  if (G) *G = ppk::orth_grid(w.n, rpt);
   return PP_OK;
 }
 
+// partial dots of vec with V(:, 0..nc); *G receives the partials' workgroup count.
 template <typename T>
-int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s) {
+int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s, int *G) {
+  const int rpt = ppk::orth_rpt(ppk::kOrthRead, std::min(nc, ppk::kMaxCols), is_f32<T>());
   for (int c0 = 0; c0 < nc; c0 += ppk::kMaxCols) {
     const int cc = std::min(ppk::kMaxCols, nc - c0);
-    PP_TRY_HIP(ppk::launch_dots<T>(w.n, w.V, w.ldv, c0, cc, vec, w.partial, s));
+    PP_TRY_HIP(ppk::launch_dots<T>(w.n, rpt, w.V, w.ldv, c0, cc, vec, w.partial, s));
   }
+  *G = ppk::orth_grid(w.n, rpt);
   return PP_OK;
 }
 
@@ -417,7 +437,7 @@ int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s) {
 // hcol[0..j+1] receives column j of Hbar; *w0 an estimate of ||Op(V_j)||.
 // Returns PP_OK, or PP_WARN_NONFINITE when a coefficient is not finite.
 template <typename T>
-int arnoldi_step(const Csr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int j,
+int arnoldi_step(const SpMat<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int j,
                  hipStream_t s, Timers &tm, Counters &cnt, double *hcol, double *w0) {
   const T *vj = w.V + (int64_t)j * w.ldv;
   const double *sj = w.colscale + j;
@@ -450,20 +470,23 @@ int arnoldi_step(const Csr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, in
   double *h1 = w.hbuf, *h2 = w.hbuf + L, *nrm = w.hbuf + 2 * L;
   T *vnext = w.V + (int64_t)(j + 1) * w.ldv;
   // pass 1: h1 = V^T w
-  PP_TRY(dots_any<T>(w, nc, w.W, s));
-  PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, w.G, 0, nc, w.colscale, h1, w.coef1, s));
+  int G1 = 0, G2 = 0, G3 = 0;
+  PP_TRY(dots_any<T>(w, nc, w.W, s, &G1));
+  PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, G1, 0, nc, w.colscale, h1, w.coef1, s));
   if (nc <= ppk::kMaxCols) {
     // w -= V h1, fused with pass 2's dots
-    PP_TRY_HIP(ppk::launch_update<T>(w.n, w.V, w.ldv, nc, w.coef1, nullptr, 1.0, w.W, w.W, true,
-                                     false, w.partial, s));
+    const int rpt = ppk::orth_rpt(ppk::kOrthUpdateDots, nc, is_f32<T>());
+    PP_TRY_HIP(ppk::launch_update<T>(w.n, rpt, w.V, w.ldv, nc, w.coef1, nullptr, 1.0, w.W, w.W,
+                                     true, false, w.partial, s));
+    G2 = ppk::orth_grid(w.n, rpt);
   } else {
-    PP_TRY(update_any<T>(w, nc, w.coef1, w.W, w.W, false, s));
-    PP_TRY(dots_any<T>(w, nc, w.W, s));
+    PP_TRY(update_any<T>(w, nc, w.coef1, w.W, w.W, false, s, nullptr));
+    PP_TRY(dots_any<T>(w, nc, w.W, s, &G2));
   }
-  PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, w.G, 0, nc, w.colscale, h2, w.coef2, s));
+  PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, G2, 0, nc, w.colscale, h2, w.coef2, s));
   // pass 2 update, norm, store as column j+1
-  PP_TRY(update_any<T>(w, nc, w.coef2, w.W, vnext, true, s));
-  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, w.G, nrm, w.colscale + j + 1, s));
+  PP_TRY(update_any<T>(w, nc, w.coef2, w.W, vnext, true, s, &G3));
+  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, G3, nrm, w.colscale + j + 1, s));
   cnt.dots += 3;
   // three sweeps over nc basis columns; w read three times and written twice
   cnt.bytes_orth += (double)sizeof(T) * w.n * (3.0 * nc + 5.0);
@@ -490,8 +513,10 @@ int arnoldi_step(const Csr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, in
 template <typename T>
 int start_from_vector(Work<T> &w, const double *src, hipStream_t s, double *beta) {
   PP_TRY_HIP(ppk::launch_copy_from_f64<T>(w.n, src, w.V, s));
-  PP_TRY_HIP(ppk::launch_norm2<T>(w.n, w.V, nullptr, nullptr, w.partial, s));
-  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, w.G, w.misc, w.colscale, s));
+  const int rpt = ppk::orth_rpt(ppk::kOrthRead, 1, is_f32<T>());
+  PP_TRY_HIP(ppk::launch_norm2<T>(w.n, rpt, w.V, nullptr, nullptr, w.partial, s));
+  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, ppk::orth_grid(w.n, rpt), w.misc, w.colscale,
+                                     s));
   PP_TRY_HIP(hipMemcpyAsync(w.host, w.misc, sizeof(double), hipMemcpyDeviceToHost, s));
   PP_TRY_HIP(hipStreamSynchronize(s));
   *beta = w.host[0];
@@ -500,7 +525,7 @@ int start_from_vector(Work<T> &w, const double *src, hipStream_t s, double *beta
 
 // d Arnoldi steps on v0, harmonic Ritz values, Leja order, step table.
 template <typename T>
-int build_poly_impl(const Csr<T> &A, const double *v0, int d, Work<T> &w, hipStream_t s,
+int build_poly_impl(const SpMat<T> &A, const double *v0, int d, Work<T> &w, hipStream_t s,
                     Counters &cnt, Timers &tm, pp_poly *out) {
   double beta = 0.0;
   PP_TRY(start_from_vector<T>(w, v0, s, &beta));
@@ -540,7 +565,7 @@ int build_poly_impl(const Csr<T> &A, const double *v0, int d, Work<T> &w, hipStr
 // without a Cholesky failure is kept (Section IV); otherwise a failure at column
 // k keeps the solution of the leading (k-1) block, zeros above, and warns.
 template <typename T>
-int build_power_impl(const Csr<T> &A, const double *v0, int deg, bool auto_deg, Work<T> &w,
+int build_power_impl(const SpMat<T> &A, const double *v0, int deg, bool auto_deg, Work<T> &w,
                      double *gram, hipStream_t s, Counters &cnt, pp_poly *out, int *info_out) {
   const int L = deg + 2;
   PP_TRY_HIP(ppk::launch_copy_from_f64<T>(w.n, v0, w.V, s));
@@ -550,8 +575,9 @@ int build_power_impl(const Csr<T> &A, const double *v0, int deg, bool auto_deg, 
     cnt.spmvs++;
   }
   for (int j = 1; j < L; ++j) {
-    PP_TRY(dots_any<T>(w, j + 1, w.V + (int64_t)j * w.ldv, s));
-    PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, w.G, 0, j + 1, nullptr, gram + (size_t)j * L,
+    int G = 0;
+    PP_TRY(dots_any<T>(w, j + 1, w.V + (int64_t)j * w.ldv, s, &G));
+    PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, G, 0, j + 1, nullptr, gram + (size_t)j * L,
                                        nullptr, s));
   }
   cnt.dots += 2;  // the paper's two block inner products
@@ -637,7 +663,7 @@ struct Lsq {
 // One GMRES(m) cycle from V(:,0) (colscale[0] set) with start residual norm beta.
 // Returns steps taken in *k and the solution coefficients in y.
 template <typename T>
-int gmres_cycle(const Csr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int m,
+int gmres_cycle(const SpMat<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int m,
                 double beta, double tol_abs, double bscale, int max_steps, hipStream_t s,
                 Timers &tm, Counters &cnt, std::vector<double> &y, int *k, double *res,
                 bool *nonfinite) {
@@ -678,7 +704,7 @@ int gmres_cycle(const Csr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int
 
 // x_out = x_in + p(A) V(:,0..k) (colscale o y)   [x_in may equal x_out, or be nullptr]
 template <typename T>
-int cycle_update(const Csr<T> &A, const PolyRef &pr, Work<T> &w, int k,
+int cycle_update(const SpMat<T> &A, const PolyRef &pr, Work<T> &w, int k,
                  const std::vector<double> &y, const T *x_in, T *x_out, hipStream_t s,
                  Counters &cnt) {
   if (k <= 0) return PP_OK;
@@ -686,13 +712,14 @@ int cycle_update(const Csr<T> &A, const PolyRef &pr, Work<T> &w, int k,
   PP_TRY_HIP(hipMemcpyAsync(w.ybuf, w.host + 2 * w.L + 8, k * sizeof(double),
                             hipMemcpyHostToDevice, s));
   const bool poly = pr.active();
+  const int rpt = ppk::orth_rpt(ppk::kOrthWrite, std::min(k, ppk::kMaxCols), is_f32<T>());
   for (int c0 = 0; c0 < k; c0 += ppk::kMaxCols) {
     const int cc = std::min(ppk::kMaxCols, k - c0);
     T *dst = poly ? w.U : x_out;
     const T *src = poly ? (c0 == 0 ? nullptr : w.U) : (c0 == 0 ? x_in : x_out);
-    PP_TRY_HIP(ppk::launch_update<T>(w.n, w.V + (int64_t)c0 * w.ldv, w.ldv, cc, w.ybuf + c0,
-                                     w.colscale + c0, -1.0, src, dst, false, false, w.partial,
-                                     s));
+    PP_TRY_HIP(ppk::launch_update<T>(w.n, rpt, w.V + (int64_t)c0 * w.ldv, w.ldv, cc,
+                                     w.ybuf + c0, w.colscale + c0, -1.0, src, dst, false, false,
+                                     w.partial, s));
   }
   if (poly && pr.power()) {
     PP_TRY(run_horner<T>(A, *pr.coeffs, w.U, nullptr, w.Z, w.P0, w.P1, s, &cnt));
@@ -710,12 +737,113 @@ int check_csr(const pp_csr *A) {
     return PP_ERR_ARG;
   if (!A->row_ptr || (A->nnz > 0 && (!A->col_ind || !A->vals))) return PP_ERR_ARG;
   if (A->dtype != PP_F64 && A->dtype != PP_F32) return PP_ERR_ARG;
+  if (A->layout != PP_LAYOUT_AUTO && A->layout != PP_LAYOUT_CSR && A->layout != PP_LAYOUT_SELL)
+    return PP_ERR_ARG;
   return PP_OK;
 }
 
+// The sliced-ELL copy of a call's matrix (see SpMat): built on the device from
+// the CSR arrays into the arena's matrix buffer.  `use` is false when the
+// caller asked for CSR, or (PP_LAYOUT_AUTO) when the padding would exceed a
+// quarter of nnz plus one slice of the longest row, or when the stored entries
+// would not fit int32 offsets.
+struct SellCopy {
+  bool use = false;
+  int64_t snnz = 0;
+  int32_t *sp = nullptr, *sci = nullptr;
+  double *va64 = nullptr;
+  float *va32 = nullptr;
+};
+
+// want64 / want32: value arrays to fill (FP64 from A's values; FP32 from src32
+// when given, else from A's values).  Uses the main arena as scratch, so call it
+// before carving the solve's workspace.
+int make_sell(const pp_csr *A, bool want64, bool want32, const float *src32, hipStream_t s,
+              SellCopy *out) {
+  *out = SellCopy{};
+  if (A->layout == PP_LAYOUT_CSR) return PP_OK;
+  Arena *ar = nullptr;
+  PP_TRY(current_arena(&ar));
+  const int n = (int)A->n;
+  const int ns = (n + ppk::kSlice - 1) / ppk::kSlice;
+  Carver meas(nullptr);
+  meas.take<int32_t>(ns);
+  meas.take<int32_t>(ns + 1);
+  meas.take<int32_t>(ppk::scan_tmp_size(ns));
+  meas.take<int32_t>(64);
+  PP_TRY(ensure_arena(ar, meas.off + 256, 64));
+  Carver c(ar->dev);
+  int32_t *wlen = c.take<int32_t>(ns);
+  int32_t *spt = c.take<int32_t>(ns + 1);
+  int32_t *tmp = c.take<int32_t>(ppk::scan_tmp_size(ns));
+  int32_t *maxlen = c.take<int32_t>(64);
+  PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, maxlen, s));
+  PP_TRY_HIP(ppk::launch_sell_widths(n, ns, A->row_ptr, wlen, maxlen, s));
+  PP_TRY_HIP(ppk::launch_exclusive_scan(ns, wlen, spt, tmp, s));
+  int32_t *h = reinterpret_cast<int32_t *>(ar->host);
+  PP_TRY_HIP(hipMemcpyAsync(h, spt + ns, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipMemcpyAsync(h + 1, maxlen, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  const int64_t longest = h[1];
+  if ((int64_t)ppk::kSlice * longest * ns >= ((int64_t)1 << 31)) return PP_OK;
+  const int64_t snnz = h[0];
+  if (A->layout == PP_LAYOUT_AUTO && snnz > A->nnz + A->nnz / 4 + ppk::kSlice * longest)
+    return PP_OK;
+  const int64_t cap = std::max<int64_t>(snnz, 1);
+  Carver mm(nullptr);
+  mm.take<int32_t>(ns + 1);
+  mm.take<int32_t>(cap);
+  if (want64) mm.take<double>(cap);
+  if (want32) mm.take<float>(cap);
+  PP_TRY(ensure_side(&ar->mat, &ar->mat_cap, mm.off + 256));
+  Carver m(ar->mat);
+  out->sp = m.take<int32_t>(ns + 1);
+  out->sci = m.take<int32_t>(cap);
+  if (want64) out->va64 = m.take<double>(cap);
+  if (want32) out->va32 = m.take<float>(cap);
+  PP_TRY_HIP(hipMemcpyAsync(out->sp, spt, (ns + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  PP_TRY_HIP(ppk::launch_sell_fill_cols(n, ns, A->row_ptr, A->col_ind, out->sp, out->sci, s));
+  if (want64) {
+    if (A->dtype != PP_F64) return PP_ERR_ARG;
+    PP_TRY_HIP((ppk::launch_sell_fill_vals<double, double>(
+        n, ns, A->row_ptr, static_cast<const double *>(A->vals), out->sp, out->va64, s)));
+  }
+  if (want32) {
+    if (src32 || A->dtype == PP_F32) {
+      const float *src = src32 ? src32 : static_cast<const float *>(A->vals);
+      PP_TRY_HIP((ppk::launch_sell_fill_vals<float, float>(n, ns, A->row_ptr, src, out->sp,
+                                                           out->va32, s)));
+    } else {
+      PP_TRY_HIP((ppk::launch_sell_fill_vals<double, float>(
+          n, ns, A->row_ptr, static_cast<const double *>(A->vals), out->sp, out->va32, s)));
+    }
+  }
+  out->use = true;
+  out->snnz = snnz;
+  return PP_OK;
+}
+
+// Attach the sliced-ELL copy (when built) to a view of type T.
 template <typename T>
-Csr<T> view(const pp_csr *A, const void *vals) {
-  return Csr<T>{(int)A->n, (int)A->nnz, A->row_ptr, A->col_ind, static_cast<const T *>(vals)};
+SpMat<T> with_sell(SpMat<T> M, const SellCopy &c) {
+  if (!c.use) return M;
+  M.sp = c.sp;
+  M.sci = c.sci;
+  if constexpr (sizeof(T) == sizeof(double)) M.sva = c.va64;
+  else M.sva = c.va32;
+  M.snnz = (int)c.snnz;
+  return M;
+}
+
+void note_layout(pp_stats *st, const pp_csr *A, const SellCopy &c) {
+  if (!st) return;
+  st->layout_used = c.use ? PP_LAYOUT_SELL : PP_LAYOUT_CSR;
+  st->nnz_stored = c.use ? c.snnz : A->nnz;
+}
+
+template <typename T>
+SpMat<T> view(const pp_csr *A, const void *vals) {
+  return SpMat<T>{(int)A->n, (int)A->nnz, A->row_ptr, A->col_ind, static_cast<const T *>(vals)};
 }
 
 template <typename T>
@@ -723,13 +851,16 @@ int apply_impl(const pp_csr *A, const pp_poly *p, const void *v, void *y, hipStr
   Arena *ar = nullptr;
   PP_TRY(current_arena(&ar));
   const int n = (int)A->n;
+  SellCopy sc;
+  if (p->kind == 1 || !p->steps.empty())
+    PP_TRY(make_sell(A, sizeof(T) == 8, sizeof(T) == 4, nullptr, s, &sc));
   Carver meas(nullptr);
   T *bufs[3];
   for (auto &b : bufs) b = meas.take<T>(pad_ld(n));
   PP_TRY(ensure_arena(ar, meas.off + 256, 64));
   Carver c(ar->dev);
   for (auto &b : bufs) b = c.take<T>(pad_ld(n));
-  const Csr<T> M = view<T>(A, A->vals);
+  const SpMat<T> M = with_sell(view<T>(A, A->vals), sc);
   const T *vv = static_cast<const T *>(v);
   T *yy = static_cast<T *>(y);
   if (p->kind == 1) {
@@ -749,6 +880,8 @@ int build_impl(const pp_csr *A, const double *v0, int d, hipStream_t s, pp_poly 
   Arena *ar = nullptr;
   PP_TRY(current_arena(&ar));
   const int n = (int)A->n;
+  SellCopy sc;
+  PP_TRY(make_sell(A, sizeof(T) == 8, sizeof(T) == 4, nullptr, s, &sc));
   Work<T> w;
   Carver meas(nullptr);
   w.carve(meas, n, d + 1);
@@ -760,7 +893,7 @@ int build_impl(const pp_csr *A, const double *v0, int d, hipStream_t s, pp_poly 
   Timers tm;
   pp_poly *p = new pp_poly();
   p->dtype = A->dtype;
-  int rc = build_poly_impl<T>(view<T>(A, A->vals), v0, d, w, s, cnt, tm, p);
+  int rc = build_poly_impl<T>(with_sell(view<T>(A, A->vals), sc), v0, d, w, s, cnt, tm, p);
   if (rc < 0) {
     delete p;
     return rc;
@@ -792,8 +925,10 @@ int worst(int a, int b) {
 
 // ||b|| in FP64 (device) -> host.
 int norm_f64(Work<double> &w, const double *x, hipStream_t s, double *out) {
-  PP_TRY_HIP(ppk::launch_norm2<double>(w.n, x, nullptr, nullptr, w.partial, s));
-  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, w.G, w.misc + 1, nullptr, s));
+  const int rpt = ppk::orth_rpt(ppk::kOrthRead, 1, false);
+  PP_TRY_HIP(ppk::launch_norm2<double>(w.n, rpt, x, nullptr, nullptr, w.partial, s));
+  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, ppk::orth_grid(w.n, rpt), w.misc + 1, nullptr,
+                                     s));
   PP_TRY_HIP(hipMemcpyAsync(w.host, w.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
   PP_TRY_HIP(hipStreamSynchronize(s));
   *out = w.host[0];
@@ -801,7 +936,7 @@ int norm_f64(Work<double> &w, const double *x, hipStream_t s, double *out) {
 }
 
 // r = b - A x into V(:,0), colscale[0] = 1/||r||; returns ||r||.
-int residual_f64(const Csr<double> &A, Work<double> &w, const double *b, const double *x,
+int residual_f64(const SpMat<double> &A, Work<double> &w, const double *b, const double *x,
                  hipStream_t s, double *beta) {
   int nt = 0;
   PP_TRY_HIP(ppk::launch_residual<double>(A, b, x, w.V, w.partial, &nt, s));
@@ -818,6 +953,9 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
   PP_TRY(current_arena(&ar));
   const int n = (int)in.A->n;
   const int L = std::max(in.m, in.o.poly ? 0 : in.d) + 1;
+  SellCopy sc;
+  PP_TRY(make_sell(in.A, true, false, nullptr, in.s, &sc));
+  note_layout(st, in.A, sc);
   Work<double> w;
   Carver meas(nullptr);
   w.carve(meas, n, L);
@@ -827,7 +965,7 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
   w.carve(c, n, L);
   xsave = c.take<double>(n);
   w.host = ar->host;
-  const Csr<double> A = view<double>(in.A, in.A->vals);
+  const SpMat<double> A = with_sell(view<double>(in.A, in.A->vals), sc);
   hipStream_t s = in.s;
   Counters cnt;
   cnt.history = in.o.history;
@@ -938,25 +1076,31 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
   const int n = (int)in.A->n;
   const int64_t nnz = in.A->nnz;
   const int L = std::max(in.m, in.o.poly ? 0 : in.d) + 1;
+  SellCopy sc;
+  PP_TRY(make_sell(in.A, true, true, in.o.vals_f32, in.s, &sc));
+  note_layout(st, in.A, sc);
+  // the FP32 CSR values are needed only when the products run on CSR
+  const bool cast32 = !in.o.vals_f32 && !sc.use;
   Work<float> w;
   Work<double> w64;  // only the residual / norm pieces are used
   Carver meas(nullptr);
   w.carve(meas, n, L);
   w64.carve(meas, n, 1);
-  float *vals32 = in.o.vals_f32 ? nullptr : meas.take<float>(nnz > 0 ? nnz : 1);
+  float *vals32 = cast32 ? meas.take<float>(nnz > 0 ? nnz : 1) : nullptr;
   double *xsave = meas.take<double>(n);
   PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles() + 16));
   Carver c(ar->dev);
   w.carve(c, n, L);
   w64.carve(c, n, 1);
-  vals32 = in.o.vals_f32 ? nullptr : c.take<float>(nnz > 0 ? nnz : 1);
+  vals32 = cast32 ? c.take<float>(nnz > 0 ? nnz : 1) : nullptr;
   xsave = c.take<double>(n);
   w.host = ar->host;
   w64.host = ar->host;
   hipStream_t s = in.s;
-  const Csr<double> A64 = view<double>(in.A, in.A->vals);
-  if (!in.o.vals_f32) PP_TRY_HIP(ppk::launch_cast_f32(nnz, (const double *)in.A->vals, vals32, s));
-  const Csr<float> A32 = view<float>(in.A, in.o.vals_f32 ? (const void *)in.o.vals_f32 : vals32);
+  const SpMat<double> A64 = with_sell(view<double>(in.A, in.A->vals), sc);
+  if (cast32) PP_TRY_HIP(ppk::launch_cast_f32(nnz, (const double *)in.A->vals, vals32, s));
+  const SpMat<float> A32 = with_sell(
+      view<float>(in.A, in.o.vals_f32 ? (const void *)in.o.vals_f32 : (const void *)vals32), sc);
   Counters cnt;
   cnt.history = in.o.history;
   cnt.history_cap = in.o.history ? in.o.history_cap : 0;
@@ -1036,8 +1180,10 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
       break;
     }
     // V32(:,0) = (float)(r / beta), with its FP32 norm
-    PP_TRY_HIP(ppk::launch_norm2<double>(n, r64, w64.colscale, w.V, w.partial, s));
-    PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, w.G, w.misc, w.colscale, s));
+    const int rpt = ppk::orth_rpt(ppk::kOrthWrite, 1, true);
+    PP_TRY_HIP(ppk::launch_norm2<double>(n, rpt, r64, w64.colscale, w.V, w.partial, s));
+    PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, ppk::orth_grid(n, rpt), w.misc, w.colscale,
+                                       s));
     PP_TRY_HIP(hipMemcpyAsync(w.host, w.misc, sizeof(double), hipMemcpyDeviceToHost, s));
     PP_TRY_HIP(hipMemcpyAsync(w64.misc + 2, &beta, sizeof(double), hipMemcpyHostToDevice, s));
     PP_TRY_HIP(hipStreamSynchronize(s));
@@ -1173,6 +1319,8 @@ int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_deg
   const int n = (int)A->n, L = deg + 2;
   auto go = [&](auto tag) -> int {
     using T = decltype(tag);
+    SellCopy sc;
+    PP_TRY(make_sell(A, sizeof(T) == 8, sizeof(T) == 4, nullptr, s, &sc));
     Work<T> w;
     Carver meas(nullptr);
     w.carve(meas, n, L);
@@ -1185,8 +1333,8 @@ int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_deg
     Counters cnt;
     pp_poly *p = new pp_poly();
     p->dtype = A->dtype;
-    int rc = build_power_impl<T>(view<T>(A, A->vals), v0, deg, auto_degree != 0, w, gram, s, cnt,
-                                 p, info_out);
+    int rc = build_power_impl<T>(with_sell(view<T>(A, A->vals), sc), v0, deg, auto_degree != 0,
+                                 w, gram, s, cnt, p, info_out);
     if (rc < 0) {
       delete p;
       return rc;
@@ -1307,11 +1455,12 @@ void pp_release_workspace(void) {
   (void)hipGetDevice(&cur);
   for (size_t dev = 0; dev < g_arena.size(); ++dev) {
     Arena &a = g_arena[dev];
-    if (!a.dev && !a.host) continue;
+    if (!a.dev && !a.host && !a.aux && !a.mat) continue;
     (void)hipSetDevice((int)dev);
     (void)hipDeviceSynchronize();
     if (a.dev) (void)hipFree(a.dev);
     if (a.aux) (void)hipFree(a.aux);
+    if (a.mat) (void)hipFree(a.mat);
     if (a.host) (void)hipHostFree(a.host);
     a = Arena{};
   }

@@ -59,12 +59,16 @@ APPLY_CASES = [("cd2d_32", 10), ("cd3d_16_pe50", 12), ("rand_777", 9), ("rand_lo
                ("rand_5", 5), ("one", 1)]
 
 
+LAYOUTS = ["csr", "sell"]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("name,d", APPLY_CASES)
-def test_apply_matches_oracle_fp64(B, name, d):
+def test_apply_matches_oracle_fp64(B, name, d, layout):
     Ah = _matrix(name)
     As = Ah.to_scipy()
     roots, s = opoly.build_poly(As, W.uniform(Ah.n, 11), d)
-    A = B.CSRMatrix.from_host(Ah)
+    A = B.CSRMatrix.from_host(Ah, layout=layout)
     p = B.pp_poly_from_roots(Ah.n, roots)
     for seed in (1, 2):
         v = W.uniform(Ah.n, seed)
@@ -72,12 +76,13 @@ def test_apply_matches_oracle_fp64(B, name, d):
         assert _rel(y, opoly.apply_poly(As, roots, v)) <= 1e-12, name
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("name,d", APPLY_CASES[:4])
-def test_apply_matches_oracle_fp32(B, name, d):
+def test_apply_matches_oracle_fp32(B, name, d, layout):
     Ah = _matrix(name)
     As = Ah.to_scipy()
     roots, s = opoly.build_poly(As, W.uniform(Ah.n, 11), d)
-    A = B.CSRMatrix.from_host(Ah, dtype=torch.float32)
+    A = B.CSRMatrix.from_host(Ah, dtype=torch.float32, layout=layout)
     p = B.pp_poly_from_roots(Ah.n, roots, dtype="f32")
     v = W.uniform(Ah.n, 3)
     y = B.pp_apply(A, p, _up(v, torch.float32)).cpu().numpy().astype(np.float64)
@@ -96,19 +101,21 @@ ROOT_SETS = {
 }
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("key", list(ROOT_SETS))
-def test_apply_chain_variants(B, key):
+def test_apply_chain_variants(B, key, layout):
     Ah = W.random_csr(1000, 8, seed=12, diag_shift=4.0)
     As = Ah.to_scipy()
     roots = np.array(ROOT_SETS[key], dtype=complex)
-    A = B.CSRMatrix.from_host(Ah)
+    A = B.CSRMatrix.from_host(Ah, layout=layout)
     p = B.pp_poly_from_roots(Ah.n, roots)
     v = W.uniform(Ah.n, 13)
     y = B.pp_apply(A, p, _up(v)).cpu().numpy()
     assert _rel(y, opoly.apply_poly(As, roots, v)) <= 1e-12, key
 
 
-def test_apply_with_empty_rows(B):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_apply_with_empty_rows(B, layout):
     n = 700
     rng = np.random.default_rng(14)
     counts = rng.integers(0, 4, n)
@@ -121,7 +128,7 @@ def test_apply_with_empty_rows(B):
     roots = np.array([3.0, 1.0 + 1.0j, 1.0 - 1.0j, -2.0])
     p = B.pp_poly_from_roots(n, roots)
     v = W.uniform(n, 15)
-    y = B.pp_apply(B.CSRMatrix.from_host(Ah), p, _up(v)).cpu().numpy()
+    y = B.pp_apply(B.CSRMatrix.from_host(Ah, layout=layout), p, _up(v)).cpu().numpy()
     assert _rel(y, opoly.apply_poly(Ah.to_scipy(), roots, v)) <= 1e-12
 
 
@@ -152,8 +159,8 @@ def test_build_poly_degree_reduced(B):
     assert r.size == 3 and np.allclose(r, [1.0, 2.0, 4.0], rtol=1e-10)
 
 
-def _solve_both(B, Ah, b, v0, m, d, tol, max_iters=5000, op_form="pi"):
-    A = B.CSRMatrix.from_host(Ah)
+def _solve_both(B, Ah, b, v0, m, d, tol, max_iters=5000, op_form="pi", layout="auto"):
+    A = B.CSRMatrix.from_host(Ah, layout=layout)
     x, st = B.pp_gmres_solve(A, _up(b), m=m, d=d, tol=tol, v0=_up(v0), max_iters=max_iters,
                              op_form=op_form)
     xo, so = ogmres.pp_gmres(Ah.to_scipy(), b, m, tol, v0=v0, d=d, max_iters=max_iters)
@@ -176,20 +183,22 @@ def test_solve_config1_full(B, d, op_form):
     _assert_parity(st, so, xg, xo, P.tol)
 
 
-def test_solve_cd3d_ragged_tiles(B):
-    P = W.config(2, N=23)   # n = 12167: 48 full tiles and a ragged one
-    xg, st, xo, so = _solve_both(B, P.A, P.b, P.v0, P.m, 10, P.tol)
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_solve_cd3d_ragged_tiles(B, layout):
+    P = W.config(2, N=23)   # n = 12167: 48 full tiles and a ragged one (190 slices, last partial)
+    xg, st, xo, so = _solve_both(B, P.A, P.b, P.v0, P.m, 10, P.tol, layout=layout)
     _assert_parity(st, so, xg, xo, P.tol)
+    assert st.layout_used == layout
 
 
-@pytest.mark.parametrize("op_form", ["pi", "p"])
-def test_solve_complex_roots(B, op_form):
+@pytest.mark.parametrize("op_form,layout", [("pi", "auto"), ("p", "auto"), ("pi", "sell")])
+def test_solve_complex_roots(B, op_form, layout):
     Ah = W.random_csr(777, 12, seed=5, diag_shift=4.0)
     b = W.normal(777, 3)
     v0 = W.uniform(777, 4)
     roots, _ = opoly.build_poly(Ah.to_scipy(), v0, 6)
     assert np.any(roots.imag != 0)
-    xg, st, xo, so = _solve_both(B, Ah, b, v0, 20, 6, 1e-10, op_form=op_form)
+    xg, st, xo, so = _solve_both(B, Ah, b, v0, 20, 6, 1e-10, op_form=op_form, layout=layout)
     _assert_parity(st, so, xg, xo, 1e-10)
 
 
@@ -432,3 +441,65 @@ def test_history_and_timing_fields(B):
     assert h.size == st.iters and h[-1] < P.tol and np.all(np.diff(h) <= 1e-12 * h[:-1])
     assert st.t_chain > 0 and st.t_orth > 0 and st.bytes_chain > 0 and st.launches_chain > 0
     assert st.t_total >= st.t_poly > 0
+
+
+# ---- sliced-ELL layout: selection and agreement with CSR
+def test_auto_layout_choice(B):
+    P = W.config(1, N=40)       # 5-point stencil: padding only at the grid boundary
+    x, st = B.pp_gmres_solve(B.CSRMatrix.from_host(P.A), _up(P.b), m=P.m, d=P.d, tol=P.tol,
+                             v0=_up(P.v0))
+    assert st.layout_used == "sell"
+    ns = -(-P.A.n // 64)
+    assert P.A.nnz <= st.nnz_stored <= 64 * ns * 5
+    # one long row per slice: sliced ELL would store ~16x nnz, so AUTO keeps CSR
+    n = 1024
+    counts = np.ones(n, np.int64)
+    counts[::64] = 60
+    rng = np.random.default_rng(31)
+    rows = []
+    for i, c in enumerate(counts):
+        others = rng.choice(n - 1, c - 1, replace=False)
+        rows.append(np.sort(np.concatenate([[i], others + (others >= i)])))
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum([r.size for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    va = rng.uniform(-1, 1, ci.size) + 8.0 * (ci == np.repeat(np.arange(n), np.diff(rp)))
+    Ah = W.CSR(n, rp, ci, va)
+    b = W.normal(n, 32)
+    xa, sa = B.pp_gmres_solve(B.CSRMatrix.from_host(Ah), _up(b), m=20, d=4, tol=1e-10,
+                              v0=_up(W.uniform(n, 33)))
+    assert sa.layout_used == "csr" and sa.nnz_stored == Ah.nnz
+    xs, ss = B.pp_gmres_solve(B.CSRMatrix.from_host(Ah, layout="sell"), _up(b), m=20, d=4,
+                              tol=1e-10, v0=_up(W.uniform(n, 33)))
+    assert ss.layout_used == "sell" and ss.nnz_stored == 64 * (n // 64) * 60
+    assert sa.iters == ss.iters and _rel(xs.cpu().numpy(), xa.cpu().numpy()) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_ir"])
+def test_layouts_agree_on_solve(B, precision):
+    P = W.config(3, N=20)       # 27-point stencil, n = 8000 (125 slices)
+    A = B.CSRMatrix.from_host(P.A)
+    out = {}
+    for layout in LAYOUTS:
+        x, st = B.pp_gmres_solve(A.with_layout(layout), _up(P.b), m=P.m, d=P.d, tol=P.tol,
+                                 v0=_up(P.v0), precision=precision)
+        assert st.layout_used == layout and st.relres_true < P.tol
+        out[layout] = (x.cpu().numpy(), st)
+    (xc, sc), (xs, ss) = out["csr"], out["sell"]
+    # the layouts differ only in summation rounding; the FP32 inner cycles may
+    # stop a step apart on their 1e-5 implicit test
+    assert abs(sc.iters - ss.iters) <= (1 if precision == "f64" else 2 * max(sc.outer, 1))
+    assert _rel(xs, xc) <= (1e-8 if precision == "f64" else 1e-6)
+
+
+def test_refinement_with_given_fp32_values_on_sell(B):
+    P = W.config(1)
+    A = B.CSRMatrix.from_host(P.A, layout="sell")
+    v32 = _up(P.A.vals, torch.float32)
+    x1, s1 = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=P.d, tol=1e-10, v0=_up(P.v0),
+                              precision="f32_ir", vals_f32=v32)
+    x2, s2 = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=P.d, tol=1e-10, v0=_up(P.v0),
+                              precision="f32_ir")
+    assert s1.layout_used == s2.layout_used == "sell"
+    # the given FP32 values equal the internal cast: identical runs
+    assert s1.iters == s2.iters and np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
