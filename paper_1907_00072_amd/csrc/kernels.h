@@ -14,14 +14,18 @@ namespace ppk {
 
 constexpr int kBlock = 256;   // threads per workgroup (4 wavefronts of 64)
 constexpr int kMaxCols = 64;  // columns handled by one fused CGS2 sweep
-constexpr int kSlice = 64;    // rows per sliced-ELL slice (one wavefront)
+constexpr int kSlice = 64;    // rows per slice of the sliced copy (one wavefront)
+constexpr int kSellBatch = 8; // slots per row whose loads are in flight together
 
-// Sparse matrix view on the device: CSR, plus an optional sliced-ELL copy.
-// Sliced ELL groups the rows in slices of kSlice; slice s stores
-// w_s = (sp[s+1] - sp[s]) / kSlice entries per row column-major (entry j of
-// row kSlice*s + l at sp[s] + kSlice*j + l), rows shorter than w_s padded with
+// Sparse matrix view on the device: CSR, plus an optional sliced copy.
+// The sliced copy groups the rows in slices of kSlice; slice s has
+// w_s = (sp[s+1] - sp[s]) / kSlice slots per row, stored column-major (slot j
+// of row kSlice*s + l at sp[s] + kSlice*j + l).  A diagonal slice (sflag[s] =
+// 1) holds in slot j the entries on diagonal soff[s*dmax + j] (column = row +
+// offset), zero where a row has none; an explicit-column slice (sflag[s]
+// = 0) holds row l's entries in order with their columns in sci, padded with
 // column -1 and value 0.  When sp != nullptr the product kernels read only the
-// sliced-ELL arrays (sp, sci, sva) and never rp/ci/va.
+// sliced arrays and never rp/ci/va.
 template <typename T>
 struct SpMat {
   int n;
@@ -29,10 +33,14 @@ struct SpMat {
   const int32_t *rp;
   const int32_t *ci;
   const T *va;
-  const int32_t *sp = nullptr;  // [ceil(n / kSlice) + 1]
-  const int32_t *sci = nullptr; // [snnz]
-  const T *sva = nullptr;       // [snnz]
-  int snnz = 0;                 // stored entries including padding
+  const int32_t *sp = nullptr;    // [ceil(n / kSlice) + 1]
+  const int32_t *sflag = nullptr; // [ceil(n / kSlice)]
+  const int32_t *soff = nullptr;  // [ns * dmax + kSellBatch slack]
+  const int32_t *sci = nullptr;   // [snnz] (nullptr when every slice is diagonal)
+  const T *sva = nullptr;         // [snnz]
+  int snnz = 0;                   // stored slots x kSlice, padding included
+  int snnz_ell = 0;               // the part in explicit-column slices
+  int dmax = 0;                   // most slots of a diagonal slice (soff stride)
 };
 
 // One launch of the fused product + root-update chain.
@@ -159,21 +167,25 @@ hipError_t launch_sort_rows(int n, const int32_t *rp, int32_t *ci, T *va, hipStr
 hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const double *lam,
                            const double *x, double *g, hipStream_t stream);
 
-// Sliced-ELL construction from CSR (ns = ceil(n / kSlice) slices).
-// widths: wlen[s] = kSlice * (longest row of slice s), wrapping modulo 2^32;
-//         *maxlen = max(*maxlen, longest row) (caller zeroes it first; the
-//         caller rejects the layout when kSlice * maxlen * ns >= 2^31, which
-//         also covers any wrap).
-// Then sp = exclusive scan of wlen (launch_exclusive_scan), and the fills write
-// every stored entry, padding included.
-hipError_t launch_sell_widths(int n, int ns, const int32_t *rp, int32_t *wlen, int32_t *maxlen,
-                              hipStream_t stream);
-hipError_t launch_sell_fill_cols(int n, int ns, const int32_t *rp, const int32_t *ci,
-                                 const int32_t *sp, int32_t *sci, hipStream_t stream);
-// sva = (D) va in sliced-ELL order (S, D in {float, double}).
+// Sliced-copy construction from CSR (ns = ceil(n / kSlice) slices).
+// plan: wlen[s] = kSlice * (slots of slice s) and flag[s] (1 = diagonal slice);
+//       stat[0] = longest row, stat[1] = kSlice * slots of the explicit-column
+//       slices, stat[2] = most slots of a diagonal slice (the caller zeroes
+//       stat[0..2] first and rejects the copy when 96 * stat[0] * ns >= 2^31,
+//       which also covers any wrap).
+// Then sp = exclusive scan of wlen (launch_exclusive_scan), fill_idx writes the
+// diagonal offsets (soff[s * dmax + j], dmax = stat[2]) / explicit columns and
+// fill_vals the values (padding included).
+hipError_t launch_slice_plan(int n, int ns, const int32_t *rp, const int32_t *ci, int32_t *wlen,
+                             int32_t *flag, int32_t *stat, hipStream_t stream);
+hipError_t launch_slice_fill_idx(int n, int ns, int dmax, const int32_t *rp, const int32_t *ci,
+                                 const int32_t *sp, const int32_t *flag, int32_t *soff,
+                                 int32_t *sci, hipStream_t stream);
+// sva = (D) va in sliced order (S, D in {float, double}).
 template <typename S, typename D>
-hipError_t launch_sell_fill_vals(int n, int ns, const int32_t *rp, const S *va, const int32_t *sp,
-                                 D *sva, hipStream_t stream);
+hipError_t launch_slice_fill_vals(int n, int ns, const int32_t *rp, const int32_t *ci, const S *va,
+                                  const int32_t *sp, const int32_t *flag, D *sva,
+                                  hipStream_t stream);
 
 // Left Jacobi scaling: va_out[k] = va[k] / a_ii and b_out[i] = b[i] / a_ii for the
 // row i of entry k (a_ii the sum of the row's diagonal entries); *bad is set to 1

@@ -18,14 +18,20 @@
 //   nonzero; own-row operands are fetched before the reduction; streamed
 //   vectors use non-temporal loads and stores so the L2 keeps the gathered
 //   vector.
-// * When the view carries a sliced-ELL copy (64-row slices, column-major inside a
+// * When the view carries a sliced copy (64-row slices, column-major inside a
 //   slice) the same kernels run on it instead: lane l of a wavefront owns row
-//   64 s + l, loads of entry j of the slice's 64 rows are one contiguous burst,
-//   and the gather for entry j touches one diagonal of 64 consecutive rows (a
-//   few cache lines) rather than every diagonal of a handful of rows as in the
-//   CSR-stream tile.  No row pointers, no LDS and no barrier are needed.  This
-//   is what lets the FP32 chain reach the copy bandwidth; the CSR path is kept
-//   for matrices whose slices would need heavy padding.
+//   64 s + l and the loads of slot j of the slice's 64 rows are one contiguous
+//   burst.  A slice whose rows use few distinct diagonals (col - row) is stored
+//   by diagonal: slot j holds diagonal soff[j] for all 64 rows (zero where a
+//   row lacks it), so no column indices are stored and the gather becomes a
+//   contiguous shifted load.  Other slices store explicit columns (ELL); their
+//   gather for slot j still touches one entry of 64 consecutive rows rather than
+//   every diagonal of a handful of rows as in the CSR-stream tile.  No row
+//   pointers, no LDS and no barrier are needed.  The CSR path is kept for
+//   matrices whose slices would need heavy padding.
+// * Workgroups of the sparse products take their 256-row tiles in groups of 16
+//   consecutive tiles per XCD (workgroups are dealt to the 8 XCDs round-robin),
+//   so most of a tile's neighbouring rows were fetched into the same XCD's L2.
 // * The Gram-Schmidt kernels keep one basis row per thread in registers (a
 //   template bound on the column count, in steps of 8), so each sweep reads
 //   every basis column once and updates the vector and accumulates the next
@@ -36,6 +42,8 @@
 //   memory, then a second kernel), with no floating-point atomics, so results
 //   are bitwise reproducible.
 #include <hip/hip_runtime.h>
+
+#include <climits>
 
 #include "kernels.h"
 
@@ -116,39 +124,100 @@ __device__ __forceinline__ T tile_row_sum(const SpMat<T> &A, const T *__restrict
   return acc;
 }
 
-constexpr int kSellBatch = 8;  // sliced-ELL entries per row whose loads are in flight together
 
-// Row sum of A * g for `row` from the sliced-ELL copy (thread -> row, lanes of
-// a wavefront -> the 64 rows of one slice).  Rows past n return 0; padding
-// entries (column -1) contribute nothing.
+// One batch of N slots of a diagonal slice: values at sva + 64 q, diagonal
+// offsets o[q]; the shifted loads are unconditional and kept in range, and an
+// absent entry (value 0) selects 0, so it never reaches the product.
+template <typename T, int N>
+__device__ __forceinline__ T dia_batch(const T *__restrict__ sva, const T *__restrict__ g, int row,
+                                       int last, const int *o, T acc) {
+  T v[N], gl[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    v[q] = ldnt(sva + q * kSlice);
+    gl[q] = g[min(max(row + o[q], 0), last)];
+  }
+#pragma unroll
+  for (int q = 0; q < N; ++q) acc += v[q] * (v[q] != T(0) ? gl[q] : T(0));
+  return acc;
+}
+
+// One batch of N slots of an explicit-column slice (padding: column -1).
+template <typename T, int N>
+__device__ __forceinline__ T ell_batch(const T *__restrict__ sva, const int32_t *__restrict__ sci,
+                                       const T *__restrict__ g, T acc) {
+  int c[N];
+  T v[N], gv[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    v[q] = ldnt(sva + q * kSlice);
+    c[q] = ldnt(sci + q * kSlice);
+  }
+#pragma unroll
+  for (int q = 0; q < N; ++q) gv[q] = c[q] >= 0 ? g[c[q]] : T(0);
+#pragma unroll
+  for (int q = 0; q < N; ++q) acc += v[q] * gv[q];
+  return acc;
+}
+
+// Row sum of A * g for `row` from the sliced copy (thread -> row, lanes of a
+// wavefront -> the 64 rows of one slice).  Rows past n return 0.  Slot counts
+// are uniform across the wavefront, so each batch of up to kSellBatch slots
+// runs a specialisation whose loads are all issued before any is used.
 template <typename T>
 __device__ __forceinline__ T sell_row_sum(const SpMat<T> &A, const T *__restrict__ g, int row) {
-  const int s = row / kSlice;  // uniform across the wavefront
+  // the slice is uniform across the wavefront (tiles are 64-row aligned); saying
+  // so puts the slice metadata in scalar registers and makes the branches uniform
+  const int s = __builtin_amdgcn_readfirstlane(row / kSlice);
   const int lane = row - s * kSlice;
   T acc = T(0);
   if (s * kSlice >= A.n) return acc;
-  const int base = A.sp[s];
-  const int w = (A.sp[s + 1] - base) / kSlice;
+  // slice bounds, kind and first batch of diagonal offsets, all in flight together
+  // (the offset table has kSellBatch entries of slack past its end)
+  const int base = A.sp[s], next = A.sp[s + 1];
+  const int dia = A.sflag[s];
+  const int *__restrict__ offs = A.soff + (int64_t)s * A.dmax;
+  int o[kSellBatch];
+#pragma unroll
+  for (int q = 0; q < kSellBatch; ++q) o[q] = offs[q];
+  const int w = (next - base) / kSlice;
+  const int last = A.n - 1;
   for (int j0 = 0; j0 < w; j0 += kSellBatch) {
-    int cols[kSellBatch];
-    T vals[kSellBatch];
+    const int cnt = min(kSellBatch, w - j0);
+    const T *sv = A.sva + base + j0 * kSlice + lane;
+    if (dia) {
+      if (j0 > 0) {
 #pragma unroll
-    for (int q = 0; q < kSellBatch; ++q) {
-      cols[q] = -1;
-      vals[q] = T(0);
-      if (j0 + q < w) {
-        const int k = base + (j0 + q) * kSlice + lane;
-        vals[q] = ldnt(A.sva + k);
-        cols[q] = ldnt(A.sci + k);
+        for (int q = 0; q < kSellBatch; ++q) o[q] = offs[j0 + q];
       }
+#define PP_DIA(N)                                         \
+  case N:                                                 \
+    acc = dia_batch<T, N>(sv, g, row, last, o, acc);      \
+    break;
+      switch (cnt) { PP_DIA(8) PP_DIA(7) PP_DIA(6) PP_DIA(5) PP_DIA(4) PP_DIA(3) PP_DIA(2) PP_DIA(1) }
+#undef PP_DIA
+    } else {
+      const int32_t *sc = A.sci + base + j0 * kSlice + lane;
+#define PP_ELL(N)                                         \
+  case N:                                                 \
+    acc = ell_batch<T, N>(sv, sc, g, acc);                \
+    break;
+      switch (cnt) { PP_ELL(8) PP_ELL(7) PP_ELL(6) PP_ELL(5) PP_ELL(4) PP_ELL(3) PP_ELL(2) PP_ELL(1) }
+#undef PP_ELL
     }
-    T gv[kSellBatch];
-#pragma unroll
-    for (int q = 0; q < kSellBatch; ++q) gv[q] = cols[q] >= 0 ? g[cols[q]] : T(0);
-#pragma unroll
-    for (int q = 0; q < kSellBatch; ++q) acc += vals[q] * gv[q];
   }
   return acc;
+}
+
+// Tile of workgroup b among G: groups of kXcdGroup consecutive tiles go to one
+// XCD (b mod 8 is the XCD a workgroup lands on); a ragged last group keeps the
+// identity, so the map is a bijection on [0, G).
+constexpr int kXcdGroup = 16;
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  constexpr int span = 8 * kXcdGroup;
+  const int grp = b / span, w = b - grp * span;
+  if ((grp + 1) * span > G) return b;
+  return grp * span + (w % 8) * kXcdGroup + w / 8;
 }
 
 // Row sum of A * g for the calling thread's row r0 + threadIdx.x from the view's
@@ -167,7 +236,7 @@ __device__ __forceinline__ T row_product(const SpMat<T> &A, const T *__restrict_
 // ------------------------------------------------------------------ chain
 template <typename T, int KIND, bool FOLD, bool LAST, bool SELL>
 __global__ __launch_bounds__(kBlock) void k_chain(SpMat<T> A, ChainArgs<T> a) {
-  const int r0 = blockIdx.x * kBlock;
+  const int r0 = xcd_tile(blockIdx.x, gridDim.x) * kBlock;
   const int nrows = min(kBlock, A.n - r0);
   const int t = threadIdx.x;
   const int i = r0 + t;
@@ -235,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SpMat<T> A, ChainArgs<T> a) {
 template <typename T, bool SELL>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpMat<T> A, const T *__restrict__ g,
                                                  const double *gscale, T *__restrict__ out) {
-  const int r0 = blockIdx.x * kBlock;
+  const int r0 = xcd_tile(blockIdx.x, gridDim.x) * kBlock;
   const int nrows = min(kBlock, A.n - r0);
   const int i = r0 + threadIdx.x;
   int rb = 0, re = 0;
@@ -254,7 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(SpMat<T> A, const T *__rest
                                                      const T *__restrict__ x, T *__restrict__ out,
                                                      double *__restrict__ partial) {
   __shared__ double red[4];
-  const int r0 = blockIdx.x * kBlock;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int r0 = tile * kBlock;
   const int nrows = min(kBlock, A.n - r0);
   const int i = r0 + threadIdx.x;
   int rb = 0, re = 0;
@@ -274,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(SpMat<T> A, const T *__rest
     sq = (double)r * (double)r;
   }
   sq = block_sum(sq, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = sq;
+  if (threadIdx.x == 0) partial[tile] = sq;
 }
 
 template <typename T>
@@ -600,34 +670,94 @@ __global__ __launch_bounds__(kBlock) void k_csr_grad(int n, const int32_t *__res
   for (int k = rp[i]; k < rp[i + 1]; ++k) g[k] = -li * x[ci[k]];
 }
 
-// ------------------------------------------------------- sliced ELL
-__global__ __launch_bounds__(kBlock) void k_sell_widths(int n, int ns,
-                                                        const int32_t *__restrict__ rp,
-                                                        int32_t *__restrict__ wlen,
-                                                        int32_t *maxlen) {
-  __shared__ int32_t red[kBlock / 64];
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  int len = (i < n) ? rp[i + 1] - rp[i] : 0;
+// ------------------------------------------------------- sliced copy
+// Distinct diagonals of a slice in increasing order, one per call, by a k-way
+// merge over the wavefront's rows (each row's columns strictly increasing):
+// returns the next offset m = col - row (INT_MAX when all rows are consumed)
+// and sets *take to the index (within the row) of this lane's entry on that
+// diagonal, or -1.  All 64 lanes of the wavefront must call it together.
+__device__ __forceinline__ int next_diagonal(const int32_t *__restrict__ ci, int rb, int len,
+                                             int row, int *p, int *take) {
+  const int cur = (*p < len) ? ci[rb + *p] - row : INT_MAX;
+  int m = cur;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
-  const int s = i / kSlice;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) {
-    if (s < ns) wlen[s] = (int32_t)((uint32_t)kSlice * (uint32_t)len);
-    red[wv] = len;
+  for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
+  *take = -1;
+  if (cur == m && m != INT_MAX) {
+    *take = *p;
+    ++*p;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) atomicMax(maxlen, max(max(red[0], red[1]), max(red[2], red[3])));
+  return m;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sell_fill_cols(int n, int ns,
+// Plan of the sliced copy: per slice, the longest row w and the slot count:
+// the number of distinct diagonals when every row's columns strictly increase
+// and that number is at most 1.5 w (then flag = 1: stored by diagonal), else w
+// (flag = 0: explicit columns).  wlen[s] = 64 * slots (wrapping modulo 2^32),
+// stat[0] = max(stat[0], longest row), stat[1] += 64 * slots of explicit-column
+// slices, stat[2] = max(stat[2], slots of a diagonal slice) (the caller zeroes
+// them first and rejects the copy when 96 * stat[0] * ns >= 2^31, which also
+// covers any wrap).
+__global__ __launch_bounds__(kBlock) void k_slice_plan(int n, int ns,
+                                                       const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci,
+                                                       int32_t *__restrict__ wlen,
+                                                       int32_t *__restrict__ flag,
+                                                       int32_t *stat) {
+  __shared__ int32_t red[kBlock / 64];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int s = i / kSlice;  // uniform across the wavefront
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int rb = 0, len = 0;
+  if (i < n) {
+    rb = rp[i];
+    len = rp[i + 1] - rb;
+  }
+  int w = len;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, 64));
+  bool sorted = true;
+  for (int k = 1; k < len; ++k) sorted = sorted && (ci[rb + k] > ci[rb + k - 1]);
+  const bool all_sorted = __ballot(!sorted) == 0;
+  int slots = w, dia = 0;
+  if (s < ns && all_sorted && w > 0) {
+    const int cap = w + w / 2;
+    int p = 0, take = -1, cnt = 0;
+    while (cnt <= cap) {  // cnt and the returned m are uniform across the wavefront
+      if (next_diagonal(ci, rb, len, i, &p, &take) == INT_MAX) break;
+      ++cnt;
+    }
+    if (cnt <= cap) {
+      slots = cnt;
+      dia = 1;
+    }
+  }
+  if (lane == 0) {
+    if (s < ns) {
+      wlen[s] = (int32_t)((uint32_t)kSlice * (uint32_t)slots);
+      flag[s] = dia;
+      if (!dia && slots > 0) atomicAdd(stat + 1, (int32_t)((uint32_t)kSlice * (uint32_t)slots));
+      if (dia) atomicMax(stat + 2, slots);
+    }
+    red[wv] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(stat, max(max(red[0], red[1]), max(red[2], red[3])));
+}
+
+// Index part of the sliced copy: the diagonal offsets of diagonal slices
+// (soff[s * dmax + j]) and the columns of explicit-column slices (sci, -1 =
+// padding; sci may be nullptr when every slice is diagonal).
+__global__ __launch_bounds__(kBlock) void k_slice_fill_idx(int n, int ns, int dmax,
                                                            const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ ci,
                                                            const int32_t *__restrict__ sp,
+                                                           const int32_t *__restrict__ flag,
+                                                           int32_t *__restrict__ soff,
                                                            int32_t *__restrict__ sci) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int s = i / kSlice;
-  if (s >= ns) return;
+  if (s >= ns) return;  // whole wavefronts
   const int lane = i - s * kSlice;
   const int base = sp[s], w = (sp[s + 1] - base) / kSlice;
   int rb = 0, len = 0;
@@ -635,18 +765,29 @@ __global__ __launch_bounds__(kBlock) void k_sell_fill_cols(int n, int ns,
     rb = rp[i];
     len = rp[i + 1] - rb;
   }
-  for (int j = 0; j < w; ++j) sci[base + j * kSlice + lane] = j < len ? ci[rb + j] : -1;
+  if (flag[s]) {
+    int p = 0, take = -1;
+    for (int j = 0; j < w; ++j) {
+      const int m = next_diagonal(ci, rb, len, i, &p, &take);
+      if (lane == 0) soff[(int64_t)s * dmax + j] = m;
+    }
+  } else {
+    for (int j = 0; j < w; ++j) sci[base + j * kSlice + lane] = j < len ? ci[rb + j] : -1;
+  }
 }
 
+// Values of the sliced copy in D (zero where a row has no entry in the slot).
 template <typename S, typename D>
-__global__ __launch_bounds__(kBlock) void k_sell_fill_vals(int n, int ns,
-                                                           const int32_t *__restrict__ rp,
-                                                           const S *__restrict__ va,
-                                                           const int32_t *__restrict__ sp,
-                                                           D *__restrict__ sva) {
+__global__ __launch_bounds__(kBlock) void k_slice_fill_vals(int n, int ns,
+                                                            const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const S *__restrict__ va,
+                                                            const int32_t *__restrict__ sp,
+                                                            const int32_t *__restrict__ flag,
+                                                            D *__restrict__ sva) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int s = i / kSlice;
-  if (s >= ns) return;
+  if (s >= ns) return;  // whole wavefronts
   const int lane = i - s * kSlice;
   const int base = sp[s], w = (sp[s + 1] - base) / kSlice;
   int rb = 0, len = 0;
@@ -654,7 +795,15 @@ __global__ __launch_bounds__(kBlock) void k_sell_fill_vals(int n, int ns,
     rb = rp[i];
     len = rp[i + 1] - rb;
   }
-  for (int j = 0; j < w; ++j) sva[base + j * kSlice + lane] = j < len ? (D)va[rb + j] : D(0);
+  if (flag[s]) {
+    int p = 0, take = -1;
+    for (int j = 0; j < w; ++j) {
+      (void)next_diagonal(ci, rb, len, i, &p, &take);
+      sva[base + j * kSlice + lane] = take >= 0 ? (D)va[rb + take] : D(0);
+    }
+  } else {
+    for (int j = 0; j < w; ++j) sva[base + j * kSlice + lane] = j < len ? (D)va[rb + j] : D(0);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_jacobi_scale(int n, const int32_t *__restrict__ rp,
@@ -928,38 +1077,45 @@ hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const do
   return hipGetLastError();
 }
 
-hipError_t launch_sell_widths(int n, int ns, const int32_t *rp, int32_t *wlen, int32_t *maxlen,
-                              hipStream_t stream) {
+hipError_t launch_slice_plan(int n, int ns, const int32_t *rp, const int32_t *ci, int32_t *wlen,
+                             int32_t *flag, int32_t *stat, hipStream_t stream) {
   if (ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sell_widths, dim3(blocks_of((int64_t)ns * kSlice)), dim3(kBlock), 0, stream,
-                     n, ns, rp, wlen, maxlen);
+  hipLaunchKernelGGL(k_slice_plan, dim3(blocks_of((int64_t)ns * kSlice)), dim3(kBlock), 0, stream,
+                     n, ns, rp, ci, wlen, flag, stat);
   return hipGetLastError();
 }
 
-hipError_t launch_sell_fill_cols(int n, int ns, const int32_t *rp, const int32_t *ci,
-                                 const int32_t *sp, int32_t *sci, hipStream_t stream) {
+hipError_t launch_slice_fill_idx(int n, int ns, int dmax, const int32_t *rp, const int32_t *ci,
+                                 const int32_t *sp, const int32_t *flag, int32_t *soff,
+                                 int32_t *sci, hipStream_t stream) {
   if (ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sell_fill_cols, dim3(blocks_of((int64_t)ns * kSlice)), dim3(kBlock), 0,
-                     stream, n, ns, rp, ci, sp, sci);
+  hipLaunchKernelGGL(k_slice_fill_idx, dim3(blocks_of((int64_t)ns * kSlice)), dim3(kBlock), 0,
+                     stream, n, ns, dmax, rp, ci, sp, flag, soff, sci);
   return hipGetLastError();
 }
 
 template <typename S, typename D>
-hipError_t launch_sell_fill_vals(int n, int ns, const int32_t *rp, const S *va, const int32_t *sp,
-                                 D *sva, hipStream_t stream) {
+hipError_t launch_slice_fill_vals(int n, int ns, const int32_t *rp, const int32_t *ci, const S *va,
+                                  const int32_t *sp, const int32_t *flag, D *sva,
+                                  hipStream_t stream) {
   if (ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_sell_fill_vals<S, D>), dim3(blocks_of((int64_t)ns * kSlice)), dim3(kBlock),
-                     0, stream, n, ns, rp, va, sp, sva);
+  hipLaunchKernelGGL((k_slice_fill_vals<S, D>), dim3(blocks_of((int64_t)ns * kSlice)),
+                     dim3(kBlock), 0, stream, n, ns, rp, ci, va, sp, flag, sva);
   return hipGetLastError();
 }
 
-template hipError_t launch_sell_fill_vals<double, double>(int, int, const int32_t *,
-                                                          const double *, const int32_t *,
-                                                          double *, hipStream_t);
-template hipError_t launch_sell_fill_vals<double, float>(int, int, const int32_t *, const double *,
-                                                         const int32_t *, float *, hipStream_t);
-template hipError_t launch_sell_fill_vals<float, float>(int, int, const int32_t *, const float *,
-                                                        const int32_t *, float *, hipStream_t);
+template hipError_t launch_slice_fill_vals<double, double>(int, int, const int32_t *,
+                                                           const int32_t *, const double *,
+                                                           const int32_t *, const int32_t *,
+                                                           double *, hipStream_t);
+template hipError_t launch_slice_fill_vals<double, float>(int, int, const int32_t *,
+                                                          const int32_t *, const double *,
+                                                          const int32_t *, const int32_t *,
+                                                          float *, hipStream_t);
+template hipError_t launch_slice_fill_vals<float, float>(int, int, const int32_t *,
+                                                         const int32_t *, const float *,
+                                                         const int32_t *, const int32_t *, float *,
+                                                         hipStream_t);
 
 hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, const double *va,
                                const double *b, double *va_out, double *b_out, int32_t *bad,

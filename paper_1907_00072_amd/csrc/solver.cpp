@@ -259,9 +259,11 @@ struct PolyRef {
 template <typename T>
 double product_bytes(const SpMat<T> &A, int vec_rw) {
   const double vecs = (double)sizeof(T) * A.n * (1 + vec_rw);
-  if (A.sp)  // sliced ELL: stored entries (padding included) and slice offsets
-    return (double)A.snnz * (sizeof(T) + sizeof(int32_t)) +
-           4.0 * ((A.n + ppk::kSlice - 1) / ppk::kSlice + 1) + vecs;
+  if (A.sp)  // sliced copy: stored values (padding included), explicit columns,
+             // diagonal offsets, slice offsets and flags
+    return (double)A.snnz * sizeof(T) + 4.0 * A.snnz_ell +
+           4.0 * (A.snnz - A.snnz_ell) / ppk::kSlice +
+           8.0 * ((A.n + ppk::kSlice - 1) / ppk::kSlice) + 4.0 + vecs;
   return (double)A.nnz * (sizeof(T) + sizeof(int32_t)) + 4.0 * (A.n + 1) + vecs;
 }
 
@@ -742,15 +744,16 @@ int check_csr(const pp_csr *A) {
   return PP_OK;
 }
 
-// The sliced-ELL copy of a call's matrix (see SpMat): built on the device from
-// the CSR arrays into the arena's matrix buffer.  `use` is false when the
-// caller asked for CSR, or (PP_LAYOUT_AUTO) when the padding would exceed a
-// quarter of nnz plus one slice of the longest row, or when the stored entries
-// would not fit int32 offsets.
+// The sliced copy of a call's matrix (see SpMat): built on the device from the
+// CSR arrays into the arena's matrix buffer.  `use` is false when the caller
+// asked for CSR, or (PP_LAYOUT_AUTO) when one product would stream more than
+// 1.25 times the bytes of the CSR product, or when the stored slots would not
+// fit int32 offsets.
 struct SellCopy {
   bool use = false;
-  int64_t snnz = 0;
-  int32_t *sp = nullptr, *sci = nullptr;
+  int64_t snnz = 0, ell = 0;
+  int dmax = 0;
+  int32_t *sp = nullptr, *flag = nullptr, *soff = nullptr, *sci = nullptr;
   double *va64 = nullptr;
   float *va32 = nullptr;
 };
@@ -769,69 +772,92 @@ int make_sell(const pp_csr *A, bool want64, bool want32, const float *src32, hip
   Carver meas(nullptr);
   meas.take<int32_t>(ns);
   meas.take<int32_t>(ns + 1);
+  meas.take<int32_t>(ns);
   meas.take<int32_t>(ppk::scan_tmp_size(ns));
   meas.take<int32_t>(64);
   PP_TRY(ensure_arena(ar, meas.off + 256, 64));
   Carver c(ar->dev);
   int32_t *wlen = c.take<int32_t>(ns);
   int32_t *spt = c.take<int32_t>(ns + 1);
+  int32_t *flagt = c.take<int32_t>(ns);
   int32_t *tmp = c.take<int32_t>(ppk::scan_tmp_size(ns));
-  int32_t *maxlen = c.take<int32_t>(64);
-  PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, maxlen, s));
-  PP_TRY_HIP(ppk::launch_sell_widths(n, ns, A->row_ptr, wlen, maxlen, s));
+  // [0] longest row, [1] explicit-column slots, [2] most slots of a diagonal slice
+  int32_t *stats = c.take<int32_t>(64);
+  PP_TRY_HIP(ppk::launch_fill<int32_t>(3, 0, stats, s));
+  PP_TRY_HIP(ppk::launch_slice_plan(n, ns, A->row_ptr, A->col_ind, wlen, flagt, stats, s));
   PP_TRY_HIP(ppk::launch_exclusive_scan(ns, wlen, spt, tmp, s));
   int32_t *h = reinterpret_cast<int32_t *>(ar->host);
   PP_TRY_HIP(hipMemcpyAsync(h, spt + ns, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  PP_TRY_HIP(hipMemcpyAsync(h + 1, maxlen, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipMemcpyAsync(h + 1, stats, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   PP_TRY_HIP(hipStreamSynchronize(s));
   const int64_t longest = h[1];
-  if ((int64_t)ppk::kSlice * longest * ns >= ((int64_t)1 << 31)) return PP_OK;
-  const int64_t snnz = h[0];
-  if (A->layout == PP_LAYOUT_AUTO && snnz > A->nnz + A->nnz / 4 + ppk::kSlice * longest)
-    return PP_OK;
+  if ((int64_t)96 * longest * ns >= ((int64_t)1 << 31)) return PP_OK;
+  const int64_t snnz = h[0], ell = h[2], dmax = h[3];
+  if (A->layout == PP_LAYOUT_AUTO) {
+    const double vb = A->dtype == PP_F64 ? 8.0 : 4.0;
+    const double sliced = snnz * vb + ell * 4.0 + (snnz - ell) / 16.0 + 8.0 * ns;
+    const double csr = A->nnz * (vb + 4.0) + 4.0 * (n + 1);
+    if (sliced > 1.25 * csr) return PP_OK;
+  }
   const int64_t cap = std::max<int64_t>(snnz, 1);
+  // one batch of slack: the product kernel fetches whole batches of offsets
+  const int64_t ocap = (int64_t)ns * dmax + ppk::kSellBatch;
   Carver mm(nullptr);
   mm.take<int32_t>(ns + 1);
-  mm.take<int32_t>(cap);
+  mm.take<int32_t>(ns);
+  mm.take<int32_t>(ocap);
+  if (ell > 0) mm.take<int32_t>(cap);
   if (want64) mm.take<double>(cap);
   if (want32) mm.take<float>(cap);
   PP_TRY(ensure_side(&ar->mat, &ar->mat_cap, mm.off + 256));
   Carver m(ar->mat);
   out->sp = m.take<int32_t>(ns + 1);
-  out->sci = m.take<int32_t>(cap);
+  out->flag = m.take<int32_t>(ns);
+  out->soff = m.take<int32_t>(ocap);
+  if (ell > 0) out->sci = m.take<int32_t>(cap);
   if (want64) out->va64 = m.take<double>(cap);
   if (want32) out->va32 = m.take<float>(cap);
   PP_TRY_HIP(hipMemcpyAsync(out->sp, spt, (ns + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  PP_TRY_HIP(ppk::launch_sell_fill_cols(n, ns, A->row_ptr, A->col_ind, out->sp, out->sci, s));
+  PP_TRY_HIP(hipMemcpyAsync(out->flag, flagt, ns * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  PP_TRY_HIP(ppk::launch_slice_fill_idx(n, ns, (int)dmax, A->row_ptr, A->col_ind, out->sp,
+                                        out->flag, out->soff, out->sci, s));
   if (want64) {
     if (A->dtype != PP_F64) return PP_ERR_ARG;
-    PP_TRY_HIP((ppk::launch_sell_fill_vals<double, double>(
-        n, ns, A->row_ptr, static_cast<const double *>(A->vals), out->sp, out->va64, s)));
+    PP_TRY_HIP((ppk::launch_slice_fill_vals<double, double>(
+        n, ns, A->row_ptr, A->col_ind, static_cast<const double *>(A->vals), out->sp, out->flag,
+        out->va64, s)));
   }
   if (want32) {
     if (src32 || A->dtype == PP_F32) {
       const float *src = src32 ? src32 : static_cast<const float *>(A->vals);
-      PP_TRY_HIP((ppk::launch_sell_fill_vals<float, float>(n, ns, A->row_ptr, src, out->sp,
-                                                           out->va32, s)));
+      PP_TRY_HIP((ppk::launch_slice_fill_vals<float, float>(n, ns, A->row_ptr, A->col_ind, src,
+                                                            out->sp, out->flag, out->va32, s)));
     } else {
-      PP_TRY_HIP((ppk::launch_sell_fill_vals<double, float>(
-          n, ns, A->row_ptr, static_cast<const double *>(A->vals), out->sp, out->va32, s)));
+      PP_TRY_HIP((ppk::launch_slice_fill_vals<double, float>(
+          n, ns, A->row_ptr, A->col_ind, static_cast<const double *>(A->vals), out->sp,
+          out->flag, out->va32, s)));
     }
   }
   out->use = true;
   out->snnz = snnz;
+  out->ell = ell;
+  out->dmax = (int)dmax;
   return PP_OK;
 }
 
-// Attach the sliced-ELL copy (when built) to a view of type T.
+// Attach the sliced copy (when built) to a view of type T.
 template <typename T>
 SpMat<T> with_sell(SpMat<T> M, const SellCopy &c) {
   if (!c.use) return M;
   M.sp = c.sp;
+  M.sflag = c.flag;
+  M.soff = c.soff;
   M.sci = c.sci;
   if constexpr (sizeof(T) == sizeof(double)) M.sva = c.va64;
   else M.sva = c.va32;
   M.snnz = (int)c.snnz;
+  M.snnz_ell = (int)c.ell;
+  M.dmax = c.dmax;
   return M;
 }
 

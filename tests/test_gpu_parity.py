@@ -503,3 +503,79 @@ def test_refinement_with_given_fp32_values_on_sell(B):
     assert s1.layout_used == s2.layout_used == "sell"
     # the given FP32 values equal the internal cast: identical runs
     assert s1.iters == s2.iters and np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+
+
+def _mixed_structure_matrix():
+    """2D 5-point stencil whose rows 512..767 are replaced by random rows: slices 8..11
+    of the sliced copy need explicit columns, the others are stored by diagonal."""
+    S = W.config(1, N=32).A
+    R = W.random_csr(1024, 9, seed=41, diag_shift=6.0)
+    rows = []
+    for i in range(1024):
+        src = R if 512 <= i < 768 else S
+        a, b = src.row_ptr[i], src.row_ptr[i + 1]
+        rows.append((src.col_ind[a:b], src.vals[a:b]))
+    rp = np.zeros(1025, np.int32)
+    rp[1:] = np.cumsum([r[0].size for r in rows])
+    return W.CSR(1024, rp, np.concatenate([r[0] for r in rows]).astype(np.int32),
+                 np.concatenate([r[1] for r in rows]))
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_apply_mixed_diagonal_and_explicit_slices(B, layout):
+    Ah = _mixed_structure_matrix()
+    roots = np.array([6.0, 3.0 + 1.0j, 3.0 - 1.0j, 2.0, 8.0])
+    p = B.pp_poly_from_roots(Ah.n, roots)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-4)):
+        v = W.uniform(Ah.n, 42)
+        A = B.CSRMatrix.from_host(Ah, dtype=dt, layout=layout)
+        pp = p if dt == torch.float64 else B.pp_poly_from_roots(Ah.n, roots, dtype="f32")
+        y = B.pp_apply(A, pp, _up(v, dt)).cpu().numpy().astype(np.float64)
+        assert _rel(y, opoly.apply_poly(Ah.to_scipy(), roots, v)) <= tol
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_apply_unsorted_rows_and_duplicate_columns(B, layout):
+    base = W.config(1, N=24).A            # n = 576: 9 slices
+    rp, ci, va = base.row_ptr.copy(), base.col_ind.copy(), base.vals.copy()
+    for i in range(0, base.n, 5):         # reverse every fifth row's column order
+        a, b = rp[i], rp[i + 1]
+        ci[a:b] = ci[a:b][::-1].copy()
+        va[a:b] = va[a:b][::-1].copy()
+    # split the diagonal entry of every seventh row into two duplicate entries
+    rows_ci, rows_va = [], []
+    for i in range(base.n):
+        c, v = list(ci[rp[i]:rp[i + 1]]), list(va[rp[i]:rp[i + 1]])
+        if i % 7 == 0:
+            k = c.index(i)
+            c.insert(k, i)
+            v[k] = 0.25 * v[k]
+            v.insert(k, 3.0 * v[k])
+        rows_ci.append(c)
+        rows_va.append(v)
+    rp2 = np.zeros(base.n + 1, np.int32)
+    rp2[1:] = np.cumsum([len(c) for c in rows_ci])
+    Ah = W.CSR(base.n, rp2, np.concatenate(rows_ci).astype(np.int32), np.concatenate(rows_va))
+    As = Ah.to_scipy()                    # scipy sums duplicates in its products
+    assert np.allclose(As.toarray(), base.to_scipy().toarray())
+    roots = np.array([5.0, 2.0 + 0.5j, 2.0 - 0.5j, 7.0])
+    p = B.pp_poly_from_roots(Ah.n, roots)
+    v = W.uniform(Ah.n, 43)
+    y = B.pp_apply(B.CSRMatrix.from_host(Ah, layout=layout), p, _up(v)).cpu().numpy()
+    assert _rel(y, opoly.apply_poly(As, roots, v)) <= 1e-12
+
+
+def test_sliced_copy_stores_stencils_by_diagonal(B):
+    # the bytes per chain launch drop to values + offsets when every slice is diagonal:
+    # 8 * stored + small; an explicit-column copy would add 4 bytes per stored entry
+    P = W.config(2, N=24)
+    x, st = B.pp_gmres_solve(B.CSRMatrix.from_host(P.A), _up(P.b), m=P.m, d=10, tol=P.tol,
+                             v0=_up(P.v0), timing=True)
+    assert st.layout_used == "sell" and st.relres_true < P.tol
+    n, stored = P.A.n, st.nnz_stored
+    ns = -(-n // 64)
+    per_launch = st.bytes_chain / st.launches_chain
+    # values + one offset per 64 stored slots + slice offsets and flags + at most 4 vectors
+    assert per_launch <= 8.0 * stored + stored / 16.0 + 8.0 * ns + 4.0 + 32.0 * n
+    # explicit columns would cost at least 12 bytes per stored slot plus 2 vectors
+    assert 12.0 * stored + 16.0 * n > 8.0 * stored + stored / 16.0 + 8.0 * ns + 4.0 + 32.0 * n
