@@ -15,17 +15,17 @@ true relative residual < 1e-8.  `value` is the mean time-to-tolerance (s).
 Extra legs on the same matrix: the FP32-inside-FP64 refinement solve and plain
 GMRES(30) (no polynomial), each one timed solve after a warm-up.
 
-The library runs its sparse products on a sliced-ELL copy of the CSR matrix
-that it builds on the device at the start of each solve (64-row slices,
-column-major inside a slice; 0.11% padding on this stencil); the copy is part
-of every timed solve.  The `csr` leg times the same solve on the caller's CSR
-arrays.
+The library runs its sparse products on a sliced copy of the CSR matrix that
+it builds on the device at the start of each solve (64-row slices stored by
+diagonal: values plus one offset per slot, no column indices; 0.11% padding on
+this stencil); the copy is part of every timed solve.  The `csr` leg times the
+same solve on the caller's CSR arrays.
 
 roofline: the fused product + root-update chain kernel dominates (39 of every
 40 products).  Its achieved bandwidth is the algorithmic bytes of the
-event-timed chain launches (sliced ELL: 12 nnz_stored + n/16 bytes of matrix,
-plus 16 n of vectors for a middle real-root step) over their event-timed
-duration, both accumulated by the library over the timed solves.
+event-timed chain launches (8 nnz_stored + nnz_stored/16 + n/8 bytes of
+matrix, plus 16 n of vectors for a middle real-root step) over their
+event-timed duration, both accumulated by the library over the timed solves.
 
 cpu_baseline: the CPU oracle (NumPy/SciPy, complex-arithmetic product form) on
 a bounded sample of the same solve: one preconditioned Arnoldi step on the full
@@ -127,7 +127,8 @@ def main():
     bo = sum(s.bytes_orth for s in stats)
     to = sum(s.t_orth for s in stats)
     chain_gbps = bc / tc / 1e9 if tc > 0 else None
-    layout_name = {"sell": "sliced-ELL", "csr": "CSR"}.get(st.layout_used, st.layout_used)
+    layout_name = {"sell": "sliced (diagonal slices)", "csr": "CSR"}.get(st.layout_used,
+                                                                       st.layout_used)
     roofline = {
         "kernel": f"k_chain (fused {layout_name} product + Leja root update), FP64",
         "bound": "hbm",

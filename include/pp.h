@@ -76,9 +76,9 @@ extern "C" {
 #define PP_OP_PRODUCT 1       /* w = A (p(A) v): d-1 fused updates, then one product */
 
 /* ---- storage of A for the sparse products --------------------------- */
-#define PP_LAYOUT_AUTO 0 /* sliced ELL unless its padding is large (below), else CSR */
+#define PP_LAYOUT_AUTO 0 /* the sliced copy unless it would stream more bytes (below), else CSR */
 #define PP_LAYOUT_CSR 1  /* run the products on the caller's CSR arrays */
-#define PP_LAYOUT_SELL 2 /* always sliced ELL (unless its offsets would overflow int32) */
+#define PP_LAYOUT_SELL 2 /* always the sliced copy (unless its offsets would overflow int32) */
 
 /* Square sparse matrix in CSR form, all arrays in device memory.
  * row_ptr[n+1] int32, row_ptr[0] = 0, nondecreasing, row_ptr[n] = nnz < 2^31;
@@ -86,14 +86,20 @@ extern "C" {
  * vals[nnz] of type dtype.  Duplicate (row, col) entries are summed.
  *
  * layout: with PP_LAYOUT_AUTO (0, the zero-initialised default) or
- * PP_LAYOUT_SELL, each call first copies A, in library memory, into sliced
- * ELL: slices of 64 consecutive rows, each stored column-major and padded to its
- * longest row (padding = column -1, value 0).  The products then run on the
- * copy: one wavefront owns a slice, and each gather reads one entry of 64
- * consecutive rows (for a stencil, 64 neighbouring values of one diagonal).
- * The copy costs one pass over A per call.  AUTO keeps CSR when the copy would
- * hold more than nnz + nnz/4 + 64 * (longest row) entries.  Both layouts give
- * the same products up to the rounding of the summation. */
+ * PP_LAYOUT_SELL, each call first copies A, in library memory, into a sliced
+ * form: slices of 64 consecutive rows, each stored column-major (slot-major).
+ * A slice whose rows have strictly increasing columns and use at most 1.5 x
+ * (longest row) distinct diagonals (col - row) is stored by diagonal: slot j
+ * holds diagonal d_j for all 64 rows (0 where a row has no entry there) and
+ * only the offsets d_j are kept, no column indices.  Any other slice keeps
+ * explicit columns, padded to its longest row (column -1, value 0).  The
+ * products then run on the copy: one wavefront owns a slice, and each load of
+ * the vector reads one diagonal (or one entry) of 64 consecutive rows.  The
+ * copy costs about two passes over A per call.  AUTO keeps CSR when one product
+ * on the copy would stream more than 1.25 x the bytes of the CSR product
+ * (irregular row lengths).  Both layouts give the same products up to the
+ * rounding of the summation; an entry stored as an explicit 0 and an absent
+ * one are treated alike. */
 typedef struct pp_csr {
   int64_t n;
   int64_t nnz;
@@ -159,11 +165,11 @@ typedef struct pp_stats {
   /* Algorithmic HBM bytes of the launches inside the timed phases above (the
    * Arnoldi steps' chains, operator products and CGS2 sweeps), from the
    * per-launch traffic model: a chain launch reads the matrix once (CSR: vals,
-   * col_ind, row_ptr, 12 nnz + 4 n bytes in FP64; sliced ELL: the stored values
-   * and columns and the slice offsets, 12 nnz_stored + n/16 bytes), the gathered
-   * vector once and the accumulator / partner vectors once, and writes its
-   * outputs once.  Divided by t_chain / t_spmv / t_orth they give achieved
-   * bandwidth. */
+   * col_ind, row_ptr, 12 nnz + 4 n bytes in FP64; sliced copy: the stored values,
+   * the columns of explicit-column slices, one offset per slot of diagonal
+   * slices and the slice table, 8 nnz_stored + ... bytes), the gathered vector
+   * once and the accumulator / partner vectors once, and writes its outputs
+   * once.  Divided by t_chain / t_spmv / t_orth they give achieved bandwidth. */
   double bytes_chain;
   double bytes_spmv;
   double bytes_orth;
@@ -171,7 +177,8 @@ typedef struct pp_stats {
   double relres_original;  /* ||b - A x|| / ||b|| of the unpreconditioned system (equals
                               relres_true unless left_jacobi is set) */
   int32_t layout_used;     /* PP_LAYOUT_CSR or PP_LAYOUT_SELL: what the products ran on */
-  int64_t nnz_stored;      /* entries one product streams: nnz (CSR) or nnz + padding */
+  int64_t nnz_stored;      /* values one product streams: nnz (CSR) or the sliced copy's
+                              stored values, padding included */
 } pp_stats;
 
 /* Build the polynomial for (A, v0) with d roots.

@@ -162,7 +162,7 @@ class CSRMatrix:
     """Square CSR matrix whose arrays live in device memory (torch tensors).
 
     ``layout`` ("auto", "csr" or "sell") is the storage the library uses for its
-    sparse products (``pp_csr.layout``): "auto" builds a sliced-ELL copy per call
+    sparse products (``pp_csr.layout``): "auto" builds a sliced copy per call
     unless its padding would be large.
     """
 

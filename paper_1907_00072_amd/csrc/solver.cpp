@@ -66,7 +66,7 @@ struct Arena {
   size_t dev_cap = 0;
   char *aux = nullptr;  // composed operator (scaled copy of A, scaled b); outlives `dev` carving
   size_t aux_cap = 0;
-  char *mat = nullptr;  // sliced-ELL copy of the call's matrix; outlives `dev` carving
+  char *mat = nullptr;  // sliced copy of the call's matrix; outlives `dev` carving
   size_t mat_cap = 0;
   double *host = nullptr;  // pinned
   size_t host_cap = 0;     // in doubles
