@@ -118,6 +118,7 @@ def main():
     xs = x.cpu().numpy()
     As = P.A.to_scipy()
     relres_host = float(np.linalg.norm(P.b - As @ xs) / np.linalg.norm(P.b))
+    ref = oracle_reference(args.grid)
 
     bc = sum(s.bytes_chain for s in stats)
     tc = sum(s.t_chain for s in stats)
@@ -151,7 +152,7 @@ def main():
     }
     legs = {"pp_fp64": {"time_s": t_solve, "iters": st.iters, "cycles": st.cycles,
                         "spmvs": st.spmvs, "dots": st.dots, "relres": st.relres_true,
-                        "nroots": st.nroots}}
+                        "nroots": st.nroots, "err_vs_oracle": error_vs_oracle(ref, xs)}}
     wanted = [s for s in args.legs.split(",") if s and s != "none"]
     if "ir" in wanted:
         solve(precision="f32_ir")
@@ -165,6 +166,7 @@ def main():
                               "relres": s2.relres_true,
                               "rel_diff_vs_fp64": float(np.linalg.norm(xir - xs) /
                                                         np.linalg.norm(xs)),
+                              "err_vs_oracle": error_vs_oracle(ref, xir),
                               "chain_GBps": s2.bytes_chain / s2.t_chain / 1e9
                               if s2.t_chain > 0 else None}
         log(f"fp32-ir: {tir:.3f}s outer {s2.outer} inner {s2.iters} relres {s2.relres_true:.2e}")
@@ -264,6 +266,28 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def oracle_reference(grid):
+    """The oracle's own solve of the default workload (sampled entries), stored by
+    tests/golden/make_fullsize_refs.py; None for other grids."""
+    if grid != 256:
+        return None
+    try:
+        refs = json.load(open(os.path.join(ROOT, "tests", "golden", "fullsize_refs.json")))
+    except OSError:
+        return None
+    return refs.get("cd3d_256_pe100_d40")
+
+
+def error_vs_oracle(ref, x):
+    """Max |x - x_oracle| over the oracle's 64 sampled entries, relative to max |x_oracle|
+    (the oracle ran the same PP-GMRES(30), d = 40 to 1e-8 in FP64 on the host)."""
+    import numpy as np
+    if ref is None:
+        return None
+    idx = np.asarray(ref["sample_idx"])
+    return float(np.max(np.abs(x[idx] - np.asarray(ref["x_sample"]))) / ref["x_absmax"])
+
+
 def pmc_traffic(grid):
     """HBM bytes per middle chain launch from the committed rocprofv3 counter runs.
 
@@ -323,6 +347,14 @@ def cpu_baseline(P, As, B, A, v0, st):
     t_mv = time.perf_counter() - ts
     est = t_step * (st.iters + st.cycles) + P.d * t_mv
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     log(f"cpu baseline: step {t_step:.1f}s product {t_mv:.2f}s -> estimated solve {est:.0f}s")
     return {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
             "sample": (f"one preconditioned Arnoldi step (p(A)v with {len(roots)} roots in "
@@ -330,7 +362,8 @@ def cpu_baseline(P, As, B, A, v0, st):
                        f"full n={P.A.n} matrix took {t_step:.2f}s; one product {t_mv:.3f}s; "
                        f"scaled by the GPU solve's {st.iters} steps + {st.cycles} cycle-end "
                        f"updates + {P.d} build products.  SciPy CSR products are "
-                       f"single-threaded; BLAS dots use the available cores.")}
+                       f"single-threaded; BLAS dots use the available cores.  Host: {model}, "
+                       f"{os.cpu_count()} logical CPUs visible.")}
 
 
 if __name__ == "__main__":
