@@ -135,7 +135,10 @@ __device__ __forceinline__ T dia_batch(const T *__restrict__ sva, const T *__res
 #pragma unroll
   for (int q = 0; q < N; ++q) {
     v[q] = ldnt(sva + q * kSlice);
-    gl[q] = g[min(max(row + o[q], 0), last)];
+    // column in unsigned arithmetic: a present entry's column lies in [0, n); for an
+    // absent one the sum may fall outside (or wrap) and is clamped to row n - 1
+    const unsigned col = (unsigned)row + (unsigned)o[q];
+    gl[q] = g[min(col, (unsigned)last)];
   }
 #pragma unroll
   for (int q = 0; q < N; ++q) acc += v[q] * (v[q] != T(0) ? gl[q] : T(0));
