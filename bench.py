@@ -58,8 +58,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=256, help="grid points per axis (256 = headline)")
-    ap.add_argument("--legs", default="ir,plain,power,csr",
-                    help="comma list of extra legs: ir, plain, power, csr, none")
+    ap.add_argument("--legs", default="ir,plain,power,csr,jacobi",
+                    help="comma list of extra legs: ir, plain, power, csr, jacobi, none")
     ap.add_argument("--plain-max-iters", type=int, default=30000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-check", type=int, default=1,
@@ -205,6 +205,20 @@ def main():
                                       "chain_GBps": s5.bytes_chain / s5.t_chain / 1e9
                                       if s5.t_chain > 0 else None}
         log(f"csr layout: {tcsr:.3f}s iters {s5.iters} relres {s5.relres_true:.2e}")
+
+    if "jacobi" in wanted:
+        # composition with a left Jacobi preconditioner (the polynomial is built for D^-1 A);
+        # the stencil's diagonal is constant, so this measures the composition's overhead
+        solve(left_jacobi=True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        s6 = solve(left_jacobi=True)
+        torch.cuda.synchronize()
+        tj = time.perf_counter() - ts
+        legs["pp_fp64_left_jacobi"] = {"time_s": tj, "iters": s6.iters,
+                                       "relres_preconditioned": s6.relres_true,
+                                       "relres_original": s6.relres_original}
+        log(f"left jacobi: {tj:.3f}s iters {s6.iters} relres {s6.relres_original:.2e}")
 
     if args.copy_check:
         # torch's own device copy: context only (it is not a ceiling; a flat HIP copy

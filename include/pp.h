@@ -97,7 +97,10 @@ extern "C" {
  * the vector reads one diagonal (or one entry) of 64 consecutive rows.  The
  * copy costs about two passes over A per call.  AUTO keeps CSR when one product
  * on the copy would stream more than 1.25 x the bytes of the CSR product
- * (irregular row lengths).  Both layouts give the same products up to the
+ * (irregular row lengths), or when the call runs too few products to repay
+ * the copy (e.g. pp_apply with a handful of roots: each product is credited
+ * with the bytes it saves, at least 5% of a CSR product, against the bytes the
+ * conversion moves).  Both layouts give the same products up to the
  * rounding of the summation; an entry stored as an explicit 0 and an absent
  * one are treated alike. */
 typedef struct pp_csr {

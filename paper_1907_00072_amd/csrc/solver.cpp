@@ -746,9 +746,12 @@ int check_csr(const pp_csr *A) {
 
 // The sliced copy of a call's matrix (see SpMat): built on the device from the
 // CSR arrays into the arena's matrix buffer.  `use` is false when the caller
-// asked for CSR, or (PP_LAYOUT_AUTO) when one product would stream more than
-// 1.25 times the bytes of the CSR product, or when the stored slots would not
-// fit int32 offsets.
+// asked for CSR, when the stored slots would not fit int32 offsets, or
+// (PP_LAYOUT_AUTO) when one product would stream more than 1.25 times the bytes
+// of the CSR product, or when the call's `products` sparse products cannot
+// repay the copy: each is credited with the bytes it saves (at least 5% of the
+// CSR product, the sliced kernels' better bandwidth), against the bytes the
+// conversion moves.
 struct SellCopy {
   bool use = false;
   int64_t snnz = 0, ell = 0;
@@ -761,13 +764,22 @@ struct SellCopy {
 // want64 / want32: value arrays to fill (FP64 from A's values; FP32 from src32
 // when given, else from A's values).  Uses the main arena as scratch, so call it
 // before carving the solve's workspace.
-int make_sell(const pp_csr *A, bool want64, bool want32, const float *src32, hipStream_t s,
-              SellCopy *out) {
+int make_sell(const pp_csr *A, bool want64, bool want32, const float *src32, double products,
+              hipStream_t s, SellCopy *out) {
   *out = SellCopy{};
   if (A->layout == PP_LAYOUT_CSR) return PP_OK;
+  const int n = (int)A->n;
+  const double vb = A->dtype == PP_F64 ? 8.0 : 4.0;
+  const double csr = A->nnz * (vb + 4.0) + 4.0 * (n + 1);
+  const double idx_pass = 4.0 * A->nnz + 4.0 * (n + 1);  // one read of row_ptr and col_ind
+  const int nvals = (want64 ? 1 : 0) + (want32 ? 1 : 0);
+  if (A->layout == PP_LAYOUT_AUTO) {
+    // best case: every slice diagonal without padding (8 or 4 bytes per entry)
+    const double conv_min = 3.0 * idx_pass + nvals * (vb + 4.0) * A->nnz;
+    if (products * (csr - vb * A->nnz) < conv_min) return PP_OK;
+  }
   Arena *ar = nullptr;
   PP_TRY(current_arena(&ar));
-  const int n = (int)A->n;
   const int ns = (n + ppk::kSlice - 1) / ppk::kSlice;
   Carver meas(nullptr);
   meas.take<int32_t>(ns);
@@ -794,10 +806,10 @@ int make_sell(const pp_csr *A, bool want64, bool want32, const float *src32, hip
   if ((int64_t)96 * longest * ns >= ((int64_t)1 << 31)) return PP_OK;
   const int64_t snnz = h[0], ell = h[2], dmax = h[3];
   if (A->layout == PP_LAYOUT_AUTO) {
-    const double vb = A->dtype == PP_F64 ? 8.0 : 4.0;
     const double sliced = snnz * vb + ell * 4.0 + (snnz - ell) / 16.0 + 8.0 * ns;
-    const double csr = A->nnz * (vb + 4.0) + 4.0 * (n + 1);
-    if (sliced > 1.25 * csr) return PP_OK;
+    const double conv = 3.0 * idx_pass + nvals * vb * A->nnz +
+                        snnz * (nvals * vb + (ell > 0 ? 4.0 : 0.0));
+    if (sliced > 1.25 * csr || products * std::max(csr - sliced, 0.05 * csr) < conv) return PP_OK;
   }
   const int64_t cap = std::max<int64_t>(snnz, 1);
   // one batch of slack: the product kernel fetches whole batches of offsets
@@ -878,8 +890,8 @@ int apply_impl(const pp_csr *A, const pp_poly *p, const void *v, void *y, hipStr
   PP_TRY(current_arena(&ar));
   const int n = (int)A->n;
   SellCopy sc;
-  if (p->kind == 1 || !p->steps.empty())
-    PP_TRY(make_sell(A, sizeof(T) == 8, sizeof(T) == 4, nullptr, s, &sc));
+  const double products = p->kind == 1 ? (double)p->coeffs.size() - 1.0 : (double)p->steps.size();
+  if (products > 0) PP_TRY(make_sell(A, sizeof(T) == 8, sizeof(T) == 4, nullptr, products, s, &sc));
   Carver meas(nullptr);
   T *bufs[3];
   for (auto &b : bufs) b = meas.take<T>(pad_ld(n));
@@ -907,7 +919,7 @@ int build_impl(const pp_csr *A, const double *v0, int d, hipStream_t s, pp_poly 
   PP_TRY(current_arena(&ar));
   const int n = (int)A->n;
   SellCopy sc;
-  PP_TRY(make_sell(A, sizeof(T) == 8, sizeof(T) == 4, nullptr, s, &sc));
+  PP_TRY(make_sell(A, sizeof(T) == 8, sizeof(T) == 4, nullptr, d, s, &sc));
   Work<T> w;
   Carver meas(nullptr);
   w.carve(meas, n, d + 1);
@@ -942,6 +954,13 @@ struct SolveIn {
 // Products with A per application of the preconditioned operator A p(A).
 int poly_size(const pp_poly *p) {
   return p->kind == 1 ? (int)p->coeffs.size() : (int)p->re.size();
+}
+
+// A lower estimate of a solve's sparse products: the build's d, then one
+// restart cycle of m preconditioned steps (d products each) and its cycle end.
+double solve_products(const SolveIn &in) {
+  const int d = in.o.poly ? poly_size(in.o.poly) : in.d;
+  return (double)d + (double)in.m * std::max(d, 1) + (double)d + 1.0;
 }
 
 int worst(int a, int b) {
@@ -980,7 +999,7 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
   const int n = (int)in.A->n;
   const int L = std::max(in.m, in.o.poly ? 0 : in.d) + 1;
   SellCopy sc;
-  PP_TRY(make_sell(in.A, true, false, nullptr, in.s, &sc));
+  PP_TRY(make_sell(in.A, true, false, nullptr, solve_products(in), in.s, &sc));
   note_layout(st, in.A, sc);
   Work<double> w;
   Carver meas(nullptr);
@@ -1103,7 +1122,7 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
   const int64_t nnz = in.A->nnz;
   const int L = std::max(in.m, in.o.poly ? 0 : in.d) + 1;
   SellCopy sc;
-  PP_TRY(make_sell(in.A, true, true, in.o.vals_f32, in.s, &sc));
+  PP_TRY(make_sell(in.A, true, true, in.o.vals_f32, solve_products(in), in.s, &sc));
   note_layout(st, in.A, sc);
   // the FP32 CSR values are needed only when the products run on CSR
   const bool cast32 = !in.o.vals_f32 && !sc.use;
@@ -1346,7 +1365,7 @@ int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_deg
   auto go = [&](auto tag) -> int {
     using T = decltype(tag);
     SellCopy sc;
-    PP_TRY(make_sell(A, sizeof(T) == 8, sizeof(T) == 4, nullptr, s, &sc));
+    PP_TRY(make_sell(A, sizeof(T) == 8, sizeof(T) == 4, nullptr, deg + 1.0, s, &sc));
     Work<T> w;
     Carver meas(nullptr);
     w.carve(meas, n, L);

@@ -1,6 +1,7 @@
 """CPU tests of the C ABI: the library loads, exports every declared symbol, and
 its host-only numerics (harmonic Ritz eigenproblem, Leja order, root tables)
 agree with numpy / the oracle.  No device work is done here."""
+import ctypes
 import os
 import re
 
@@ -131,3 +132,43 @@ def test_host_validation_rejects_malformed_csr():
     with pytest.raises(ValueError):
         B.check_csr_host(np.array([0, 1, 3], np.int32), np.array([0, 1], np.int32), 2)
     B.check_csr_host(np.array([0, 1, 1, 2], np.int32), np.array([0, 2], np.int32), 3)
+
+
+def _c_layout(struct, fields):
+    """sizeof and offsetof of a pp.h struct, measured by compiling a tiny C program."""
+    import shutil
+    import subprocess
+    import tempfile
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    body = "".join(f'  printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"pp.h\"\nint main(void) {\n"
+           f'  printf("%zu\\n", sizeof({struct}));\n{body}  return 0;\n}}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(root, "include"), c, "-o", exe],
+                       check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("name", ["pp_csr", "pp_opts", "pp_stats"])
+def test_ctypes_structs_match_the_c_header(name):
+    from paper_1907_00072_amd import binding
+    cls = getattr(binding, name)
+    fields = [f[0] for f in cls._fields_]
+    size, offsets = _c_layout(name, fields)
+    assert ctypes.sizeof(cls) == size
+    assert [getattr(cls, f).offset for f in fields] == offsets
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr

@@ -579,3 +579,18 @@ def test_sliced_copy_stores_stencils_by_diagonal(B):
     assert per_launch <= 8.0 * stored + stored / 16.0 + 8.0 * ns + 4.0 + 32.0 * n
     # explicit columns would cost at least 12 bytes per stored slot plus 2 vectors
     assert 12.0 * stored + 16.0 * n > 8.0 * stored + stored / 16.0 + 8.0 * ns + 4.0 + 32.0 * n
+
+
+def test_auto_layout_keeps_csr_for_a_short_apply(B):
+    # two roots on a small stencil: the conversion would cost more than it saves, AUTO keeps
+    # CSR; the result is the same polynomial either way
+    Ah = W.config(1, N=48).A
+    roots = np.array([4.0, 6.0])
+    p = B.pp_poly_from_roots(Ah.n, roots)
+    v = W.uniform(Ah.n, 51)
+    ys = {lay: B.pp_apply(B.CSRMatrix.from_host(Ah, layout=lay), p, _up(v)).cpu().numpy()
+          for lay in ("auto", "csr", "sell")}
+    ref = opoly.apply_poly(Ah.to_scipy(), roots, v)
+    for lay, y in ys.items():
+        assert _rel(y, ref) <= 1e-13, lay
+    assert np.array_equal(ys["auto"], ys["csr"])
