@@ -18,14 +18,17 @@ constexpr int kSlice = 64;    // rows per slice of the sliced copy (one wavefron
 constexpr int kSellBatch = 8; // slots per row whose loads are in flight together
 
 // Sparse matrix view on the device: CSR, plus an optional sliced copy.
-// The sliced copy groups the rows in slices of kSlice; slice s has
-// w_s = (sp[s+1] - sp[s]) / kSlice slots per row, stored column-major (slot j
-// of row kSlice*s + l at sp[s] + kSlice*j + l).  A diagonal slice (sflag[s] =
-// 1) holds in slot j the entries on diagonal soff[s*dmax + j] (column = row +
-// offset), zero where a row has none; an explicit-column slice (sflag[s]
-// = 0) holds row l's entries in order with their columns in sci, padded with
-// column -1 and value 0.  When sp != nullptr the product kernels read only the
-// sliced arrays and never rp/ci/va.
+// The sliced copy groups the rows in slices of kSlice.  Slice s is described by
+// kDesc ints at sdesc[s * kDesc]: its value offset b_s, its slot count w_s, its
+// kind (1 = diagonal slice), 0, then the first kSellBatch diagonal offsets
+// (zeros past w_s or for explicit-column slices).  Its values are stored
+// column-major: slot j of row kSlice*s + l at b_s + kSlice*j + l.  A diagonal
+// slice holds in slot j the entries on diagonal soff[s*dmax + j] (column = row
+// + offset), zero where a row has none; an explicit-column slice holds row l's
+// entries in order with their columns in sci, padded with column -1 and value
+// 0.  When sdesc != nullptr the product kernels read only the sliced arrays and
+// never rp/ci/va.
+constexpr int kDesc = 16;  // ints per slice descriptor (one 64-byte scalar load)
 template <typename T>
 struct SpMat {
   int n;
@@ -33,14 +36,14 @@ struct SpMat {
   const int32_t *rp;
   const int32_t *ci;
   const T *va;
-  const int32_t *sp = nullptr;    // [ceil(n / kSlice) + 1]
-  const int32_t *sflag = nullptr; // [ceil(n / kSlice)]
+  const int32_t *sdesc = nullptr; // [ceil(n / kSlice) * kDesc]
   const int32_t *soff = nullptr;  // [ns * dmax + kSellBatch slack]
   const int32_t *sci = nullptr;   // [snnz] (nullptr when every slice is diagonal)
   const T *sva = nullptr;         // [snnz]
   int snnz = 0;                   // stored slots x kSlice, padding included
   int snnz_ell = 0;               // the part in explicit-column slices
   int dmax = 0;                   // most slots of a diagonal slice (soff stride)
+  int soff_extra = 0;             // diagonal offsets read from soff (past the descriptors)
 };
 
 // One launch of the fused product + root-update chain.
@@ -170,17 +173,18 @@ hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const do
 // Sliced-copy construction from CSR (ns = ceil(n / kSlice) slices).
 // plan: wlen[s] = kSlice * (slots of slice s) and flag[s] (1 = diagonal slice);
 //       stat[0] = longest row, stat[1] = kSlice * slots of the explicit-column
-//       slices, stat[2] = most slots of a diagonal slice (the caller zeroes
-//       stat[0..2] first and rejects the copy when 96 * stat[0] * ns >= 2^31,
-//       which also covers any wrap).
+//       slices, stat[2] = most slots of a diagonal slice, stat[3] = slots of
+//       diagonal slices past the descriptor's first kSellBatch (the caller
+//       zeroes stat[0..3] first and rejects the copy when
+//       96 * stat[0] * ns >= 2^31, which also covers any wrap).
 // Then sp = exclusive scan of wlen (launch_exclusive_scan), fill_idx writes the
-// diagonal offsets (soff[s * dmax + j], dmax = stat[2]) / explicit columns and
-// fill_vals the values (padding included).
+// slice descriptors, the diagonal offsets (soff[s * dmax + j], dmax = stat[2])
+// and the explicit columns, and fill_vals the values (padding included).
 hipError_t launch_slice_plan(int n, int ns, const int32_t *rp, const int32_t *ci, int32_t *wlen,
                              int32_t *flag, int32_t *stat, hipStream_t stream);
 hipError_t launch_slice_fill_idx(int n, int ns, int dmax, const int32_t *rp, const int32_t *ci,
-                                 const int32_t *sp, const int32_t *flag, int32_t *soff,
-                                 int32_t *sci, hipStream_t stream);
+                                 const int32_t *sp, const int32_t *flag, int32_t *sdesc,
+                                 int32_t *soff, int32_t *sci, hipStream_t stream);
 // sva = (D) va in sliced order (S, D in {float, double}).
 template <typename S, typename D>
 hipError_t launch_slice_fill_vals(int n, int ns, const int32_t *rp, const int32_t *ci, const S *va,

@@ -259,11 +259,10 @@ struct PolyRef {
 template <typename T>
 double product_bytes(const SpMat<T> &A, int vec_rw) {
   const double vecs = (double)sizeof(T) * A.n * (1 + vec_rw);
-  if (A.sp)  // sliced copy: stored values (padding included), explicit columns,
-             // diagonal offsets, slice offsets and flags
-    return (double)A.snnz * sizeof(T) + 4.0 * A.snnz_ell +
-           4.0 * (A.snnz - A.snnz_ell) / ppk::kSlice +
-           8.0 * ((A.n + ppk::kSlice - 1) / ppk::kSlice) + 4.0 + vecs;
+  if (A.sdesc)  // sliced copy: stored values (padding included), explicit columns,
+                // diagonal offsets past the descriptors, slice descriptors
+    return (double)A.snnz * sizeof(T) + 4.0 * A.snnz_ell + 4.0 * A.soff_extra +
+           4.0 * ppk::kDesc * ((A.n + ppk::kSlice - 1) / ppk::kSlice) + vecs;
   return (double)A.nnz * (sizeof(T) + sizeof(int32_t)) + 4.0 * (A.n + 1) + vecs;
 }
 
@@ -754,9 +753,9 @@ int check_csr(const pp_csr *A) {
 // conversion moves.
 struct SellCopy {
   bool use = false;
-  int64_t snnz = 0, ell = 0;
+  int64_t snnz = 0, ell = 0, extra = 0;
   int dmax = 0;
-  int32_t *sp = nullptr, *flag = nullptr, *soff = nullptr, *sci = nullptr;
+  int32_t *desc = nullptr, *soff = nullptr, *sci = nullptr;
   double *va64 = nullptr;
   float *va32 = nullptr;
 };
@@ -793,20 +792,21 @@ int make_sell(const pp_csr *A, bool want64, bool want32, const float *src32, dou
   int32_t *spt = c.take<int32_t>(ns + 1);
   int32_t *flagt = c.take<int32_t>(ns);
   int32_t *tmp = c.take<int32_t>(ppk::scan_tmp_size(ns));
-  // [0] longest row, [1] explicit-column slots, [2] most slots of a diagonal slice
+  // [0] longest row, [1] explicit-column slots, [2] most slots of a diagonal slice,
+  // [3] diagonal slots past the descriptors
   int32_t *stats = c.take<int32_t>(64);
-  PP_TRY_HIP(ppk::launch_fill<int32_t>(3, 0, stats, s));
+  PP_TRY_HIP(ppk::launch_fill<int32_t>(4, 0, stats, s));
   PP_TRY_HIP(ppk::launch_slice_plan(n, ns, A->row_ptr, A->col_ind, wlen, flagt, stats, s));
   PP_TRY_HIP(ppk::launch_exclusive_scan(ns, wlen, spt, tmp, s));
   int32_t *h = reinterpret_cast<int32_t *>(ar->host);
   PP_TRY_HIP(hipMemcpyAsync(h, spt + ns, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  PP_TRY_HIP(hipMemcpyAsync(h + 1, stats, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipMemcpyAsync(h + 1, stats, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   PP_TRY_HIP(hipStreamSynchronize(s));
   const int64_t longest = h[1];
   if ((int64_t)96 * longest * ns >= ((int64_t)1 << 31)) return PP_OK;
-  const int64_t snnz = h[0], ell = h[2], dmax = h[3];
+  const int64_t snnz = h[0], ell = h[2], dmax = h[3], extra = h[4];
   if (A->layout == PP_LAYOUT_AUTO) {
-    const double sliced = snnz * vb + ell * 4.0 + (snnz - ell) / 16.0 + 8.0 * ns;
+    const double sliced = snnz * vb + ell * 4.0 + extra * 4.0 + 4.0 * ppk::kDesc * ns;
     const double conv = 3.0 * idx_pass + nvals * vb * A->nnz +
                         snnz * (nvals * vb + (ell > 0 ? 4.0 : 0.0));
     if (sliced > 1.25 * csr || products * std::max(csr - sliced, 0.05 * csr) < conv) return PP_OK;
@@ -815,45 +815,43 @@ int make_sell(const pp_csr *A, bool want64, bool want32, const float *src32, dou
   // one batch of slack: the product kernel fetches whole batches of offsets
   const int64_t ocap = (int64_t)ns * dmax + ppk::kSellBatch;
   Carver mm(nullptr);
-  mm.take<int32_t>(ns + 1);
-  mm.take<int32_t>(ns);
+  mm.take<int32_t>((int64_t)ns * ppk::kDesc);
   mm.take<int32_t>(ocap);
   if (ell > 0) mm.take<int32_t>(cap);
   if (want64) mm.take<double>(cap);
   if (want32) mm.take<float>(cap);
   PP_TRY(ensure_side(&ar->mat, &ar->mat_cap, mm.off + 256));
   Carver m(ar->mat);
-  out->sp = m.take<int32_t>(ns + 1);
-  out->flag = m.take<int32_t>(ns);
+  out->desc = m.take<int32_t>((int64_t)ns * ppk::kDesc);
   out->soff = m.take<int32_t>(ocap);
   if (ell > 0) out->sci = m.take<int32_t>(cap);
   if (want64) out->va64 = m.take<double>(cap);
   if (want32) out->va32 = m.take<float>(cap);
-  PP_TRY_HIP(hipMemcpyAsync(out->sp, spt, (ns + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  PP_TRY_HIP(hipMemcpyAsync(out->flag, flagt, ns * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  PP_TRY_HIP(ppk::launch_slice_fill_idx(n, ns, (int)dmax, A->row_ptr, A->col_ind, out->sp,
-                                        out->flag, out->soff, out->sci, s));
+  // sp and the kinds stay in the scratch arena: only the fills below read them
+  PP_TRY_HIP(ppk::launch_slice_fill_idx(n, ns, (int)dmax, A->row_ptr, A->col_ind, spt, flagt,
+                                        out->desc, out->soff, out->sci, s));
   if (want64) {
     if (A->dtype != PP_F64) return PP_ERR_ARG;
     PP_TRY_HIP((ppk::launch_slice_fill_vals<double, double>(
-        n, ns, A->row_ptr, A->col_ind, static_cast<const double *>(A->vals), out->sp, out->flag,
+        n, ns, A->row_ptr, A->col_ind, static_cast<const double *>(A->vals), spt, flagt,
         out->va64, s)));
   }
   if (want32) {
     if (src32 || A->dtype == PP_F32) {
       const float *src = src32 ? src32 : static_cast<const float *>(A->vals);
       PP_TRY_HIP((ppk::launch_slice_fill_vals<float, float>(n, ns, A->row_ptr, A->col_ind, src,
-                                                            out->sp, out->flag, out->va32, s)));
+                                                            spt, flagt, out->va32, s)));
     } else {
       PP_TRY_HIP((ppk::launch_slice_fill_vals<double, float>(
-          n, ns, A->row_ptr, A->col_ind, static_cast<const double *>(A->vals), out->sp,
-          out->flag, out->va32, s)));
+          n, ns, A->row_ptr, A->col_ind, static_cast<const double *>(A->vals), spt, flagt,
+          out->va32, s)));
     }
   }
   out->use = true;
   out->snnz = snnz;
   out->ell = ell;
   out->dmax = (int)dmax;
+  out->extra = extra;
   return PP_OK;
 }
 
@@ -861,8 +859,7 @@ int make_sell(const pp_csr *A, bool want64, bool want32, const float *src32, dou
 template <typename T>
 SpMat<T> with_sell(SpMat<T> M, const SellCopy &c) {
   if (!c.use) return M;
-  M.sp = c.sp;
-  M.sflag = c.flag;
+  M.sdesc = c.desc;
   M.soff = c.soff;
   M.sci = c.sci;
   if constexpr (sizeof(T) == sizeof(double)) M.sva = c.va64;
@@ -870,6 +867,7 @@ SpMat<T> with_sell(SpMat<T> M, const SellCopy &c) {
   M.snnz = (int)c.snnz;
   M.snnz_ell = (int)c.ell;
   M.dmax = c.dmax;
+  M.soff_extra = (int)c.extra;
   return M;
 }
 
