@@ -17,15 +17,16 @@ GMRES(30) (no polynomial), each one timed solve after a warm-up.
 
 The library runs its sparse products on a sliced copy of the CSR matrix that
 it builds on the device at the start of each solve (64-row slices stored by
-diagonal: values plus one offset per slot, no column indices; 0.11% padding on
+diagonal: values plus a 64-byte descriptor per slice, no column indices; 0.11% padding on
 this stencil); the copy is part of every timed solve.  The `csr` leg times the
 same solve on the caller's CSR arrays.
 
 roofline: the fused product + root-update chain kernel dominates (39 of every
 40 products).  Its achieved bandwidth is the algorithmic bytes of the
-event-timed chain launches (8 nnz_stored + nnz_stored/16 + n/8 bytes of
-matrix, plus 16 n of vectors for a middle real-root step) over their
-event-timed duration, both accumulated by the library over the timed solves.
+event-timed chain launches (8 nnz_stored + n bytes of matrix: the values and
+one 64-byte descriptor per 64-row slice; plus 16 n of vectors for a middle
+real-root step) over their event-timed duration, both accumulated by the
+library over the timed solves.
 
 cpu_baseline: the CPU oracle (NumPy/SciPy, complex-arithmetic product form) on
 a bounded sample of the same solve: one preconditioned Arnoldi step on the full

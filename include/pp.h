@@ -169,10 +169,11 @@ typedef struct pp_stats {
    * Arnoldi steps' chains, operator products and CGS2 sweeps), from the
    * per-launch traffic model: a chain launch reads the matrix once (CSR: vals,
    * col_ind, row_ptr, 12 nnz + 4 n bytes in FP64; sliced copy: the stored values,
-   * the columns of explicit-column slices, one offset per slot of diagonal
-   * slices and the slice table, 8 nnz_stored + ... bytes), the gathered vector
-   * once and the accumulator / partner vectors once, and writes its outputs
-   * once.  Divided by t_chain / t_spmv / t_orth they give achieved bandwidth. */
+   * the columns of explicit-column slices, a 64-byte descriptor per 64-row slice
+   * and any diagonal offsets past the descriptor's first 8, 8 nnz_stored + n
+   * bytes for a stencil), the gathered vector once and the accumulator / partner
+   * vectors once, and writes its outputs once.  Divided by t_chain / t_spmv /
+   * t_orth they give achieved bandwidth. */
   double bytes_chain;
   double bytes_spmv;
   double bytes_orth;
