@@ -59,8 +59,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=256, help="grid points per axis (256 = headline)")
-    ap.add_argument("--legs", default="ir,plain,power,csr,jacobi",
-                    help="comma list of extra legs: ir, plain, power, csr, jacobi, none")
+    ap.add_argument("--legs", default="ir,plain,power,csr,jacobi,adjoint",
+                    help="comma list of extra legs: ir, plain, power, csr, jacobi, adjoint, none")
     ap.add_argument("--plain-max-iters", type=int, default=30000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-check", type=int, default=1,
@@ -221,6 +221,10 @@ def main():
                                        "relres_original": s6.relres_original}
         log(f"left jacobi: {tj:.3f}s iters {s6.iters} relres {s6.relres_original:.2e}")
 
+    if "adjoint" in wanted:
+        legs["adjoint_512"] = adjoint_leg(B, W, torch, dev)
+        log(f"adjoint 512^2: {legs['adjoint_512']['time_s']:.3f}s")
+
     if args.copy_check:
         # torch's own device copy: context only (it is not a ceiling; a flat HIP copy
         # kernel reaches more), and the reference kernel for the counter scaling
@@ -279,6 +283,40 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def adjoint_leg(B, W, torch, dev):
+    """Forward solve, adjoint solve on A^T and the gradient on the CSR pattern
+    (2D convection-diffusion 512^2, Pe 20, L = 0.5 ||x - x_t||^2, forward and
+    adjoint d = 15, tol 1e-12), through the torch autograd wrapper; one warm-up,
+    then one timed forward + backward."""
+    import warnings
+
+    from paper_1907_00072_amd.autograd import SolveConfig, pp_solve
+    P = W.config(4)
+    pattern = B.CSRMatrix.from_host(P.A, device=dev)
+    xt = torch.from_numpy(P.extra["x_target"]).to(dev)
+
+    def once():
+        vals = torch.from_numpy(P.A.vals).to(dev).requires_grad_(True)
+        bb = torch.from_numpy(P.b).to(dev).requires_grad_(True)
+        cfg = SolveConfig(m=P.m, d=P.d, tol=P.tol, v0=torch.from_numpy(P.v0).to(dev),
+                          adj_v0=torch.from_numpy(P.extra["v0_adjoint"]).to(dev))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        x = pp_solve(pattern, vals, bb, cfg)
+        loss = 0.5 * ((x - xt) ** 2).sum()
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")  # the adjoint may end on the stagnation test
+            loss.backward()
+        torch.cuda.synchronize()
+        return time.perf_counter() - ts, cfg
+    once()
+    t, cfg = once()
+    fwd, adj = cfg.stats[0][1], cfg.stats[1][1]
+    return {"time_s": t, "n": P.A.n, "nnz": P.A.nnz, "forward_iters": fwd.iters,
+            "adjoint_iters": adj.iters, "forward_relres": fwd.relres_true,
+            "adjoint_relres": adj.relres_true}
 
 
 def oracle_reference(grid):
