@@ -341,23 +341,33 @@ def error_vs_oracle(ref, x):
     return float(np.max(np.abs(x[idx] - np.asarray(ref["x_sample"]))) / ref["x_absmax"])
 
 
+def kernels_code_hash():
+    """sha256 prefix of kernels.hip with comments and blank lines removed, so the
+    counters stay valid across comment-only edits."""
+    import hashlib
+    import re
+    src = open(os.path.join(ROOT, "paper_1907_00072_amd", "csrc", "kernels.hip")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in src.splitlines()]
+    code = "\n".join(ln for ln in lines if ln.strip())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
+
+
 def pmc_traffic(grid):
     """HBM bytes per middle chain launch from the committed rocprofv3 counter runs.
 
-    Only reported while kernels.hip is the source those counters were taken
-    from (its sha256 prefix is recorded with them); otherwise None.
+    Only reported while kernels.hip's code is what those counters were taken
+    from (kernels_code_hash is recorded with them); otherwise None.
     """
-    import hashlib
     if grid != 256:
         return None
     path = os.path.join(ROOT, "profiles", "k_chain_cd3d_256_pe100_traffic.json")
-    src = os.path.join(ROOT, "paper_1907_00072_amd", "csrc", "kernels.hip")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = kernels_code_hash()
     except OSError:
         return None
-    return rec["traffic_bytes_per_dispatch"] if rec.get("kernels_hip_sha256_16") == sha else None
+    return rec["traffic_bytes_per_dispatch"] if rec.get("kernels_code_sha256_16") == sha else None
 
 
 def torch_copy_rate(torch, nbytes=2 << 30, reps=5):

@@ -5,30 +5,27 @@
 // streaming of the matrix and the Krylov basis from HBM and a single pass over
 // each per step.
 //
-// * Sparse products use a "CSR-stream" tile: a workgroup owns 256 consecutive
-//   rows; its threads first stream the tile's nonzeros contiguously (values,
-//   column indices and the gathered vector entry), writing the products into
-//   LDS, then each thread sums its own row from LDS.  Short stencil rows (5, 7 or
-//   27 entries) therefore cost fully coalesced loads instead of one
-//   partially-used cache line per row per lane.  The root update of the
-//   polynomial chain is fused into the epilogue of the same tile, so one launch
-//   reads A once and the chain vectors once.
-//   Each thread issues all of its column-index and value loads for a chunk
-//   before any gather, so a tile costs two memory latencies, not one per
-//   nonzero; own-row operands are fetched before the reduction; streamed
-//   vectors use non-temporal loads and stores so the L2 keeps the gathered
-//   vector.
-// * When the view carries a sliced copy (64-row slices, column-major inside a
-//   slice) the same kernels run on it instead: lane l of a wavefront owns row
-//   64 s + l and the loads of slot j of the slice's 64 rows are one contiguous
-//   burst.  A slice whose rows use few distinct diagonals (col - row) is stored
-//   by diagonal: slot j holds diagonal soff[j] for all 64 rows (zero where a
-//   row lacks it), so no column indices are stored and the gather becomes a
-//   contiguous shifted load.  Other slices store explicit columns (ELL); their
-//   gather for slot j still touches one entry of 64 consecutive rows rather than
-//   every diagonal of a handful of rows as in the CSR-stream tile.  No row
-//   pointers, no LDS and no barrier are needed.  The CSR path is kept for
-//   matrices whose slices would need heavy padding.
+// * Sparse products (the polynomial chain, the outer product, the residual)
+//   run by default on a sliced copy of A: 64-row slices, one per wavefront,
+//   stored slot-major, so lane l owns row 64 s + l and the loads of slot j of
+//   the slice's 64 rows are one contiguous burst.  A slice whose rows use few
+//   distinct diagonals (col - row) is stored by diagonal: slot j holds one
+//   diagonal for all 64 rows (zero where a row lacks it), no column indices are
+//   stored, and the gather becomes a contiguous shifted load.  Other slices
+//   keep explicit columns; their gather for slot j still touches one entry of
+//   64 consecutive rows.  A 64-byte descriptor per slice (value offset, slot
+//   count, kind, first diagonal offsets) arrives in one scalar burst; each
+//   batch of up to 8 slots issues all its loads before the first use.  No row
+//   pointers, no LDS, no barrier.  FP32 products take two slices per wavefront
+//   to keep more bytes in flight.  The root update of the polynomial chain is
+//   fused into the epilogue, so one launch reads A once and the chain vectors
+//   once; streamed data use non-temporal loads and stores so the L2 keeps the
+//   gathered vector.
+// * The CSR path (matrices whose slices would need heavy padding) is a
+//   "CSR-stream" tile: a workgroup owns 256 consecutive rows; its threads
+//   stream the tile's nonzeros contiguously (all index and value loads of a
+//   chunk issued before any gather), write the products into LDS, then each
+//   thread sums its own row.
 // * Workgroups of the sparse products take their 256-row tiles in groups of 16
 //   consecutive tiles per XCD (workgroups are dealt to the 8 XCDs round-robin),
 //   so most of a tile's neighbouring rows were fetched into the same XCD's L2.
@@ -37,7 +34,8 @@
 //   every basis column once and updates the vector and accumulates the next
 //   pass's dot products in the same sweep.  Column loads are branch-free (the
 //   index is clamped to the last live column and the extra products carry a
-//   zero coefficient), so all of a row's loads are in flight together.
+//   zero coefficient), so all of a row's loads are in flight together.  Rows
+//   per thread are chosen per sweep kind (orth_rpt).
 // * All reductions are two-stage in a fixed order (per-workgroup partials in
 //   memory, then a second kernel), with no floating-point atomics, so results
 //   are bitwise reproducible.
