@@ -63,6 +63,9 @@ def main():
                     help="comma list of extra legs: ir, plain, power, csr, jacobi, adjoint, none")
     ap.add_argument("--plain-max-iters", type=int, default=30000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the default line: time-to-tol on every workload configuration "
+                         "(one JSON object)")
     ap.add_argument("--copy-check", type=int, default=1,
                     help="also time torch's 2 GiB device copy (the reference kernel that scales "
                          "the rocprofv3 byte counters)")
@@ -80,6 +83,9 @@ def main():
     from paper_1907_00072_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.sweep:
+        print(json.dumps(sweep(B, W, torch, dev, args.steps)), flush=True)
+        return
     t0 = time.perf_counter()
     P = W.config(5, N=args.grid)
     log(f"generated {P.name} grid {args.grid}^3: n={P.A.n} nnz={P.A.nnz} "
@@ -283,6 +289,48 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def sweep(B, W, torch, dev, steps):
+    """Time-to-tol (mean of `steps` solves after one warm-up, build included) on each
+    workload configuration: PP-GMRES at the configuration's d (and every d it lists),
+    plain GMRES, and FP32 inside FP64 refinement where the configuration asks for it."""
+    import warnings
+    out = {}
+    for k in sorted(W.CONFIG_NAMES):
+        P = W.config(k)
+        A = B.CSRMatrix.from_host(P.A, device=dev)
+        b = torch.from_numpy(P.b).to(dev)
+        v0 = torch.from_numpy(P.v0).to(dev)
+        x = torch.zeros_like(b)
+        rec = {"n": P.A.n, "nnz": P.A.nnz, "m": P.m, "tol": P.tol}
+
+        def timed(**kw):
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore")
+                x.zero_()
+                B.pp_gmres_solve(A, b, x, m=P.m, tol=P.tol, v0=v0, **kw)
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                for _ in range(steps):
+                    x.zero_()
+                    _, st = B.pp_gmres_solve(A, b, x, m=P.m, tol=P.tol, v0=v0, **kw)
+                torch.cuda.synchronize()
+            return {"time_s": (time.perf_counter() - ts) / steps, "iters": st.iters,
+                    "relres": st.relres_true, "layout": st.layout_used}
+        for d in P.extra.get("degrees", [P.d]):
+            rec[f"pp_d{d}" if d else "gmres"] = timed(d=d)
+        if "gmres" not in rec:
+            rec["gmres"] = timed(d=0, max_iters=30000)
+        if "inner_tol" in P.extra:
+            rec[f"pp_d{P.d}_f32_ir"] = timed(d=P.d, precision="f32_ir",
+                                            inner_tol=P.extra["inner_tol"])
+        out[P.name] = rec
+        log(f"{P.name}: " + ", ".join(f"{key} {v['time_s']:.4f}s/{v['iters']}it"
+                                      for key, v in rec.items() if isinstance(v, dict)))
+        del A, b, v0, x
+        torch.cuda.empty_cache()
+    return {"sweep": out, "steps": steps, "data": "synthetic"}
 
 
 def adjoint_leg(B, W, torch, dev):
