@@ -787,6 +787,43 @@ __device__ __forceinline__ int next_diagonal(const int32_t *__restrict__ ci, int
   return m;
 }
 
+// Rows of at most kRowRegs entries are staged in registers for the merge
+// (one burst of loads per lane instead of one dependent load per step).
+constexpr int kRowRegs = 32;
+
+// This lane's row in registers: columns c[q] (INT_MAX past the row) and, when V
+// is not void, values v[q].
+template <typename S>
+__device__ __forceinline__ void stage_row(const int32_t *__restrict__ ci, const S *__restrict__ va,
+                                          int rb, int len, int *c, S *v) {
+#pragma unroll
+  for (int q = 0; q < kRowRegs; ++q) {
+    c[q] = q < len ? ci[rb + q] : INT_MAX;
+    if (va) v[q] = q < len ? va[rb + q] : S(0);
+  }
+}
+
+// Register form of next_diagonal on a staged row: the lane's next column is
+// c[0]; taking it shifts the row (and its values) left by one.  Returns m and
+// sets *hit when this lane's entry lies on diagonal m.
+template <typename S>
+__device__ __forceinline__ int next_diagonal_regs(int *c, S *v, int row, bool *hit) {
+  const int cur = c[0] == INT_MAX ? INT_MAX : c[0] - row;
+  int m = cur;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
+  *hit = cur == m && m != INT_MAX;
+  if (*hit) {
+#pragma unroll
+    for (int q = 0; q + 1 < kRowRegs; ++q) {
+      c[q] = c[q + 1];
+      v[q] = v[q + 1];
+    }
+    c[kRowRegs - 1] = INT_MAX;
+  }
+  return m;
+}
+
 // Plan of the sliced copy: per slice, the longest row w and the slot count:
 // the number of distinct diagonals when every row's columns strictly increase
 // and that number is at most 1.5 w (then flag = 1: stored by diagonal), else w
@@ -814,15 +851,27 @@ __global__ __launch_bounds__(kBlock) void k_slice_plan(int n, int ns,
   int w = len;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, 64));
+  const bool regs = w <= kRowRegs;  // uniform
+  int c[kRowRegs];
+  char nov[kRowRegs];  // no values needed here
   bool sorted = true;
-  for (int k = 1; k < len; ++k) sorted = sorted && (ci[rb + k] > ci[rb + k - 1]);
+  if (regs) {
+    stage_row<char>(ci, nullptr, rb, len, c, nov);
+#pragma unroll
+    for (int q = 1; q < kRowRegs; ++q) sorted = sorted && (q >= len || c[q] > c[q - 1]);
+  } else {
+    for (int k = 1; k < len; ++k) sorted = sorted && (ci[rb + k] > ci[rb + k - 1]);
+  }
   const bool all_sorted = __ballot(!sorted) == 0;
   int slots = w, dia = 0;
   if (s < ns && all_sorted && w > 0) {
     const int cap = w + w / 2;
     int p = 0, take = -1, cnt = 0;
+    bool hit = false;
     while (cnt <= cap) {  // cnt and the returned m are uniform across the wavefront
-      if (next_diagonal(ci, rb, len, i, &p, &take) == INT_MAX) break;
+      const int m = regs ? next_diagonal_regs<char>(c, nov, i, &hit)
+                         : next_diagonal(ci, rb, len, i, &p, &take);
+      if (m == INT_MAX) break;
       ++cnt;
     }
     if (cnt <= cap) {
@@ -869,9 +918,18 @@ __global__ __launch_bounds__(kBlock) void k_slice_fill_idx(int n, int ns, int dm
     len = rp[i + 1] - rb;
   }
   if (flag[s]) {
+    int lw = len;  // longest row of the slice (uniform), to pick the register path
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lw = max(lw, __shfl_xor(lw, off, 64));
+    int c[kRowRegs];
+    char nov[kRowRegs];
+    const bool regs = lw <= kRowRegs;
+    if (regs) stage_row<char>(ci, nullptr, rb, len, c, nov);
     int p = 0, take = -1;
+    bool hit = false;
     for (int j = 0; j < w; ++j) {
-      const int m = next_diagonal(ci, rb, len, i, &p, &take);
+      const int m = regs ? next_diagonal_regs<char>(c, nov, i, &hit)
+                         : next_diagonal(ci, rb, len, i, &p, &take);
       if (lane == 0) {
         soff[(int64_t)s * dmax + j] = m;
         if (j < kSellBatch) d[4 + j] = m;
@@ -902,10 +960,25 @@ __global__ __launch_bounds__(kBlock) void k_slice_fill_vals(int n, int ns,
     len = rp[i + 1] - rb;
   }
   if (flag[s]) {
-    int p = 0, take = -1;
-    for (int j = 0; j < w; ++j) {
-      (void)next_diagonal(ci, rb, len, i, &p, &take);
-      sva[base + j * kSlice + lane] = take >= 0 ? (D)va[rb + take] : D(0);
+    int lw = len;  // longest row of the slice (uniform), to pick the register path
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lw = max(lw, __shfl_xor(lw, off, 64));
+    if (lw <= kRowRegs) {
+      int c[kRowRegs];
+      S v[kRowRegs];
+      stage_row<S>(ci, va, rb, len, c, v);
+      bool hit = false;
+      for (int j = 0; j < w; ++j) {
+        const S head = v[0];  // the entry a hit takes, before the row shifts
+        (void)next_diagonal_regs<S>(c, v, i, &hit);
+        sva[base + j * kSlice + lane] = hit ? (D)head : D(0);
+      }
+    } else {
+      int p = 0, take = -1;
+      for (int j = 0; j < w; ++j) {
+        (void)next_diagonal(ci, rb, len, i, &p, &take);
+        sva[base + j * kSlice + lane] = take >= 0 ? (D)va[rb + take] : D(0);
+      }
     }
   } else {
     for (int j = 0; j < w; ++j) sva[base + j * kSlice + lane] = j < len ? (D)va[rb + j] : D(0);
