@@ -171,17 +171,18 @@ hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const do
                            const double *x, double *g, hipStream_t stream);
 
 // Sliced-copy construction from CSR (ns = ceil(n / kSlice) slices).
-// plan: wlen[s] = kSlice * (slots of slice s) and flag[s] (1 = diagonal slice);
+// plan: wlen[s] = kSlice * (slots of slice s), flag[s] (1 = diagonal slice),
+//       wrow[s] = longest row of slice s, and (a second, one-workgroup kernel)
 //       stat[0] = longest row, stat[1] = kSlice * slots of the explicit-column
 //       slices, stat[2] = most slots of a diagonal slice, stat[3] = slots of
-//       diagonal slices past the descriptor's first kSellBatch (the caller
-//       zeroes stat[0..3] first and rejects the copy when
-//       96 * stat[0] * ns >= 2^31, which also covers any wrap).
+//       diagonal slices past the descriptor's first kSellBatch (sums saturate at
+//       INT_MAX; the caller rejects the copy when 96 * stat[0] * ns >= 2^31,
+//       which also covers any wrap).
 // Then sp = exclusive scan of wlen (launch_exclusive_scan), fill_idx writes the
 // slice descriptors, the diagonal offsets (soff[s * dmax + j], dmax = stat[2])
 // and the explicit columns, and fill_vals the values (padding included).
 hipError_t launch_slice_plan(int n, int ns, const int32_t *rp, const int32_t *ci, int32_t *wlen,
-                             int32_t *flag, int32_t *stat, hipStream_t stream);
+                             int32_t *flag, int32_t *wrow, int32_t *stat, hipStream_t stream);
 hipError_t launch_slice_fill_idx(int n, int ns, int dmax, const int32_t *rp, const int32_t *ci,
                                  const int32_t *sp, const int32_t *flag, int32_t *sdesc,
                                  int32_t *soff, int32_t *sci, hipStream_t stream);

@@ -828,21 +828,16 @@ __device__ __forceinline__ int next_diagonal_regs(int *c, S *v, int row, bool *h
 // the number of distinct diagonals when every row's columns strictly increase
 // and that number is at most 1.5 w (then flag = 1: stored by diagonal), else w
 // (flag = 0: explicit columns).  wlen[s] = 64 * slots (wrapping modulo 2^32),
-// stat[0] = max(stat[0], longest row), stat[1] += 64 * slots of explicit-column
-// slices, stat[2] = max(stat[2], slots of a diagonal slice), stat[3] += slots of
-// diagonal slices past the descriptor's kSellBatch (the caller zeroes them
-// first and rejects the copy when 96 * stat[0] * ns >= 2^31, which also covers
-// any wrap).
+// wrow[s] = w.  No atomics: k_slice_stats reduces the per-slice values.
 __global__ __launch_bounds__(kBlock) void k_slice_plan(int n, int ns,
                                                        const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci,
                                                        int32_t *__restrict__ wlen,
                                                        int32_t *__restrict__ flag,
-                                                       int32_t *stat) {
-  __shared__ int32_t red[kBlock / 64];
+                                                       int32_t *__restrict__ wrow) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int s = i / kSlice;  // uniform across the wavefront
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   int rb = 0, len = 0;
   if (i < n) {
     rb = rp[i];
@@ -879,18 +874,55 @@ __global__ __launch_bounds__(kBlock) void k_slice_plan(int n, int ns,
       dia = 1;
     }
   }
-  if (lane == 0) {
-    if (s < ns) {
-      wlen[s] = (int32_t)((uint32_t)kSlice * (uint32_t)slots);
-      flag[s] = dia;
-      if (!dia && slots > 0) atomicAdd(stat + 1, (int32_t)((uint32_t)kSlice * (uint32_t)slots));
-      if (dia) atomicMax(stat + 2, slots);
-      if (dia && slots > kSellBatch) atomicAdd(stat + 3, slots - kSellBatch);
+  if (lane == 0 && s < ns) {
+    wlen[s] = (int32_t)((uint32_t)kSlice * (uint32_t)slots);
+    flag[s] = dia;
+    wrow[s] = w;
+  }
+}
+
+// Totals of the plan in one workgroup, in a fixed order: stat[0] = longest row,
+// stat[1] = 64 * slots of explicit-column slices, stat[2] = most slots of a
+// diagonal slice, stat[3] = slots of diagonal slices past the descriptor's
+// kSellBatch (sums saturate at INT_MAX; the caller rejects the copy when
+// 96 * stat[0] * ns >= 2^31).
+__global__ __launch_bounds__(1024) void k_slice_stats(int ns, const int32_t *__restrict__ wlen,
+                                                      const int32_t *__restrict__ flag,
+                                                      const int32_t *__restrict__ wrow,
+                                                      int32_t *__restrict__ stat) {
+  __shared__ int64_t red[4][1024 / 64];
+  int64_t mrow = 0, ell = 0, dmax = 0, extra = 0;
+  for (int s = threadIdx.x; s < ns; s += 1024) {
+    const int64_t slots = (uint32_t)wlen[s] / kSlice;
+    mrow = max(mrow, (int64_t)wrow[s]);
+    if (flag[s]) {
+      dmax = max(dmax, slots);
+      extra += max(slots - kSellBatch, (int64_t)0);
+    } else {
+      ell += kSlice * slots;
     }
-    red[wv] = w;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mrow = max(mrow, (int64_t)__shfl_xor(mrow, off, 64));
+    dmax = max(dmax, (int64_t)__shfl_xor(dmax, off, 64));
+    ell += __shfl_xor(ell, off, 64);
+    extra += __shfl_xor(extra, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wv] = mrow;
+    red[1][wv] = ell;
+    red[2][wv] = dmax;
+    red[3][wv] = extra;
   }
   __syncthreads();
-  if (threadIdx.x == 0) atomicMax(stat, max(max(red[0], red[1]), max(red[2], red[3])));
+  if (threadIdx.x < 4) {
+    const int q = threadIdx.x;
+    int64_t r = red[q][0];
+    for (int k = 1; k < 1024 / 64; ++k) r = (q == 0 || q == 2) ? max(r, red[q][k]) : r + red[q][k];
+    stat[q] = (int32_t)min(r, (int64_t)INT_MAX);
+  }
 }
 
 // Index part of the sliced copy: the diagonal offsets of diagonal slices
@@ -1262,10 +1294,11 @@ hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const do
 }
 
 hipError_t launch_slice_plan(int n, int ns, const int32_t *rp, const int32_t *ci, int32_t *wlen,
-                             int32_t *flag, int32_t *stat, hipStream_t stream) {
+                             int32_t *flag, int32_t *wrow, int32_t *stat, hipStream_t stream) {
   if (ns <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_slice_plan, dim3(blocks_of((int64_t)ns * kSlice)), dim3(kBlock), 0, stream,
-                     n, ns, rp, ci, wlen, flag, stat);
+                     n, ns, rp, ci, wlen, flag, wrow);
+  hipLaunchKernelGGL(k_slice_stats, dim3(1), dim3(1024), 0, stream, ns, wlen, flag, wrow, stat);
   return hipGetLastError();
 }
 

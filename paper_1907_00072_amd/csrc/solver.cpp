@@ -784,6 +784,7 @@ int make_sell(const pp_csr *A, bool want64, bool want32, const float *src32, dou
   meas.take<int32_t>(ns);
   meas.take<int32_t>(ns + 1);
   meas.take<int32_t>(ns);
+  meas.take<int32_t>(ns);
   meas.take<int32_t>(ppk::scan_tmp_size(ns));
   meas.take<int32_t>(64);
   PP_TRY(ensure_arena(ar, meas.off + 256, 64));
@@ -791,12 +792,12 @@ int make_sell(const pp_csr *A, bool want64, bool want32, const float *src32, dou
   int32_t *wlen = c.take<int32_t>(ns);
   int32_t *spt = c.take<int32_t>(ns + 1);
   int32_t *flagt = c.take<int32_t>(ns);
+  int32_t *wrow = c.take<int32_t>(ns);
   int32_t *tmp = c.take<int32_t>(ppk::scan_tmp_size(ns));
   // [0] longest row, [1] explicit-column slots, [2] most slots of a diagonal slice,
   // [3] diagonal slots past the descriptors
   int32_t *stats = c.take<int32_t>(64);
-  PP_TRY_HIP(ppk::launch_fill<int32_t>(4, 0, stats, s));
-  PP_TRY_HIP(ppk::launch_slice_plan(n, ns, A->row_ptr, A->col_ind, wlen, flagt, stats, s));
+  PP_TRY_HIP(ppk::launch_slice_plan(n, ns, A->row_ptr, A->col_ind, wlen, flagt, wrow, stats, s));
   PP_TRY_HIP(ppk::launch_exclusive_scan(ns, wlen, spt, tmp, s));
   int32_t *h = reinterpret_cast<int32_t *>(ar->host);
   PP_TRY_HIP(hipMemcpyAsync(h, spt + ns, sizeof(int32_t), hipMemcpyDeviceToHost, s));
