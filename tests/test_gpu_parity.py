@@ -77,7 +77,7 @@ def test_apply_matches_oracle_fp64(B, name, d, layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("name,d", APPLY_CASES[:4])
+@pytest.mark.parametrize("name,d", APPLY_CASES)
 def test_apply_matches_oracle_fp32(B, name, d, layout):
     Ah = _matrix(name)
     As = Ah.to_scipy()
