@@ -29,9 +29,10 @@ real-root step) over their event-timed duration, both accumulated by the
 library over the timed solves.
 
 cpu_baseline: the CPU oracle (NumPy/SciPy, complex-arithmetic product form) on
-a bounded sample of the same solve: one preconditioned Arnoldi step on the full
-matrix with the GPU's roots, plus one plain product; scaled to a solve as
-t_step * (iterations + cycles) + d * t_product (the build's d products).
+a bounded sample of the same solve (one p(A)v with the GPU's roots, one product,
+one Gram-Schmidt column unit, all on the full matrix), scaled to the GPU solve's
+step, cycle, build-product and CGS2 column counts; `cores` is the number of
+threads the sample kept busy (CPU time over wall time).
 """
 from __future__ import annotations
 
@@ -435,7 +436,16 @@ def torch_copy_rate(torch, nbytes=2 << 30, reps=5):
 
 
 def cpu_baseline(P, As, B, A, v0, st):
-    """Oracle timed on a bounded sample of the same solve (see module docstring)."""
+    """Oracle timed on a bounded sample of the same solve (see module docstring).
+
+    Timed on the full matrix: one application of p(A) by the oracle (complex
+    arithmetic, one root at a time), one sparse product, and one Gram-Schmidt
+    column unit (a dot and an axpy of length n).  The estimate charges every
+    Arnoldi step of the GPU solve (and each cycle end) one p(A) and one product,
+    the build its d products, and both their CGS2 sweeps 3 (j + 1) column units at
+    step j.  `cores` is the CPU time of the sample over its wall time: the threads
+    it actually kept busy.
+    """
     import numpy as np
 
     from oracle import poly as op
@@ -443,21 +453,25 @@ def cpu_baseline(P, As, B, A, v0, st):
     poly = B.pp_build_poly(A, v0, P.d)
     roots = poly.roots()
     r0 = P.b / np.linalg.norm(P.b)
-    log("cpu baseline: one oracle preconditioned Arnoldi step on the full matrix")
+    log("cpu baseline: oracle p(A)v, one product and one CGS column unit on the full matrix")
+    c0, w0 = time.process_time(), time.perf_counter()
     ts = time.perf_counter()
     z = op.apply_poly(As, roots, r0)
-    w = As @ z
-    h = r0 @ w
-    w = w - h * r0
-    h2 = r0 @ w
-    w = w - h2 * r0
-    _ = np.linalg.norm(w)
-    t_step = time.perf_counter() - ts
+    t_poly = time.perf_counter() - ts
     ts = time.perf_counter()
-    _ = As @ r0
+    w = As @ z
     t_mv = time.perf_counter() - ts
-    est = t_step * (st.iters + st.cycles) + P.d * t_mv
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    ts = time.perf_counter()
+    for _ in range(3):
+        h = r0 @ w
+        w = w - h * r0
+    t_col = (time.perf_counter() - ts) / 3
+    cpu, wall = time.process_time() - c0, time.perf_counter() - w0
+    build_cols = sum(3 * (j + 1) for j in range(P.d))
+    gmres_cols = sum(3 * (j % P.m + 1) for j in range(st.iters))
+    est = ((st.iters + st.cycles) * (t_poly + t_mv) + P.d * t_mv +
+           (build_cols + gmres_cols) * t_col)
+    cores = max(1, round(cpu / wall))
     model = "unknown CPU"
     try:
         for line in open("/proc/cpuinfo"):
@@ -466,15 +480,16 @@ def cpu_baseline(P, As, B, A, v0, st):
                 break
     except OSError:
         pass
-    log(f"cpu baseline: step {t_step:.1f}s product {t_mv:.2f}s -> estimated solve {est:.0f}s")
+    log(f"cpu baseline: p(A)v {t_poly:.1f}s, product {t_mv:.3f}s, column {t_col:.3f}s "
+        f"-> estimated solve {est:.0f}s ({cpu / wall:.1f} threads busy)")
     return {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
-            "sample": (f"one preconditioned Arnoldi step (p(A)v with {len(roots)} roots in "
-                       f"complex arithmetic, one product, two CGS passes on one column) on the "
-                       f"full n={P.A.n} matrix took {t_step:.2f}s; one product {t_mv:.3f}s; "
-                       f"scaled by the GPU solve's {st.iters} steps + {st.cycles} cycle-end "
-                       f"updates + {P.d} build products.  SciPy CSR products are "
-                       f"single-threaded; BLAS dots use the available cores.  Host: {model}, "
-                       f"{os.cpu_count()} logical CPUs visible.")}
+            "sample": (f"on the full n={P.A.n} matrix: the oracle's p(A)v with {len(roots)} roots "
+                       f"(complex arithmetic) {t_poly:.2f}s, one product {t_mv:.3f}s, one CGS "
+                       f"column unit (dot + axpy) {t_col:.4f}s; scaled to the GPU solve's "
+                       f"{st.iters} steps + {st.cycles} cycle ends (p(A) and a product each), "
+                       f"{P.d} build products and {build_cols + gmres_cols} CGS2 column units.  "
+                       f"The sample kept {cpu / wall:.1f} threads busy (SciPy CSR products are "
+                       f"single-threaded).  Host: {model}, {os.cpu_count()} logical CPUs visible.")}
 
 
 if __name__ == "__main__":
