@@ -398,21 +398,33 @@ __global__ __launch_bounds__(kBlock) void k_chain(SpMat<T> A, ChainArgs<T> a) {
   }
 }
 
-template <typename T, bool SELL>
+// R rows per thread as in k_chain (R = 2 only on the sliced copy).
+template <typename T, bool SELL, int R>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpMat<T> A, const T *__restrict__ g,
                                                  const double *gscale, T *__restrict__ out) {
-  const int r0 = xcd_tile(blockIdx.x, gridDim.x) * kBlock;
-  const int nrows = min(kBlock, A.n - r0);
-  const int i = r0 + threadIdx.x;
-  int rb = 0, re = 0;
-  if constexpr (!SELL) {
-    if ((int)threadIdx.x < nrows) {
-      rb = A.rp[i];
-      re = A.rp[i + 1];
+  static_assert(R == 1 || (R == 2 && SELL), "two rows per thread need the sliced copy");
+  const int r0 = xcd_tile(blockIdx.x, gridDim.x) * kBlock * R;
+  const int t = threadIdx.x;
+  T acc[R];
+  if constexpr (R == 1) {
+    const int nrows = min(kBlock, A.n - r0);
+    int rb = 0, re = 0;
+    if constexpr (!SELL) {
+      if (t < nrows) {
+        rb = A.rp[r0 + t];
+        re = A.rp[r0 + t + 1];
+      }
     }
+    acc[0] = row_product<T, SELL>(A, g, r0, nrows, rb, re);
+  } else {
+    sell_row_sum2(A, g, r0 + t, r0 + kBlock + t, &acc[0], &acc[1]);
   }
-  const T acc = row_product<T, SELL>(A, g, r0, nrows, rb, re);
-  if ((int)threadIdx.x < nrows) stnt((gscale ? (T)(*gscale) : T(1)) * acc, out + i);
+  const T gs = gscale ? (T)(*gscale) : T(1);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = r0 + r * kBlock + t;
+    if (i < A.n) stnt(gs * acc[r], out + i);
+  }
 }
 
 template <typename T, bool SELL>
@@ -1097,11 +1109,14 @@ hipError_t launch_axpy(int n, double c, const T *g, const double *gscale, const 
 template <typename T>
 hipError_t launch_spmv(const SpMat<T> &A, const T *g, const double *gscale, T *out,
                        hipStream_t stream) {
-  if (A.sdesc)
-    hipLaunchKernelGGL((k_spmv<T, true>), dim3(tiles_of(A.n)), dim3(kBlock), 0, stream, A, g,
+  if (A.sdesc && sizeof(T) == sizeof(float))
+    hipLaunchKernelGGL((k_spmv<T, true, 2>), dim3((A.n + 2 * kBlock - 1) / (2 * kBlock)),
+                       dim3(kBlock), 0, stream, A, g, gscale, out);
+  else if (A.sdesc)
+    hipLaunchKernelGGL((k_spmv<T, true, 1>), dim3(tiles_of(A.n)), dim3(kBlock), 0, stream, A, g,
                        gscale, out);
   else
-    hipLaunchKernelGGL((k_spmv<T, false>), dim3(tiles_of(A.n)), dim3(kBlock), 0, stream, A, g,
+    hipLaunchKernelGGL((k_spmv<T, false, 1>), dim3(tiles_of(A.n)), dim3(kBlock), 0, stream, A, g,
                        gscale, out);
   return hipGetLastError();
 }
