@@ -18,6 +18,9 @@ gmres    -- right-preconditioned restarted GMRES(m) with two-pass classical
             refinement loop.
 adjoint  -- direct-solve adjoint gradient and Sherman-Morrison central
             differences for dL/dA_ij and dL/db.
+ilu      -- ILU(0) factors, their triangular solves and dependency levels,
+            and GMRES(m) with ILU(0) on the left and the polynomial on the
+            right (Section VI, second example).
 
 Every function works in the floating-point type of its vector inputs
 (float64 unless a float32 vector is passed), with all small dense algebra
@@ -29,4 +32,4 @@ numbers printed in Section V (the Laplacian worked example).  Parity
 unpinned: Table I and the counts of Sections III-IV (their Matrix Market
 matrices and random vectors are not available).
 """
-from . import poly, gmres, adjoint  # noqa: F401
+from . import poly, gmres, adjoint, ilu  # noqa: F401

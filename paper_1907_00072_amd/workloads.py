@@ -24,6 +24,12 @@ Matrices
   spectrum.
 * The unscaled 5-point Laplacian (4, -1) on a 201 x 201 interior grid
   (Section V, n = 40401), eigenvalues in (0, 8).
+* Recirculating-flow convection-diffusion (Section VI's second example):
+  -eps*lap(u) + w.grad(u) = 0 on [-1, 1]^2 with w = (2y(1-x^2), -2x(1-y^2)),
+  u = 1 on the boundary x = 1 and 0 on the others; central differences on an
+  N x N interior grid (h = 2/(N+1)), scaled by h^2/eps, so the diagonal is 4
+  and the neighbours along axis a carry -1 +- w_a(x, y) h / (2 eps) at the
+  row's own grid point; the boundary values go to the right-hand side.
 
 Every CSR array is returned as numpy ``int32`` row_ptr / col_ind (columns
 sorted ascending inside each row) and ``float64`` values.
@@ -38,7 +44,7 @@ import numpy as np
 __all__ = [
     "CSR", "Problem", "convection_diffusion", "stencil27_random", "bidiag1",
     "bidiag2", "laplacian5", "uniform", "normal", "config", "CONFIG_NAMES",
-    "random_csr",
+    "random_csr", "recirculating_flow", "ILU_WORKLOAD",
 ]
 
 
@@ -165,6 +171,41 @@ def convection_diffusion(N: int, dim: int, peclet: float, wind) -> CSR:
     return _stencil_csr((N,) * dim, offsets, coeffs)
 
 
+def recirculating_flow(N: int, eps: float = 1.0 / 200.0):
+    """The recirculating-wind problem on an N x N interior grid: (A, b).
+
+    Rows in lexicographic order, x fastest; column order per row -y, -x, 0,
+    +x, +y.  b holds the boundary data u = 1 on x = 1 (zero source).
+    """
+    N = int(N)
+    h = 2.0 / (N + 1)
+    t = -1.0 + (np.arange(N) + 1) * h
+    X, Y = np.meshgrid(t, t, indexing="xy")  # X[j, i] = x_i, Y[j, i] = y_j
+    px = (2.0 * Y * (1.0 - X * X) * h / (2.0 * eps)).ravel()
+    py = (-2.0 * X * (1.0 - Y * Y) * h / (2.0 * eps)).ravel()
+    n = N * N
+    ii = np.tile(np.arange(N), N)
+    jj = np.repeat(np.arange(N), N)
+    idx = np.arange(n, dtype=np.int64)
+    # (row validity, column, value) per stencil slot, in ascending column order
+    slots = [
+        (jj > 0, idx - N, -1.0 - py),
+        (ii > 0, idx - 1, -1.0 - px),
+        (np.ones(n, bool), idx, np.full(n, 4.0)),
+        (ii < N - 1, idx + 1, -1.0 + px),
+        (jj < N - 1, idx + N, -1.0 + py),
+    ]
+    valid = np.stack([s[0] for s in slots], axis=1)
+    cols = np.stack([s[1] for s in slots], axis=1)
+    vals = np.stack([s[2] for s in slots], axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(valid.sum(axis=1), out=row_ptr[1:])
+    A = CSR(n, row_ptr.astype(np.int32), cols[valid].astype(np.int32),
+            np.ascontiguousarray(vals[valid], dtype=np.float64))
+    b = np.where(ii == N - 1, 1.0 - px, 0.0)
+    return A, b
+
+
 def laplacian5(N: int = 201) -> CSR:
     """Unscaled 5-point Laplacian (diagonal 4, neighbours -1) on N x N."""
     offsets = [(0, -1), (-1, 0), (0, 0), (1, 0), (0, 1)]
@@ -250,6 +291,13 @@ CONFIG_NAMES = {
     4: "cd2d_512_pe20_adjoint",
     5: "cd3d_256_pe100",
 }
+
+
+# ILU(0) + polynomial composition (Section VI, second example): the paper's
+# eps = 1/200 and GMRES(50) at tol 1e-8, with its degree-12 polynomial (d = 13
+# roots), on an N x N grid (the paper's mesh has 1025^2 vertices).
+ILU_WORKLOAD = {"name": "recirc2d_257_eps200_ilu0", "N": 257, "eps": 1.0 / 200.0, "m": 50,
+                "d": 13, "tol": 1e-8, "v0_seed": 106}
 
 
 def _rhs_from_solution(A: CSR, x: np.ndarray) -> np.ndarray:
