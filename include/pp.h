@@ -118,6 +118,12 @@ typedef struct pp_csr {
  * and no pointer into A: pass the same A it was built from to pp_apply. */
 typedef struct pp_poly pp_poly;
 
+/* Opaque ILU(0) factorisation M = L U of a matrix (pp_ilu0_factor): the factors
+ * and their level schedules in device memory on the device that was current when
+ * it was made.  Library-owned; free with pp_ilu0_free.  It keeps no pointer into
+ * the matrix it was made from. */
+typedef struct pp_ilu pp_ilu;
+
 /* Optional solver controls.  Zero-initialise and set what you need; zero
  * fields take the defaults shown. */
 typedef struct pp_opts {
@@ -140,6 +146,12 @@ typedef struct pp_opts {
                              stops on ||D^-1 (b - A x)|| / ||D^-1 b|| < tol; D = diag(A)
                              (zero or missing diagonal -> PP_ERR_SINGULAR).  The scaled
                              copy of A's values is made once per call. */
+  const pp_ilu *left_ilu; /* non-NULL: compose with this ILU(0) factorisation M of A
+                             (pp_ilu0_factor of the same matrix) on the left, Section VI's
+                             second example: GMRES runs on M^-1 A p(M^-1 A) y = M^-1 b,
+                             x = p(M^-1 A) y, the polynomial is built for M^-1 A, and the
+                             solve stops on ||M^-1 (b - A x)|| / ||M^-1 b|| < tol.  FP64
+                             only; not together with left_jacobi or F32_IR (PP_ERR_ARG). */
 } pp_opts;
 
 /* Solve statistics (all counts follow Section III: a dot is one block inner
@@ -179,7 +191,7 @@ typedef struct pp_stats {
   double bytes_orth;
   int64_t launches_chain;  /* chain launches inside t_chain */
   double relres_original;  /* ||b - A x|| / ||b|| of the unpreconditioned system (equals
-                              relres_true unless left_jacobi is set) */
+                              relres_true unless left_jacobi or left_ilu is set) */
   int32_t layout_used;     /* PP_LAYOUT_CSR or PP_LAYOUT_SELL: what the products ran on */
   int64_t nnz_stored;      /* values one product streams: nnz (CSR) or the sliced copy's
                               stored values, padding included */
@@ -290,6 +302,41 @@ int pp_csr_transpose(const pp_csr *A, int32_t *rp_t, int32_t *ci_t, void *vals_t
  * (only the pattern is read).  Returns PP_OK, PP_ERR_ARG, PP_ERR_HIP. */
 int pp_csr_grad(const pp_csr *A, const double *lam, const double *x, double *g_vals,
                 void *stream);
+
+/* ---- ILU(0), the second preconditioner of Section VI's second example ----
+ * ILU(0) (the incomplete LU factorisation with no fill, Saad, "Iterative
+ * Methods for Sparse Linear Systems", Section 10.3): L unit lower and U upper
+ * triangular on A's pattern with (L U)_ij = a_ij for every stored (i, j).  The
+ * rows keep A's order.  The factorisation and both triangular sweeps run level
+ * by level on the device (the rows of a level wait only for earlier levels);
+ * runs of narrow levels go to a single workgroup, wider levels to a launch
+ * each, so the cost of a sweep grows with its number of levels (2N-1 for an
+ * N x N grid in natural order, 3N-2 for N^3). */
+
+/* Factor A (PP_F64; every row's columns strictly increasing, in [0, n), with a
+ * stored diagonal).  out receives a new pp_ilu.  Synchronises the stream.
+ * Returns PP_OK; PP_ERR_ARG for a bad pattern, a non-FP64 A or null pointers;
+ * PP_ERR_SINGULAR for a zero pivot or a non-finite factor entry; PP_ERR_HIP;
+ * PP_ERR_NOMEM.  Not serialised with the other calls: it uses no shared
+ * workspace. */
+int pp_ilu0_factor(const pp_csr *A, void *stream, pp_ilu **out);
+
+/* z = M^-1 r = U^-1 (L^-1 r): device FP64 vectors of n entries; z may equal r
+ * (in place).  Synchronises the stream.  Calls with one pp_ilu may overlap (the
+ * factor is read-only).  Returns PP_OK, PP_ERR_ARG, PP_ERR_HIP. */
+int pp_ilu0_apply(const pp_ilu *M, const double *r, double *z, void *stream);
+
+/* Copy the factors into lu (device FP64[nnz], A's CSR order): the strictly lower
+ * entries hold L (its unit diagonal implied), the others U.  Synchronises. */
+int pp_ilu0_values(const pp_ilu *M, double *lu, void *stream);
+
+/* Levels of the forward and backward sweeps, and the launches one pp_ilu0_apply
+ * makes (any pointer may be NULL).  Host only. */
+int pp_ilu0_levels(const pp_ilu *M, int32_t *nlev_forward, int32_t *nlev_backward,
+                   int32_t *launches);
+
+/* Free a factorisation (NULL is ignored); waits for the device first. */
+void pp_ilu0_free(pp_ilu *M);
 
 /* Free the library's device and pinned-host arena on every device. */
 void pp_release_workspace(void);

@@ -29,7 +29,8 @@ LAYOUTS = {"auto": PP_LAYOUT_AUTO, "csr": PP_LAYOUT_CSR, "sell": PP_LAYOUT_SELL}
 EXPORTS = ("pp_build_poly", "pp_apply", "pp_gmres_solve", "pp_poly_roots", "pp_poly_from_roots",
            "pp_poly_free", "pp_roots_from_hessenberg", "pp_csr_transpose", "pp_csr_grad",
            "pp_release_workspace", "pp_status_string", "pp_version", "pp_build_poly_power",
-           "pp_poly_coeffs")
+           "pp_poly_coeffs", "pp_ilu0_factor", "pp_ilu0_apply", "pp_ilu0_values",
+           "pp_ilu0_levels", "pp_ilu0_free")
 
 
 class pp_csr(ctypes.Structure):
@@ -44,7 +45,7 @@ class pp_opts(ctypes.Structure):
                 ("v0", ctypes.c_void_p), ("poly", ctypes.c_void_p), ("vals_f32", ctypes.c_void_p),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("op_form", ctypes.c_int32),
-                ("left_jacobi", ctypes.c_int32)]
+                ("left_jacobi", ctypes.c_int32), ("left_ilu", ctypes.c_void_p)]
 
 
 class pp_stats(ctypes.Structure):
@@ -94,10 +95,18 @@ def lib():
     L.pp_status_string.restype = ctypes.c_char_p
     L.pp_version.argtypes = []
     L.pp_version.restype = ctypes.c_char_p
+    I32 = ctypes.c_int32
+    L.pp_ilu0_factor.argtypes = [CSRP, VP, P(VP)]
+    L.pp_ilu0_apply.argtypes = [VP, VP, VP, VP]
+    L.pp_ilu0_values.argtypes = [VP, VP, VP]
+    L.pp_ilu0_levels.argtypes = [VP, P(I32), P(I32), P(I32)]
+    L.pp_ilu0_free.argtypes = [VP]
+    L.pp_ilu0_free.restype = None
     for name in ("pp_build_poly", "pp_build_poly_power", "pp_poly_coeffs", "pp_apply",
                  "pp_gmres_solve", "pp_poly_roots",
                  "pp_poly_from_roots", "pp_roots_from_hessenberg", "pp_csr_transpose",
-                 "pp_csr_grad"):
+                 "pp_csr_grad", "pp_ilu0_factor", "pp_ilu0_apply", "pp_ilu0_values",
+                 "pp_ilu0_levels"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -255,6 +264,60 @@ class Poly:
             self._h = None
 
 
+class ILU0:
+    """Owner of a pp_ilu handle: the ILU(0) factorisation of one matrix."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, nnz: int, device):
+        self._h = handle
+        self.n = n
+        self.nnz = nnz
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def levels(self):
+        """(forward levels, backward levels, launches per apply)."""
+        f, b, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().pp_ilu0_levels(self._h, ctypes.byref(f), ctypes.byref(b), ctypes.byref(k)),
+               "pp_ilu0_levels")
+        return f.value, b.value, k.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.pp_ilu0_free(h)
+            self._h = None
+
+
+def pp_ilu0_factor(A: CSRMatrix, stream=None) -> ILU0:
+    """ILU(0) of an FP64 matrix with sorted columns and a stored diagonal in every row."""
+    h = ctypes.c_void_p()
+    _check(lib().pp_ilu0_factor(ctypes.byref(A.c()), _stream(stream), ctypes.byref(h)),
+           "pp_ilu0_factor")
+    return ILU0(h, A.n, A.nnz, A.vals.device)
+
+
+def pp_ilu0_apply(M: ILU0, r, z=None, stream=None):
+    """z = M^-1 r (z may be r)."""
+    torch = _torch()
+    _dev_vec(r, torch.float64, M.n, "r")
+    if z is None:
+        z = torch.empty_like(r)
+    _dev_vec(z, torch.float64, M.n, "z")
+    _check(lib().pp_ilu0_apply(M.handle, _ptr(r), _ptr(z), _stream(stream)), "pp_ilu0_apply")
+    return z
+
+
+def pp_ilu0_values(M: ILU0, stream=None):
+    """The factors in the matrix's CSR order (L strictly below the diagonal, U on and above)."""
+    torch = _torch()
+    lu = torch.empty(M.nnz, dtype=torch.float64, device=M.device)
+    _check(lib().pp_ilu0_values(M.handle, _ptr(lu), _stream(stream)), "pp_ilu0_values")
+    return lu
+
+
 def pp_build_poly(A: CSRMatrix, v0, d: int, stream=None) -> Poly:
     torch = _torch()
     _dev_vec(v0, torch.float64, A.n, "v0")
@@ -325,10 +388,12 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
                    v0=None, poly: Optional[Poly] = None, precision: str = "f64",
                    max_iters: int = 0, inner_tol: float = 0.0, max_outer: int = 0,
                    vals_f32=None, history: int = 0, timing: bool = False, op_form: str = "pi",
-                   left_jacobi: bool = False, stream=None):
+                   left_jacobi: bool = False, left_ilu: Optional[ILU0] = None, stream=None):
     """Solve A x = b; returns (x, Stats).  ``x`` (if given) is the start guess and is overwritten.
 
     ``op_form``: "pi" applies A p(A) v as v - pi(A) v (default), "p" as A (p(A) v).
+    ``left_ilu``: an ILU(0) of A (pp_ilu0_factor) applied on the left, the
+    polynomial built for M^-1 A on the right.
     """
     torch = _torch()
     _dev_vec(b, torch.float64, A.n, "b")
@@ -356,6 +421,8 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
     o.timing = 1 if timing else 0
     o.op_form = {"pi": PP_OP_RESIDUAL_POLY, "p": PP_OP_PRODUCT}[op_form]
     o.left_jacobi = 1 if left_jacobi else 0
+    if left_ilu is not None:
+        o.left_ilu = left_ilu.handle.value
     st = pp_stats()
     rc = lib().pp_gmres_solve(ctypes.byref(A.c()), _ptr(b), _ptr(x), int(m), int(d), float(tol),
                               ctypes.byref(o), _stream(stream), ctypes.byref(st))

@@ -1,0 +1,478 @@
+// ILU(0) kernels for gfx950: pattern check, level schedules by frontier
+// expansion, the level-scheduled factorisation and triangular sweeps, and the
+// elementwise pieces of the composed operator M^-1 A (a chain step with the
+// product given, the residual with its norm partials).
+//
+// The sweeps are bound by the chain of dependent levels, not by bandwidth: each
+// level is one round of dependent loads (row, its entries, the solved values it
+// waits for).  Narrow levels therefore run back to back inside one workgroup
+// (a barrier between levels, no launch between them); a level wider than
+// kRunRows gets its own launch with one thread per row.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "ilu.h"
+
+namespace ppk {
+namespace {
+
+constexpr int kB = 256;
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
+
+// ------------------------------------------------------------- pattern check
+__global__ __launch_bounds__(kB) void k_ilu_check(int n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci,
+                                                  int32_t *__restrict__ dpos,
+                                                  int32_t *__restrict__ indeg_l,
+                                                  int32_t *__restrict__ indeg_u, int32_t *flag) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const int b = rp[i], e = rp[i + 1];
+  int d = -1, prev = -1, bad = 0;
+  for (int p = b; p < e; ++p) {
+    const int c = ci[p];
+    if (c <= prev || c >= n) bad |= 1;  // c <= prev also catches c < 0
+    if (c == i) d = p;
+    prev = c;
+  }
+  if (d < 0) bad |= 2;
+  dpos[i] = d;
+  indeg_l[i] = d < 0 ? 0 : d - b;
+  indeg_u[i] = d < 0 ? 0 : e - 1 - d;
+  if (bad) atomicOr(flag, bad);
+}
+
+__global__ __launch_bounds__(kB) void k_scatter_pattern(int n, const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci,
+                                                        const int32_t *__restrict__ rp_t,
+                                                        int32_t *cursor,
+                                                        int32_t *__restrict__ rows_t) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    const int j = ci[p];
+    rows_t[rp_t[j] + atomicAdd(&cursor[j], 1)] = i;
+  }
+}
+
+// ------------------------------------------------------------- levels
+__global__ __launch_bounds__(kB) void k_level_seed(int n, const int32_t *__restrict__ indeg,
+                                                   int32_t *__restrict__ perm, int32_t *lsz) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i < n && indeg[i] == 0) perm[atomicAdd(&lsz[0], 1)] = i;
+}
+
+__global__ __launch_bounds__(kB) void k_level_pass(int level, const int32_t *__restrict__ rp_t,
+                                                   const int32_t *__restrict__ rows_t, int upper,
+                                                   int32_t *indeg, int32_t *perm, int32_t *lbeg,
+                                                   int32_t *lsz) {
+  const int beg = lbeg[level], cnt = lsz[level];
+  const int next = beg + cnt;
+  if (blockIdx.x == 0 && threadIdx.x == 0) lbeg[level + 1] = next;
+  for (int t = blockIdx.x * kB + threadIdx.x; t < cnt; t += gridDim.x * kB) {
+    const int k = perm[beg + t];
+    for (int p = rp_t[k]; p < rp_t[k + 1]; ++p) {
+      const int i = rows_t[p];
+      if (upper ? (i < k) : (i > k)) {
+        if (atomicSub(&indeg[i], 1) == 1) perm[next + atomicAdd(&lsz[level + 1], 1)] = i;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- factorisation
+// Row i of ILU(0), IKJ order: for each stored l_ik (k ascending) divide by the
+// pivot u_kk, then subtract l_ik * u_kj from the stored a_ij with j > k (a merge
+// of the two sorted rows).  Rows k < i it reads are final (earlier levels).
+__device__ __forceinline__ void ilu0_row(int i, const int32_t *__restrict__ rp,
+                                         const int32_t *__restrict__ ci,
+                                         const int32_t *__restrict__ dpos, double *lu) {
+  const int b = rp[i], d = dpos[i], e = rp[i + 1];
+  for (int p = b; p < d; ++p) {
+    const int k = ci[p];
+    const double lik = lu[p] / lu[dpos[k]];
+    lu[p] = lik;
+    int q = dpos[k] + 1;
+    const int qe = rp[k + 1];
+    int r = p + 1;
+    while (q < qe && r < e) {
+      const int cq = ci[q], cr = ci[r];
+      if (cq == cr) {
+        lu[r] -= lik * lu[q];
+        ++q;
+        ++r;
+      } else if (cq < cr) {
+        ++q;
+      } else {
+        ++r;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_factor_level(const int32_t *__restrict__ row, int q0,
+                                                     int cnt, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci,
+                                                     const int32_t *__restrict__ dpos,
+                                                     double *lu) {
+  const int t = blockIdx.x * kB + threadIdx.x;
+  if (t < cnt) ilu0_row(row[q0 + t], rp, ci, dpos, lu);
+}
+
+__global__ __launch_bounds__(kRunThreads) void k_factor_run(const int32_t *__restrict__ row,
+                                                            const int32_t *__restrict__ lbeg,
+                                                            int l0, int l1,
+                                                            const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const int32_t *__restrict__ dpos,
+                                                            double *lu) {
+  for (int l = l0; l < l1; ++l) {
+    const int q1 = lbeg[l + 1];
+    for (int q = lbeg[l] + (int)threadIdx.x; q < q1; q += kRunThreads)
+      ilu0_row(row[q], rp, ci, dpos, lu);
+    __syncthreads();  // this level's rows are final before the next level reads them
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_ilu_pivots(int n, int64_t nnz,
+                                                   const int32_t *__restrict__ dpos,
+                                                   const double *__restrict__ lu, int32_t *flag) {
+  int bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * kB;
+  for (int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x; p < nnz; p += stride)
+    if (!isfinite(lu[p])) bad |= 2;
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += stride)
+    if (lu[dpos[i]] == 0.0) bad |= 1;
+  if (bad) atomicOr(flag, bad);
+}
+
+// ------------------------------------------------------------- level-ordered factors
+__global__ __launch_bounds__(kB) void k_sweep_counts(int n, const int32_t *__restrict__ row,
+                                                     const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ dpos, int upper,
+                                                     int32_t *__restrict__ cnt) {
+  const int q = blockIdx.x * kB + threadIdx.x;
+  if (q >= n) return;
+  const int i = row[q];
+  cnt[q] = upper ? rp[i + 1] - dpos[i] - 1 : dpos[i] - rp[i];
+}
+
+__global__ __launch_bounds__(kB) void k_sweep_fill(int n, const int32_t *__restrict__ row,
+                                                   const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const int32_t *__restrict__ dpos,
+                                                   const double *__restrict__ lu, int upper,
+                                                   const int32_t *__restrict__ ptr,
+                                                   int32_t *__restrict__ col,
+                                                   double *__restrict__ val,
+                                                   double *__restrict__ diag) {
+  const int q = blockIdx.x * kB + threadIdx.x;
+  if (q >= n) return;
+  const int i = row[q];
+  const int lo = upper ? dpos[i] + 1 : rp[i];
+  const int hi = upper ? rp[i + 1] : dpos[i];
+  int e = ptr[q];
+  for (int p = lo; p < hi; ++p, ++e) {
+    col[e] = ci[p];
+    val[e] = lu[p];
+  }
+  if (upper) diag[q] = lu[dpos[i]];
+}
+
+// ------------------------------------------------------------- sweeps
+// r and z (z and x) may be the same array: a row reads its own right-hand side
+// before writing its solution, and the solutions it reads belong to earlier levels.
+__device__ __forceinline__ void forward_row(int q, const int32_t *__restrict__ row,
+                                            const int32_t *__restrict__ ptr,
+                                            const int32_t *__restrict__ col,
+                                            const double *__restrict__ val, const double *r,
+                                            double *z) {
+  const int i = row[q];
+  double acc = r[i];
+  const int e1 = ptr[q + 1];
+  for (int e = ptr[q]; e < e1; ++e) acc -= val[e] * z[col[e]];
+  z[i] = acc;
+}
+
+__device__ __forceinline__ void backward_row(int q, const int32_t *__restrict__ row,
+                                             const int32_t *__restrict__ ptr,
+                                             const int32_t *__restrict__ col,
+                                             const double *__restrict__ val,
+                                             const double *__restrict__ diag, const double *z,
+                                             double *x) {
+  const int i = row[q];
+  double acc = z[i];
+  const int e1 = ptr[q + 1];
+  for (int e = ptr[q]; e < e1; ++e) acc -= val[e] * x[col[e]];
+  x[i] = acc / diag[q];
+}
+
+__global__ __launch_bounds__(kB) void k_forward_level(int q0, int cnt,
+                                                      const int32_t *__restrict__ row,
+                                                      const int32_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const double *__restrict__ val,
+                                                      const double *r, double *z) {
+  const int t = blockIdx.x * kB + threadIdx.x;
+  if (t < cnt) forward_row(q0 + t, row, ptr, col, val, r, z);
+}
+
+__global__ __launch_bounds__(kRunThreads) void k_forward_run(
+    int l0, int l1, const int32_t *__restrict__ lbeg, const int32_t *__restrict__ row,
+    const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *r, double *z) {
+  for (int l = l0; l < l1; ++l) {
+    const int q1 = lbeg[l + 1];
+    for (int q = lbeg[l] + (int)threadIdx.x; q < q1; q += kRunThreads)
+      forward_row(q, row, ptr, col, val, r, z);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_backward_level(int q0, int cnt,
+                                                       const int32_t *__restrict__ row,
+                                                       const int32_t *__restrict__ ptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val,
+                                                       const double *__restrict__ diag,
+                                                       const double *z, double *x) {
+  const int t = blockIdx.x * kB + threadIdx.x;
+  if (t < cnt) backward_row(q0 + t, row, ptr, col, val, diag, z, x);
+}
+
+__global__ __launch_bounds__(kRunThreads) void k_backward_run(
+    int l0, int l1, const int32_t *__restrict__ lbeg, const int32_t *__restrict__ row,
+    const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ diag, const double *z,
+    double *x) {
+  for (int l = l0; l < l1; ++l) {
+    const int q1 = lbeg[l + 1];
+    for (int q = lbeg[l] + (int)threadIdx.x; q < q1; q += kRunThreads)
+      backward_row(q, row, ptr, col, val, diag, z, x);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- composed operator
+// The chain step kinds of ChainArgs with (A g)(i) replaced by the given prod(i).
+template <int KIND, bool FOLD, bool LAST>
+__global__ __launch_bounds__(kB) void k_chain_given(int n, const double *__restrict__ prod,
+                                                    ChainArgs<double> a) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  constexpr bool kReadY = (KIND == 0) || (KIND == 1) || (KIND == 2 && (FOLD || LAST)) ||
+                          (KIND == 3 && LAST);
+  constexpr bool kReadSelf = (KIND == 2) || (KIND == 4);
+  const double gs = a.gscale ? *a.gscale : 1.0;
+  const double own = a.g[i];
+  const double yv = (kReadY && a.y_in) ? a.y_in[i] : 0.0;
+  const double sf = kReadSelf ? a.self[i] : 0.0;
+  const double acc = prod[i];
+  const double c1 = a.c1, c2 = a.c2, cf = a.cf;
+  if constexpr (KIND == 0) {
+    const double p = gs * own;
+    double y = yv + c1 * p;
+    const double pn = p - c1 * (gs * acc);
+    if constexpr (FOLD) {
+      y += cf * pn;
+    } else {
+      a.out[i] = pn;
+    }
+    a.y_out[i] = y;
+  } else if constexpr (KIND == 1) {
+    const double tt = gs * acc;
+    a.y_out[i] = yv + c1 * (gs * own) - c2 * tt;
+    if constexpr (!LAST) a.out[i] = tt;
+  } else if constexpr (KIND == 2) {
+    const double ss = a.sscale ? *a.sscale : 1.0;
+    const double pn = ss * sf - c1 * (gs * own) + c2 * (gs * acc);
+    if constexpr (FOLD) {
+      a.y_out[i] = yv + cf * pn;
+    } else if constexpr (LAST) {
+      const double ys = a.yscale ? *a.yscale : 1.0;
+      a.out[i] = ys * yv - pn;
+    } else {
+      a.out[i] = pn;
+    }
+  } else if constexpr (KIND == 4) {
+    const double ss = a.sscale ? *a.sscale : 1.0;
+    a.out[i] = c2 * (gs * acc) + c1 * (ss * sf);
+  } else {
+    const double pn = gs * own - c1 * (gs * acc);
+    if constexpr (LAST) {
+      const double ys = a.yscale ? *a.yscale : 1.0;
+      a.out[i] = ys * yv - pn;
+    } else {
+      a.out[i] = pn;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_sub_norm(int n, const double *__restrict__ b,
+                                                 const double *__restrict__ y,
+                                                 double *__restrict__ out,
+                                                 double *__restrict__ partial) {
+  __shared__ double red[kB / 64];
+  const int i = blockIdx.x * kB + threadIdx.x;
+  double sq = 0.0;
+  if (i < n) {
+    const double r = b[i] - y[i];
+    out[i] = r;
+    sq = r * r;
+  }
+  for (int off = 32; off > 0; off >>= 1) sq += __shfl_down(sq, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kB / 64; ++w) s += red[w];
+    partial[blockIdx.x] = s;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- wrappers
+hipError_t launch_ilu_check(int n, const int32_t *rp, const int32_t *ci, int32_t *dpos,
+                            int32_t *indeg_l, int32_t *indeg_u, int32_t *flag,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL(k_ilu_check, dim3(blocks(n)), dim3(kB), 0, stream, n, rp, ci, dpos, indeg_l,
+                     indeg_u, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_pattern(int n, const int32_t *rp, const int32_t *ci,
+                                  const int32_t *rp_t, int32_t *cursor, int32_t *rows_t,
+                                  hipStream_t stream) {
+  hipLaunchKernelGGL(k_scatter_pattern, dim3(blocks(n)), dim3(kB), 0, stream, n, rp, ci, rp_t,
+                     cursor, rows_t);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_seed(int n, const int32_t *indeg, int32_t *perm, int32_t *lsz,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_level_seed, dim3(blocks(n)), dim3(kB), 0, stream, n, indeg, perm, lsz);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_pass(int level, const int32_t *rp_t, const int32_t *rows_t, bool upper,
+                             int32_t *indeg, int32_t *perm, int32_t *lbeg, int32_t *lsz,
+                             hipStream_t stream) {
+  // a fixed grid that strides over the frontier, whose size only the device knows
+  hipLaunchKernelGGL(k_level_pass, dim3(512), dim3(kB), 0, stream, level, rp_t, rows_t,
+                     upper ? 1 : 0, indeg, perm, lbeg, lsz);
+  return hipGetLastError();
+}
+
+hipError_t launch_ilu_factor(const Sweep &L, const int32_t *rp, const int32_t *ci,
+                             const int32_t *dpos, double *lu, hipStream_t stream) {
+  for (const LevelSpan &sp : L.spans) {
+    if (sp.run) {
+      hipLaunchKernelGGL(k_factor_run, dim3(1), dim3(kRunThreads), 0, stream, L.row, L.lbeg,
+                         sp.l0, sp.l1, rp, ci, dpos, lu);
+    } else {
+      const int q0 = L.lbeg_host[sp.l0], cnt = L.lbeg_host[sp.l0 + 1] - q0;
+      hipLaunchKernelGGL(k_factor_level, dim3(blocks(cnt)), dim3(kB), 0, stream, L.row, q0, cnt,
+                         rp, ci, dpos, lu);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ilu_pivots(int n, int64_t nnz, const int32_t *dpos, const double *lu,
+                             int32_t *flag, hipStream_t stream) {
+  const unsigned g = (unsigned)std::min<int64_t>(blocks(std::max<int64_t>(n, nnz)), 4096);
+  hipLaunchKernelGGL(k_ilu_pivots, dim3(g), dim3(kB), 0, stream, n, nnz, dpos, lu, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_counts(int n, const int32_t *row, const int32_t *rp,
+                               const int32_t *dpos, bool upper, int32_t *cnt,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(k_sweep_counts, dim3(blocks(n)), dim3(kB), 0, stream, n, row, rp, dpos,
+                     upper ? 1 : 0, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_fill(int n, const int32_t *row, const int32_t *rp, const int32_t *ci,
+                             const int32_t *dpos, const double *lu, bool upper,
+                             const int32_t *ptr, int32_t *col, double *val, double *diag,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_sweep_fill, dim3(blocks(n)), dim3(kB), 0, stream, n, row, rp, ci, dpos,
+                     lu, upper ? 1 : 0, ptr, col, val, diag);
+  return hipGetLastError();
+}
+
+hipError_t launch_ilu_forward(int n, const Sweep &L, const double *r, double *z,
+                              hipStream_t stream) {
+  (void)n;
+  for (const LevelSpan &sp : L.spans) {
+    if (sp.run) {
+      hipLaunchKernelGGL(k_forward_run, dim3(1), dim3(kRunThreads), 0, stream, sp.l0, sp.l1,
+                         L.lbeg, L.row, L.ptr, L.col, L.val, r, z);
+    } else {
+      const int q0 = L.lbeg_host[sp.l0], cnt = L.lbeg_host[sp.l0 + 1] - q0;
+      hipLaunchKernelGGL(k_forward_level, dim3(blocks(cnt)), dim3(kB), 0, stream, q0, cnt, L.row,
+                         L.ptr, L.col, L.val, r, z);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ilu_backward(int n, const Sweep &U, const double *z, double *x,
+                               hipStream_t stream) {
+  (void)n;
+  for (const LevelSpan &sp : U.spans) {
+    if (sp.run) {
+      hipLaunchKernelGGL(k_backward_run, dim3(1), dim3(kRunThreads), 0, stream, sp.l0, sp.l1,
+                         U.lbeg, U.row, U.ptr, U.col, U.val, U.diag, z, x);
+    } else {
+      const int q0 = U.lbeg_host[sp.l0], cnt = U.lbeg_host[sp.l0 + 1] - q0;
+      hipLaunchKernelGGL(k_backward_level, dim3(blocks(cnt)), dim3(kB), 0, stream, q0, cnt,
+                         U.row, U.ptr, U.col, U.val, U.diag, z, x);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_chain_given(int n, int kind, bool fold, bool last, const double *prod,
+                              const ChainArgs<double> &a, hipStream_t stream) {
+  const dim3 grid(blocks(n)), block(kB);
+#define PP_GIVEN(K, F, L) \
+  hipLaunchKernelGGL((k_chain_given<K, F, L>), grid, block, 0, stream, n, prod, a)
+  switch (kind) {
+    case 0:
+      if (fold) PP_GIVEN(0, true, false); else PP_GIVEN(0, false, false);
+      break;
+    case 1:
+      if (last) PP_GIVEN(1, false, true); else PP_GIVEN(1, false, false);
+      break;
+    case 2:
+      if (fold) PP_GIVEN(2, true, false);
+      else if (last) PP_GIVEN(2, false, true);
+      else PP_GIVEN(2, false, false);
+      break;
+    case 3:
+      if (last) PP_GIVEN(3, false, true); else PP_GIVEN(3, false, false);
+      break;
+    case 4:
+      PP_GIVEN(4, false, false);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PP_GIVEN
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_norm(int n, const double *b, const double *y, double *out,
+                           double *partial, int *ntiles, hipStream_t stream) {
+  *ntiles = (int)blocks(n);
+  hipLaunchKernelGGL(k_sub_norm, dim3(*ntiles), dim3(kB), 0, stream, n, b, y, out, partial);
+  return hipGetLastError();
+}
+
+}  // namespace ppk

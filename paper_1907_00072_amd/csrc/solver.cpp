@@ -22,6 +22,7 @@
 
 #include "../../include/pp.h"
 #include "host_numerics.h"
+#include "ilu.h"
 #include "kernels.h"
 
 struct pp_poly {
@@ -252,13 +253,51 @@ struct PolyRef {
   }
 };
 
+// The operator of a solve: A itself, or M^-1 A with M an ILU(0) factorisation
+// applied on the left (Section VI, second example; FP64 only).  prod is the
+// composed operator's product buffer (n entries).
+template <typename T>
+struct Opr : SpMat<T> {
+  const pp_ilu *ilu = nullptr;
+  T *prod = nullptr;
+  Opr(const SpMat<T> &m) : SpMat<T>(m) {}  // NOLINT: a plain matrix is an operator
+};
+
+// out = Op (gscale * g).
+template <typename T>
+int op_product(const Opr<T> &A, const T *g, const double *gscale, T *out, hipStream_t s) {
+  PP_TRY_HIP(ppk::launch_spmv<T>(A, g, gscale, out, s));
+  if constexpr (sizeof(T) == sizeof(double)) {
+    if (A.ilu) PP_TRY_HIP(ppi::ilu_solve(*A.ilu, out, out, s));
+  }
+  return PP_OK;
+}
+
+// One chain step (ChainArgs kinds) with the operator's product: fused with the
+// sparse product for A, elementwise after the product for M^-1 A.
+template <typename T>
+int op_chain(const Opr<T> &A, int kind, bool fold, bool last, const ppk::ChainArgs<T> &a,
+             hipStream_t s) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    if (A.ilu) {
+      PP_TRY(op_product<T>(A, a.g, nullptr, A.prod, s));
+      PP_TRY_HIP(ppk::launch_chain_given(A.n, kind, fold, last, A.prod, a, s));
+      return PP_OK;
+    }
+  }
+  PP_TRY_HIP(ppk::launch_chain<T>(A, kind, fold, last, a, s));
+  return PP_OK;
+}
+
 // ------------------------------------------------------------------ chain
 // Algorithmic HBM bytes of one sparse-product launch: the matrix (values,
 // column indices, row pointers) and the gathered vector once, plus `vec_rw`
 // further vector reads/writes of n entries.
 template <typename T>
-double product_bytes(const SpMat<T> &A, int vec_rw) {
-  const double vecs = (double)sizeof(T) * A.n * (1 + vec_rw);
+double product_bytes(const Opr<T> &A, int vec_rw) {
+  double vecs = (double)sizeof(T) * A.n * (1 + vec_rw);
+  if (A.ilu)  // the two triangular sweeps, and the product written then read back
+    vecs += ppi::ilu_solve_bytes(*A.ilu) + 2.0 * sizeof(T) * A.n;
   if (A.sdesc)  // sliced copy: stored values (padding included), explicit columns,
                 // diagonal offsets past the descriptors, slice descriptors
     return (double)A.snnz * sizeof(T) + 4.0 * A.snnz_ell + 4.0 * A.soff_extra +
@@ -270,7 +309,7 @@ double product_bytes(const SpMat<T> &A, int vec_rw) {
 // (zero) or equal y_out.  Uses P0, P1, Tb as chain temporaries.  Adds the
 // launches and their algorithmic bytes to *bytes / *launches when given.
 template <typename T>
-int run_chain(const SpMat<T> &A, const std::vector<ppn::Step> &steps, const T *g,
+int run_chain(const Opr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
               const double *gscale, const T *y_in, T *y_out, T *P0, T *P1, T *Tb,
               hipStream_t s, Counters *cnt, double *bytes = nullptr,
               int64_t *launches = nullptr) {
@@ -296,7 +335,7 @@ int run_chain(const SpMat<T> &A, const std::vector<ppn::Step> &steps, const T *g
       }
       ppk::ChainArgs<T> a{cur, cs, nullptr, nullptr, fold ? nullptr : bufs[pb], yi, y_out,
                           st.c1, 0.0, cf};
-      PP_TRY_HIP(ppk::launch_chain<T>(A, 0, fold, false, a, s));
+      PP_TRY(op_chain<T>(A, 0, fold, false, a, s));
       if (cnt) cnt->spmvs++;
       account((yi ? 1 : 0) + 1 + (fold ? 0 : 1));
       yi = y_out;
@@ -307,14 +346,14 @@ int run_chain(const SpMat<T> &A, const std::vector<ppn::Step> &steps, const T *g
     } else {
       ppk::ChainArgs<T> a{cur, cs, nullptr, nullptr, last ? nullptr : Tb, yi, y_out,
                           st.c1, st.c2, 0.0};
-      PP_TRY_HIP(ppk::launch_chain<T>(A, 1, false, last, a, s));
+      PP_TRY(op_chain<T>(A, 1, false, last, a, s));
       if (cnt) cnt->spmvs++;
       account((yi ? 1 : 0) + 1 + (last ? 0 : 1));
       yi = y_out;
       if (last) break;
       ppk::ChainArgs<T> b{Tb, nullptr, cur, cs, fold ? nullptr : bufs[pb], yi, y_out,
                           st.c1, st.c2, cf};
-      PP_TRY_HIP(ppk::launch_chain<T>(A, 2, fold, false, b, s));
+      PP_TRY(op_chain<T>(A, 2, fold, false, b, s));
       if (cnt) cnt->spmvs++;
       account(1 + (fold ? 2 : 1));
       if (fold) break;
@@ -330,7 +369,7 @@ int run_chain(const SpMat<T> &A, const std::vector<ppn::Step> &steps, const T *g
 // z <- A z + c[k] v from the top coefficient down: deg fused product + axpy
 // launches (one axpy launch for a constant polynomial).
 template <typename T>
-int run_horner(const SpMat<T> &A, const std::vector<double> &c, const T *g, const double *gscale,
+int run_horner(const Opr<T> &A, const std::vector<double> &c, const T *g, const double *gscale,
                T *out, T *P0, T *P1, hipStream_t s, Counters *cnt, double *bytes = nullptr,
                int64_t *launches = nullptr) {
   const int deg = (int)c.size() - 1;
@@ -347,7 +386,7 @@ int run_horner(const SpMat<T> &A, const std::vector<double> &c, const T *g, cons
     T *dst = (k == 0) ? out : bufs[pb];
     ppk::ChainArgs<T> a{z, zs, g, gscale, dst, nullptr, nullptr, c[k],
                         k == deg - 1 ? c[deg] : 1.0, 0.0, nullptr};
-    PP_TRY_HIP(ppk::launch_chain<T>(A, 4, false, false, a, s));
+    PP_TRY(op_chain<T>(A, 4, false, false, a, s));
     if (bytes) *bytes += product_bytes(A, 2);
     if (launches) ++*launches;
     if (cnt) cnt->spmvs++;
@@ -363,7 +402,7 @@ int run_horner(const SpMat<T> &A, const std::vector<double> &c, const T *g, cons
 // conjugate pair (t = A p, then p' = p - c1 t + c2 A t), the last launch writing
 // v - p' instead of p'.  d products, no accumulator vector.
 template <typename T>
-int run_op_chain(const SpMat<T> &A, const std::vector<ppn::Step> &steps, const T *g,
+int run_op_chain(const Opr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
                  const double *gscale, T *w_out, T *P0, T *P1, T *Tb, hipStream_t s,
                  Counters *cnt, double *bytes = nullptr, int64_t *launches = nullptr) {
   auto account = [&](int vec_rw) {
@@ -383,14 +422,14 @@ int run_op_chain(const SpMat<T> &A, const std::vector<ppn::Step> &steps, const T
     if (st.kind == 0) {
       ppk::ChainArgs<T> a{cur, cs, nullptr, nullptr, dst, last ? g : nullptr, nullptr,
                           st.c1, 0.0, 0.0, last ? gscale : nullptr};
-      PP_TRY_HIP(ppk::launch_chain<T>(A, 3, false, last, a, s));
+      PP_TRY(op_chain<T>(A, 3, false, last, a, s));
       account(1 + (last ? 1 : 0));
     } else {
-      PP_TRY_HIP(ppk::launch_spmv<T>(A, cur, cs, Tb, s));
+      PP_TRY(op_product<T>(A, cur, cs, Tb, s));
       account(1);
       ppk::ChainArgs<T> b{Tb, nullptr, cur, cs, dst, last ? g : nullptr, nullptr,
                           st.c1, st.c2, 0.0, last ? gscale : nullptr};
-      PP_TRY_HIP(ppk::launch_chain<T>(A, 2, false, last, b, s));
+      PP_TRY(op_chain<T>(A, 2, false, last, b, s));
       account(2 + (last ? 1 : 0));
     }
     cur = dst;
@@ -438,7 +477,7 @@ int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s, int *G) {
 // hcol[0..j+1] receives column j of Hbar; *w0 an estimate of ||Op(V_j)||.
 // Returns PP_OK, or PP_WARN_NONFINITE when a coefficient is not finite.
 template <typename T>
-int arnoldi_step(const SpMat<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int j,
+int arnoldi_step(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int j,
                  hipStream_t s, Timers &tm, Counters &cnt, double *hcol, double *w0) {
   const T *vj = w.V + (int64_t)j * w.ldv;
   const double *sj = w.colscale + j;
@@ -457,10 +496,10 @@ int arnoldi_step(const SpMat<T> &A, const PolyRef &pr, int op_form, Work<T> &w, 
         PP_TRY(run_chain<T>(A, *pr.steps, vj, sj, nullptr, w.Z, w.P0, w.P1, w.Tb, s, &cnt,
                             &cnt.bytes_chain, &cnt.launches_chain));
       tm.mark(1, s);
-      PP_TRY_HIP(ppk::launch_spmv<T>(A, w.Z, nullptr, w.W, s));
+      PP_TRY(op_product<T>(A, w.Z, nullptr, w.W, s));
     } else {
       tm.mark(1, s);
-      PP_TRY_HIP(ppk::launch_spmv<T>(A, vj, sj, w.W, s));
+      PP_TRY(op_product<T>(A, vj, sj, w.W, s));
     }
     cnt.spmvs++;
     cnt.bytes_spmv += product_bytes(A, 1);
@@ -526,7 +565,7 @@ int start_from_vector(Work<T> &w, const double *src, hipStream_t s, double *beta
 
 // d Arnoldi steps on v0, harmonic Ritz values, Leja order, step table.
 template <typename T>
-int build_poly_impl(const SpMat<T> &A, const double *v0, int d, Work<T> &w, hipStream_t s,
+int build_poly_impl(const Opr<T> &A, const double *v0, int d, Work<T> &w, hipStream_t s,
                     Counters &cnt, Timers &tm, pp_poly *out) {
   double beta = 0.0;
   PP_TRY(start_from_vector<T>(w, v0, s, &beta));
@@ -566,13 +605,13 @@ int build_poly_impl(const SpMat<T> &A, const double *v0, int d, Work<T> &w, hipS
 // without a Cholesky failure is kept (Section IV); otherwise a failure at column
 // k keeps the solution of the leading (k-1) block, zeros above, and warns.
 template <typename T>
-int build_power_impl(const SpMat<T> &A, const double *v0, int deg, bool auto_deg, Work<T> &w,
+int build_power_impl(const Opr<T> &A, const double *v0, int deg, bool auto_deg, Work<T> &w,
                      double *gram, hipStream_t s, Counters &cnt, pp_poly *out, int *info_out) {
   const int L = deg + 2;
   PP_TRY_HIP(ppk::launch_copy_from_f64<T>(w.n, v0, w.V, s));
   for (int k = 1; k < L; ++k) {
-    PP_TRY_HIP(ppk::launch_spmv<T>(A, w.V + (int64_t)(k - 1) * w.ldv, nullptr,
-                                   w.V + (int64_t)k * w.ldv, s));
+    PP_TRY(op_product<T>(A, w.V + (int64_t)(k - 1) * w.ldv, nullptr, w.V + (int64_t)k * w.ldv,
+                         s));
     cnt.spmvs++;
   }
   for (int j = 1; j < L; ++j) {
@@ -664,7 +703,7 @@ struct Lsq {
 // One GMRES(m) cycle from V(:,0) (colscale[0] set) with start residual norm beta.
 // Returns steps taken in *k and the solution coefficients in y.
 template <typename T>
-int gmres_cycle(const SpMat<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int m,
+int gmres_cycle(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int m,
                 double beta, double tol_abs, double bscale, int max_steps, hipStream_t s,
                 Timers &tm, Counters &cnt, std::vector<double> &y, int *k, double *res,
                 bool *nonfinite) {
@@ -705,7 +744,7 @@ int gmres_cycle(const SpMat<T> &A, const PolyRef &pr, int op_form, Work<T> &w, i
 
 // x_out = x_in + p(A) V(:,0..k) (colscale o y)   [x_in may equal x_out, or be nullptr]
 template <typename T>
-int cycle_update(const SpMat<T> &A, const PolyRef &pr, Work<T> &w, int k,
+int cycle_update(const Opr<T> &A, const PolyRef &pr, Work<T> &w, int k,
                  const std::vector<double> &y, const T *x_in, T *x_out, hipStream_t s,
                  Counters &cnt) {
   if (k <= 0) return PP_OK;
@@ -948,6 +987,7 @@ struct SolveIn {
   double tol;
   pp_opts o;
   hipStream_t s;
+  const pp_ilu *ilu = nullptr;  // left ILU(0): the operator is M^-1 A and b is M^-1 b
 };
 
 // Products with A per application of the preconditioned operator A p(A).
@@ -980,10 +1020,15 @@ int norm_f64(Work<double> &w, const double *x, hipStream_t s, double *out) {
 }
 
 // r = b - A x into V(:,0), colscale[0] = 1/||r||; returns ||r||.
-int residual_f64(const SpMat<double> &A, Work<double> &w, const double *b, const double *x,
+int residual_f64(const Opr<double> &A, Work<double> &w, const double *b, const double *x,
                  hipStream_t s, double *beta) {
   int nt = 0;
-  PP_TRY_HIP(ppk::launch_residual<double>(A, b, x, w.V, w.partial, &nt, s));
+  if (A.ilu) {  // M^-1 b - M^-1 A x, with b = M^-1 b given
+    PP_TRY(op_product<double>(A, x, nullptr, A.prod, s));
+    PP_TRY_HIP(ppk::launch_sub_norm(A.n, b, A.prod, w.V, w.partial, &nt, s));
+  } else {
+    PP_TRY_HIP(ppk::launch_residual<double>(A, b, x, w.V, w.partial, &nt, s));
+  }
   PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, nt, w.misc, w.colscale, s));
   PP_TRY_HIP(hipMemcpyAsync(w.host, w.misc, sizeof(double), hipMemcpyDeviceToHost, s));
   PP_TRY_HIP(hipStreamSynchronize(s));
@@ -1004,12 +1049,16 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
   Carver meas(nullptr);
   w.carve(meas, n, L);
   double *xsave = meas.take<double>(n);
+  double *prod = in.ilu ? meas.take<double>(n) : nullptr;
   PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
   Carver c(ar->dev);
   w.carve(c, n, L);
   xsave = c.take<double>(n);
+  prod = in.ilu ? c.take<double>(n) : nullptr;
   w.host = ar->host;
-  const SpMat<double> A = with_sell(view<double>(in.A, in.A->vals), sc);
+  Opr<double> A(with_sell(view<double>(in.A, in.A->vals), sc));
+  A.ilu = in.ilu;
+  A.prod = prod;
   hipStream_t s = in.s;
   Counters cnt;
   cnt.history = in.o.history;
@@ -1299,6 +1348,20 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
   }
   std::lock_guard<std::mutex> lk(g_lock);
   Arena *ar = nullptr;
+  if (in.o.left_ilu) {
+    // Section VI, second example: ILU(0) on the left, the polynomial of M^-1 A on
+    // the right; the solve runs on (M^-1 A, M^-1 b)
+    const pp_ilu *M = in.o.left_ilu;
+    if (in.o.left_jacobi || in.o.precision != PP_PREC_F64 || in.o.vals_f32 || M->n != A->n ||
+        M->nnz != A->nnz)
+      return PP_ERR_ARG;
+    PP_TRY(current_arena(&ar));
+    PP_TRY(ensure_aux(ar, (size_t)A->n * sizeof(double) + 256));
+    double *bs = reinterpret_cast<double *>(ar->aux);
+    PP_TRY_HIP(ppi::ilu_solve(*M, b, bs, in.s));
+    in.b = bs;
+    in.ilu = M;
+  }
   if (in.o.left_jacobi) {
     // Section II composition: run the unchanged solver on (D^-1 A, D^-1 b).
     if (in.o.vals_f32) return PP_ERR_ARG;
@@ -1331,7 +1394,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
     st->status = rc;
     st->relres_original = st->relres_true;
   }
-  if (in.o.left_jacobi && rc >= 0 && st) {
+  if ((in.o.left_jacobi || in.o.left_ilu) && rc >= 0 && st) {
     // ||b - A x|| / ||b|| of the original system, in the (re-carved) main arena
     const int n = (int)A->n;
     Work<double> w;

@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle import gmres as og  # noqa: E402
+from oracle import ilu as oi  # noqa: E402
 from oracle import poly as op  # noqa: E402
 from paper_1907_00072_amd import workloads as W  # noqa: E402
 
@@ -58,8 +59,22 @@ def run(names):
     jobs.append(("stencil27_96_ir_d25", 3, 25))
     jobs.append(("stencil27_96_f64_d25", 3, -25))
     jobs.append(("cd3d_256_pe100_d40", 5, 40))
+    jobs.append(("recirc2d_257_eps200_ilu0_d13", "ilu", 13))
     for name, cfg, d in jobs:
         if names and name not in names:
+            continue
+        if cfg == "ilu":
+            # Section VI's second example: ILU(0) left, polynomial of M^-1 A right
+            wl = W.ILU_WORKLOAD
+            Ah, b = W.recirculating_flow(wl["N"], wl["eps"])
+            P = W.Problem(wl["name"], Ah, b, W.uniform(Ah.n, wl["v0_seed"]), m=wl["m"], d=d,
+                          tol=wl["tol"])
+            t0 = time.time()
+            x, st = oi.pp_gmres_left_ilu0(Ah.to_scipy(), b, P.m, P.tol, v0=P.v0, d=d,
+                                          max_iters=20000)
+            refs[name] = record(name, P, d, x, st, time.time() - t0,
+                                {"relres_original": st.relres_original})
+            json.dump(refs, open(OUT, "w"), indent=1)
             continue
         P = W.config(cfg)
         A = P.A.to_scipy()

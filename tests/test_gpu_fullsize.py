@@ -11,6 +11,9 @@
 * 512^2 adjoint (n = 262k): dL/dvals and dL/db against the oracle's direct
   adjoint on every stored entry and Sherman-Morrison central differences on the
   64 sampled entries.
+* 257^2 recirculating flow with ILU(0) on the left and d = 13 on the right
+  (Section VI's second example, n = 66k): every factor entry and M^-1 r against
+  the oracle, and the solve against the stored oracle solve.
 """
 import json
 import os
@@ -20,6 +23,7 @@ import numpy as np
 import pytest
 
 from oracle import adjoint as oadj
+from oracle import ilu as oilu
 from oracle import poly as opoly
 from paper_1907_00072_amd import workloads as W
 
@@ -176,3 +180,24 @@ def test_adjoint_512(B):
     ents = P.extra["fd_entries"]
     fd = oadj.fd_gradient_vals(M, P.b, xt, ents, h=P.extra["fd_h"], solver=S, x=xo)
     assert np.max(np.abs(gv[ents] - fd)) <= 1e-6 * np.max(np.abs(gv_ref))
+
+
+def test_recirc_257_ilu0_left_poly_right(B, refs):
+    wl = W.ILU_WORKLOAD
+    Ah, b = W.recirculating_flow(wl["N"], wl["eps"])
+    As = Ah.to_scipy()
+    A = B.CSRMatrix.from_host(Ah)
+    M = B.pp_ilu0_factor(A)
+    LU = oilu.ilu0(As)
+    lu = B.pp_ilu0_values(M).cpu().numpy()
+    assert np.max(np.abs(lu - LU.data)) <= 1e-12 * np.max(np.abs(LU.data))
+    assert M.levels()[:2] == (2 * wl["N"] - 1, 2 * wl["N"] - 1)
+    r = W.normal(Ah.n, 12)
+    z = B.pp_ilu0_apply(M, _up(r)).cpu().numpy()
+    zo = oilu.ilu0_solve(LU, r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    ref = refs["recirc2d_257_eps200_ilu0_d13"]
+    x, st = B.pp_gmres_solve(A, _up(b), m=wl["m"], d=wl["d"], tol=wl["tol"],
+                             v0=_up(W.uniform(Ah.n, wl["v0_seed"])), left_ilu=M)
+    _check_against_ref(ref, st, x, wl["tol"])
+    assert abs(st.relres_original - ref["relres_original"]) <= 1e-3 * ref["relres_original"]
