@@ -60,8 +60,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=256, help="grid points per axis (256 = headline)")
-    ap.add_argument("--legs", default="ir,plain,power,csr,jacobi,adjoint",
-                    help="comma list of extra legs: ir, plain, power, csr, jacobi, adjoint, none")
+    ap.add_argument("--legs", default="ir,plain,power,csr,jacobi,ilu,adjoint",
+                    help="comma list of extra legs: ir, plain, power, csr, jacobi, ilu, adjoint, "
+                         "none")
     ap.add_argument("--plain-max-iters", type=int, default=30000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--sweep", action="store_true",
@@ -228,6 +229,13 @@ def main():
                                        "relres_original": s6.relres_original}
         log(f"left jacobi: {tj:.3f}s iters {s6.iters} relres {s6.relres_original:.2e}")
 
+    if "ilu" in wanted:
+        legs["ilu0_left_recirc_257"] = ilu_leg(B, W, torch, dev)
+        li = legs["ilu0_left_recirc_257"]
+        log(f"ILU(0) + d={li['d']}: {li['time_s']:.3f}s iters {li['iters']}; ILU(0) alone "
+            f"{li['ilu_only']['iters']} iters relres {li['ilu_only']['relres']:.2e}; "
+            f"M^-1 r {li['apply_ms']:.3f} ms ({li['us_per_level']:.2f} us per level)")
+
     if "adjoint" in wanted:
         legs["adjoint_512"] = adjoint_leg(B, W, torch, dev)
         log(f"adjoint 512^2: {legs['adjoint_512']['time_s']:.3f}s")
@@ -334,6 +342,63 @@ def sweep(B, W, torch, dev, steps):
     return {"sweep": out, "steps": steps, "data": "synthetic"}
 
 
+def ilu_leg(B, W, torch, dev, ilu_only_cap=1000):
+    """Section VI's second example: ILU(0) on the left, the polynomial of M^-1 A on
+    the right (recirculating wind, eps = 1/200, 257^2, GMRES(50), d = 13, tol
+    1e-8).  Times the factorisation, one M^-1 r (two level-scheduled sweeps) and
+    the composed solve (one warm-up, one timed), and runs ILU(0) alone up to
+    `ilu_only_cap` iterations (it stalls on this problem, as the paper reports)."""
+    import warnings
+
+    wl = W.ILU_WORKLOAD
+    Ah, bh = W.recirculating_flow(wl["N"], wl["eps"])
+    A = B.CSRMatrix.from_host(Ah, device=dev)
+    b = torch.from_numpy(bh).to(dev)
+    v0 = torch.from_numpy(W.uniform(Ah.n, wl["v0_seed"])).to(dev)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    M = B.pp_ilu0_factor(A)
+    t_factor = time.perf_counter() - ts
+    nf, nb, launches = M.levels()
+    r = torch.from_numpy(W.normal(Ah.n, 1)).to(dev)
+    z = torch.empty_like(r)
+    B.pp_ilu0_apply(M, r, z)
+    reps = 50
+    ts = time.perf_counter()
+    for _ in range(reps):
+        B.pp_ilu0_apply(M, r, z)
+    t_apply = (time.perf_counter() - ts) / reps
+
+    def solve(**kw):
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            _, st = B.pp_gmres_solve(A, b, x, m=wl["m"], tol=wl["tol"], v0=v0, left_ilu=M, **kw)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, x, st
+    solve(d=wl["d"])
+    t_pp, x, st = solve(d=wl["d"])
+    t_alone, _, s0 = solve(d=0, max_iters=ilu_only_cap)
+    # algorithmic bytes of one M^-1 r: per sweep the level order and row pointers
+    # (8 n), the waited-for entries (12 each, nnz - n in all), right-hand side,
+    # solution written and gathered (24 n); the backward sweep's pivots (8 n)
+    sweep_bytes = 72.0 * Ah.n + 12.0 * (Ah.nnz - Ah.n)
+    ref = oracle_reference_named("recirc2d_257_eps200_ilu0_d13")
+    return {"workload": wl["name"], "n": Ah.n, "nnz": Ah.nnz, "m": wl["m"], "d": wl["d"],
+            "tol": wl["tol"], "time_s": t_pp, "iters": st.iters, "cycles": st.cycles,
+            "relres_preconditioned": st.relres_true, "relres_original": st.relres_original,
+            "err_vs_oracle": error_vs_oracle(ref, x.cpu().numpy()) if ref else None,
+            "oracle_iters": ref["iters"] if ref else None,
+            "factor_s": t_factor, "levels_forward": nf, "levels_backward": nb,
+            "launches_per_apply": launches, "apply_ms": t_apply * 1e3,
+            "us_per_level": t_apply * 1e6 / (nf + nb),
+            "apply_alg_GBps": sweep_bytes / t_apply / 1e9,
+            "ilu_only": {"time_s": t_alone, "iters": s0.iters, "relres": s0.relres_true,
+                         "converged": bool(s0.relres_true < wl["tol"]), "cap": ilu_only_cap}}
+
+
 def adjoint_leg(B, W, torch, dev):
     """Forward solve, adjoint solve on A^T and the gradient on the CSR pattern
     (2D convection-diffusion 512^2, Pe 20, L = 0.5 ||x - x_t||^2, forward and
@@ -373,11 +438,16 @@ def oracle_reference(grid):
     tests/golden/make_fullsize_refs.py; None for other grids."""
     if grid != 256:
         return None
+    return oracle_reference_named("cd3d_256_pe100_d40")
+
+
+def oracle_reference_named(name):
+    """A stored oracle solve (tests/golden/fullsize_refs.json), or None."""
     try:
         refs = json.load(open(os.path.join(ROOT, "tests", "golden", "fullsize_refs.json")))
     except OSError:
         return None
-    return refs.get("cd3d_256_pe100_d40")
+    return refs.get(name)
 
 
 def error_vs_oracle(ref, x):
