@@ -26,6 +26,7 @@ namespace ppk {
 
 constexpr int kRunThreads = 1024;  // threads of the one workgroup that steps through a run
 constexpr int kRunRows = 1024;     // widest level handled inside a run
+constexpr int kPipeSlots = 8;      // most waited-for entries per row of the pipelined run
 
 // A span of consecutive levels [l0, l1): a run (narrow levels, one workgroup) or
 // a single wide level.
@@ -37,7 +38,10 @@ struct LevelSpan {
 // Level schedule of one triangular sweep and its level-ordered copy of the factor.
 // Position q (0..n-1) is the q-th row of the sweep in level order: row[q]; the
 // off-diagonal entries the row waits for are ptr[q]..ptr[q+1] in col/val; diag[q]
-// is U's pivot of the row (backward sweep only).
+// is U's pivot of the row (backward sweep only).  When no row waits for more than
+// kPipeSlots entries the same entries are also kept slot-major (width slots per
+// position, slot s of position q at s * n + q, padding column -1 / value 0) for
+// the pipelined run kernel.
 struct Sweep {
   int nlev = 0;
   int32_t *row = nullptr;   // [n]
@@ -47,6 +51,9 @@ struct Sweep {
   double *val = nullptr;    // [entries]
   double *diag = nullptr;   // [n] (backward sweep)
   int64_t entries = 0;
+  int width = 0;            // most entries one row waits for
+  int32_t *ecol = nullptr;  // [width * n] slot-major copy (nullptr: width > kPipeSlots)
+  double *eval = nullptr;   // [width * n]
   std::vector<int32_t> lbeg_host;
   std::vector<LevelSpan> spans;
 };
@@ -87,10 +94,14 @@ hipError_t launch_ilu_factor(const Sweep &L, const int32_t *rp, const int32_t *c
 // *flag |= 1 for a zero pivot, |= 2 for a non-finite factor entry.
 hipError_t launch_ilu_pivots(int n, int64_t nnz, const int32_t *dpos, const double *lu,
                              int32_t *flag, hipStream_t stream);
-// cnt[q] = entries row[q] waits for (left of the diagonal, or right when `upper`).
+// cnt[q] = entries row[q] waits for (left of the diagonal, or right when `upper`);
+// *wmax = max of them (atomic max; zeroed by the caller).
 hipError_t launch_sweep_counts(int n, const int32_t *row, const int32_t *rp,
-                               const int32_t *dpos, bool upper, int32_t *cnt,
+                               const int32_t *dpos, bool upper, int32_t *cnt, int32_t *wmax,
                                hipStream_t stream);
+// Slot-major copy of a level-ordered sweep (width >= every row's entry count).
+hipError_t launch_sweep_ell(int n, int width, const int32_t *ptr, const int32_t *col,
+                            const double *val, int32_t *ecol, double *eval, hipStream_t stream);
 // Level-ordered copy of one triangle of lu: col/val at ptr[q].., diag[q] when upper.
 hipError_t launch_sweep_fill(int n, const int32_t *row, const int32_t *rp, const int32_t *ci,
                              const int32_t *dpos, const double *lu, bool upper,
@@ -110,7 +121,6 @@ hipError_t launch_sub_norm(int n, const double *b, const double *y, double *out,
 // The factor object behind pp_ilu: device arrays owned by it.
 struct pp_ilu {
   int64_t n = 0, nnz = 0;
-  int32_t *rp = nullptr, *ci = nullptr;  // copy of A's pattern
   double *lu = nullptr;                  // factors in A's CSR order
   ppk::Sweep fwd, bwd;
   std::vector<void *> owned;             // every device allocation above

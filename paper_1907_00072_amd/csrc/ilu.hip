@@ -153,11 +153,29 @@ __global__ __launch_bounds__(kB) void k_ilu_pivots(int n, int64_t nnz,
 __global__ __launch_bounds__(kB) void k_sweep_counts(int n, const int32_t *__restrict__ row,
                                                      const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ dpos, int upper,
-                                                     int32_t *__restrict__ cnt) {
+                                                     int32_t *__restrict__ cnt, int32_t *wmax) {
   const int q = blockIdx.x * kB + threadIdx.x;
   if (q >= n) return;
   const int i = row[q];
-  cnt[q] = upper ? rp[i + 1] - dpos[i] - 1 : dpos[i] - rp[i];
+  const int c = upper ? rp[i + 1] - dpos[i] - 1 : dpos[i] - rp[i];
+  cnt[q] = c;
+  atomicMax(wmax, c);
+}
+
+__global__ __launch_bounds__(kB) void k_sweep_ell(int n, int width,
+                                                  const int32_t *__restrict__ ptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const double *__restrict__ val,
+                                                  int32_t *__restrict__ ecol,
+                                                  double *__restrict__ eval) {
+  const int q = blockIdx.x * kB + threadIdx.x;
+  if (q >= n) return;
+  const int b = ptr[q], e = ptr[q + 1];
+  for (int s = 0; s < width; ++s) {
+    const bool have = b + s < e;
+    ecol[(int64_t)s * n + q] = have ? col[b + s] : -1;
+    eval[(int64_t)s * n + q] = have ? val[b + s] : 0.0;
+  }
 }
 
 __global__ __launch_bounds__(kB) void k_sweep_fill(int n, const int32_t *__restrict__ row,
@@ -253,6 +271,99 @@ __global__ __launch_bounds__(kRunThreads) void k_backward_run(
     for (int q = lbeg[l] + (int)threadIdx.x; q < q1; q += kRunThreads)
       backward_row(q, row, ptr, col, val, diag, z, x);
     __syncthreads();
+  }
+}
+
+// Pipelined run over narrow levels (at most one row per thread per level), on the
+// slot-major copy of W slots.  In the iteration of level l a thread issues the
+// gathers of level l's solved values, then the right-hand side of its level-(l+1)
+// row and the entries of its level-(l+2) row (neither depends on the solve), then
+// finishes level l: each level costs one round of memory latency instead of the
+// chain row -> entries -> gathers.  BACK: the backward sweep (divides by the
+// pivot).  rhs may equal out: a row's right-hand side is read before the row is
+// solved, at the level before its own.
+constexpr int kLbegChunk = 1024;  // level offsets staged in LDS at a time
+static_assert(kRunRows <= kRunThreads, "a run level must fit one row per thread");
+
+template <int W, bool BACK>
+__device__ __forceinline__ void load_slots(int q, int n, const int32_t *__restrict__ row,
+                                           const int32_t *__restrict__ ecol,
+                                           const double *__restrict__ eval,
+                                           const double *__restrict__ diag, int &i, int (&c)[W],
+                                           double (&v)[W], double &d) {
+  i = -1;
+  d = 1.0;
+#pragma unroll
+  for (int s = 0; s < W; ++s) {
+    c[s] = -1;
+    v[s] = 0.0;
+  }
+  if (q >= 0) {
+    i = row[q];
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      c[s] = ecol[(int64_t)s * n + q];
+      v[s] = eval[(int64_t)s * n + q];
+    }
+    if constexpr (BACK) d = diag[q];
+  }
+}
+
+template <int W, bool BACK>
+__global__ __launch_bounds__(kRunThreads) void k_sweep_pipe(
+    int l0, int l1, int n, const int32_t *__restrict__ lbeg, const int32_t *__restrict__ row,
+    const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+    const double *__restrict__ diag, const double *rhs, double *out) {
+  __shared__ int32_t s_lb[kLbegChunk + 4];
+  const int t = threadIdx.x;
+  int base = l0;
+  // lbeg[base + k] for k < kLbegChunk + 4 (clamped to the run's last offset)
+  auto stage = [&]() {
+    for (int k = t; k < kLbegChunk + 4; k += kRunThreads) s_lb[k] = lbeg[min(base + k, l1)];
+    __syncthreads();
+  };
+  auto pos = [&](int l) -> int {  // this thread's position at level l, or -1
+    if (l >= l1) return -1;
+    const int q = s_lb[l - base] + t;
+    return q < s_lb[l - base + 1] ? q : -1;
+  };
+  stage();
+  int i0, i1, c0[W], c1[W];
+  double v0[W], v1[W], d0, d1;
+  load_slots<W, BACK>(pos(l0), n, row, ecol, eval, diag, i0, c0, v0, d0);
+  double r0 = i0 >= 0 ? rhs[i0] : 0.0;
+  load_slots<W, BACK>(pos(l0 + 1), n, row, ecol, eval, diag, i1, c1, v1, d1);
+  for (int l = l0; l < l1; ++l) {
+    if (l - base > kLbegChunk) {  // uniform: every thread restages
+      base = l;
+      stage();
+    }
+    double g[W];
+#pragma unroll
+    for (int s = 0; s < W; ++s) g[s] = (i0 >= 0 && c0[s] >= 0) ? out[c0[s]] : 0.0;
+    const double r1 = i1 >= 0 ? rhs[i1] : 0.0;
+    int i2, c2[W];
+    double v2[W], d2;
+    load_slots<W, BACK>(pos(l + 2), n, row, ecol, eval, diag, i2, c2, v2, d2);
+    if (i0 >= 0) {
+      double acc = r0;
+#pragma unroll
+      for (int s = 0; s < W; ++s) acc -= v0[s] * g[s];
+      out[i0] = BACK ? acc / d0 : acc;
+    }
+    __syncthreads();  // level l is solved before level l + 1 gathers it
+    i0 = i1;
+    r0 = r1;
+    d0 = d1;
+    i1 = i2;
+    d1 = d2;
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      c0[s] = c1[s];
+      v0[s] = v1[s];
+      c1[s] = c2[s];
+      v1[s] = v2[s];
+    }
   }
 }
 
@@ -390,11 +501,38 @@ hipError_t launch_ilu_pivots(int n, int64_t nnz, const int32_t *dpos, const doub
 }
 
 hipError_t launch_sweep_counts(int n, const int32_t *row, const int32_t *rp,
-                               const int32_t *dpos, bool upper, int32_t *cnt,
+                               const int32_t *dpos, bool upper, int32_t *cnt, int32_t *wmax,
                                hipStream_t stream) {
   hipLaunchKernelGGL(k_sweep_counts, dim3(blocks(n)), dim3(kB), 0, stream, n, row, rp, dpos,
-                     upper ? 1 : 0, cnt);
+                     upper ? 1 : 0, cnt, wmax);
   return hipGetLastError();
+}
+
+hipError_t launch_sweep_ell(int n, int width, const int32_t *ptr, const int32_t *col,
+                            const double *val, int32_t *ecol, double *eval, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sweep_ell, dim3(blocks(n)), dim3(kB), 0, stream, n, width, ptr, col, val,
+                     ecol, eval);
+  return hipGetLastError();
+}
+
+// The pipelined run for the sweep's slot count (1..kPipeSlots).
+template <bool BACK>
+static void launch_pipe(const Sweep &S, const LevelSpan &sp, int n, const double *rhs,
+                        double *out, hipStream_t stream) {
+#define PP_PIPE(W)                                                                            \
+  hipLaunchKernelGGL((k_sweep_pipe<W, BACK>), dim3(1), dim3(kRunThreads), 0, stream, sp.l0, \
+                     sp.l1, n, S.lbeg, S.row, S.ecol, S.eval, S.diag, rhs, out)
+  switch (S.width) {
+    case 1: PP_PIPE(1); break;
+    case 2: PP_PIPE(2); break;
+    case 3: PP_PIPE(3); break;
+    case 4: PP_PIPE(4); break;
+    case 5: PP_PIPE(5); break;
+    case 6: PP_PIPE(6); break;
+    case 7: PP_PIPE(7); break;
+    default: PP_PIPE(8); break;
+  }
+#undef PP_PIPE
 }
 
 hipError_t launch_sweep_fill(int n, const int32_t *row, const int32_t *rp, const int32_t *ci,
@@ -408,9 +546,10 @@ hipError_t launch_sweep_fill(int n, const int32_t *row, const int32_t *rp, const
 
 hipError_t launch_ilu_forward(int n, const Sweep &L, const double *r, double *z,
                               hipStream_t stream) {
-  (void)n;
   for (const LevelSpan &sp : L.spans) {
-    if (sp.run) {
+    if (sp.run && L.ecol) {
+      launch_pipe<false>(L, sp, n, r, z, stream);
+    } else if (sp.run) {
       hipLaunchKernelGGL(k_forward_run, dim3(1), dim3(kRunThreads), 0, stream, sp.l0, sp.l1,
                          L.lbeg, L.row, L.ptr, L.col, L.val, r, z);
     } else {
@@ -424,9 +563,10 @@ hipError_t launch_ilu_forward(int n, const Sweep &L, const double *r, double *z,
 
 hipError_t launch_ilu_backward(int n, const Sweep &U, const double *z, double *x,
                                hipStream_t stream) {
-  (void)n;
   for (const LevelSpan &sp : U.spans) {
-    if (sp.run) {
+    if (sp.run && U.ecol) {
+      launch_pipe<true>(U, sp, n, z, x, stream);
+    } else if (sp.run) {
       hipLaunchKernelGGL(k_backward_run, dim3(1), dim3(kRunThreads), 0, stream, sp.l0, sp.l1,
                          U.lbeg, U.row, U.ptr, U.col, U.val, U.diag, z, x);
     } else {

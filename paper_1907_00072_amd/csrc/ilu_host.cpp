@@ -120,21 +120,33 @@ int build_levels(int n, const int32_t *rp_t, const int32_t *rows_t, bool upper, 
 int build_sweep(int n, const int32_t *rp, const int32_t *ci, const int32_t *dpos,
                 const double *lu, bool upper, Sweep &S, Allocs &own, Allocs &tmp,
                 hipStream_t s) {
-  int32_t *cnt = nullptr, *scan = nullptr;
+  int32_t *cnt = nullptr, *scan = nullptr, *wmax = nullptr;
   ILU_TRY(tmp.take(&cnt, n));
   ILU_TRY(tmp.take(&scan, ppk::scan_tmp_size(n)));
+  ILU_TRY(tmp.take(&wmax, 64));
   ILU_TRY(own.take(&S.ptr, (int64_t)n + 1));
-  ILU_TRY_HIP(ppk::launch_sweep_counts(n, S.row, rp, dpos, upper, cnt, s));
+  ILU_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, wmax, s));
+  ILU_TRY_HIP(ppk::launch_sweep_counts(n, S.row, rp, dpos, upper, cnt, wmax, s));
   ILU_TRY_HIP(ppk::launch_exclusive_scan(n, cnt, S.ptr, scan, s));
-  int32_t entries = 0;
-  ILU_TRY_HIP(hipMemcpyAsync(&entries, S.ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t hv[2] = {0, 0};
+  ILU_TRY_HIP(hipMemcpyAsync(&hv[0], S.ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  ILU_TRY_HIP(hipMemcpyAsync(&hv[1], wmax, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   ILU_TRY_HIP(hipStreamSynchronize(s));
+  const int32_t entries = hv[0];
   S.entries = entries;
+  S.width = hv[1];
   ILU_TRY(own.take(&S.col, entries));
   ILU_TRY(own.take(&S.val, entries));
   if (upper) ILU_TRY(own.take(&S.diag, n));
   ILU_TRY_HIP(ppk::launch_sweep_fill(n, S.row, rp, ci, dpos, lu, upper, S.ptr, S.col, S.val,
                                      S.diag, s));
+  if (S.width <= ppk::kPipeSlots) {  // slot-major copy for the pipelined runs (>= 1 slot)
+    const int w = std::max(S.width, 1);
+    S.width = w;
+    ILU_TRY(own.take(&S.ecol, (int64_t)w * n));
+    ILU_TRY(own.take(&S.eval, (int64_t)w * n));
+    ILU_TRY_HIP(ppk::launch_sweep_ell(n, w, S.ptr, S.col, S.val, S.ecol, S.eval, s));
+  }
   return PP_OK;
 }
 
