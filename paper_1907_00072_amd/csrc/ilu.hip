@@ -4,10 +4,10 @@
 // product given, the residual with its norm partials).
 //
 // The sweeps are bound by the chain of dependent levels, not by bandwidth: each
-// level is one round of dependent loads (row, its entries, the solved values it
-// waits for).  Narrow levels therefore run back to back inside one workgroup
-// (a barrier between levels, no launch between them); a level wider than
-// kRunRows gets its own launch with one thread per row.
+// level needs the solved values of earlier levels.  Narrow levels therefore run
+// back to back inside one workgroup (a barrier between levels, no launch between
+// them), pipelined so that a level costs one round of gathers (k_sweep_pipe); a
+// level wider than kRunRows gets its own launch with one thread per row.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
