@@ -339,7 +339,55 @@ def sweep(B, W, torch, dev, steps):
                                       for key, v in rec.items() if isinstance(v, dict)))
         del A, b, v0, x
         torch.cuda.empty_cache()
+    out[W.EX1_WORKLOAD["name"]] = example1(B, W, torch, dev, steps)
     return {"sweep": out, "steps": steps, "data": "synthetic"}
+
+
+def example1(B, W, torch, dev, steps):
+    """Section VI's first example: recirculating flow, eps = 1/2, 1025^2, GMRES(50) to
+    1e-8 without a preconditioner and with the paper's degrees 4 and 9 (d = 5, 10),
+    and with the power basis at Section IV's automatic degree.  Besides time-to-tol,
+    one extra solve with phase timing gives the share of GPU time in orthogonalisation
+    (CGS2 dots and updates) against the application of A p(A), the split the paper
+    plots."""
+    import warnings
+    wl = W.EX1_WORKLOAD
+    Ah, bh = W.recirculating_flow(wl["N"], wl["eps"])
+    A = B.CSRMatrix.from_host(Ah, device=dev)
+    b = torch.from_numpy(bh).to(dev)
+    v0 = torch.from_numpy(W.uniform(Ah.n, wl["v0_seed"])).to(dev)
+    x = torch.zeros_like(b)
+    rec = {"n": Ah.n, "nnz": Ah.nnz, "m": wl["m"], "tol": wl["tol"]}
+
+    def run(**kw):
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            x.zero_()
+            B.pp_gmres_solve(A, b, x, m=wl["m"], tol=wl["tol"], v0=v0, max_iters=60000, **kw)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for _ in range(steps):
+                x.zero_()
+                _, st = B.pp_gmres_solve(A, b, x, m=wl["m"], tol=wl["tol"], v0=v0,
+                                         max_iters=60000, **kw)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - ts) / steps
+            x.zero_()
+            _, sp = B.pp_gmres_solve(A, b, x, m=wl["m"], tol=wl["tol"], v0=v0, max_iters=60000,
+                                     timing=True, **kw)
+        busy = sp.t_chain + sp.t_spmv + sp.t_orth
+        return {"time_s": t, "iters": st.iters, "relres": st.relres_true,
+                "orth_share": sp.t_orth / busy if busy > 0 else None,
+                "apply_share": (sp.t_chain + sp.t_spmv) / busy if busy > 0 else None}
+    for d in wl["degrees"]:
+        rec[f"pp_d{d}" if d else "gmres"] = run(d=d)
+    p, info = B.pp_build_poly_power(A, v0, 30, auto_degree=True)
+    deg = len(B.pp_poly_coeffs(p)) - 1
+    rec["power_auto"] = dict(run(d=0, poly=p), degree=deg, potrf_info=info)
+    log(f"{wl['name']}: " + ", ".join(
+        f"{key} {v['time_s']:.3f}s/{v['iters']}it orth {v['orth_share']:.2f}"
+        for key, v in rec.items() if isinstance(v, dict)))
+    return rec
 
 
 def ilu_leg(B, W, torch, dev, ilu_only_cap=1000):

@@ -58,8 +58,8 @@ extern "C" {
 #define PP_ERR_SINGULAR (-5)  /* H_d singular, or a zero / non-finite root */
 #define PP_WARN_DEGREE_REDUCED 1 /* Arnoldi on v0 broke down after s < d steps: s roots */
 #define PP_WARN_NOT_CONVERGED 2  /* iteration cap reached, or the true residual stagnated
-                                    within 100 x tol (the attainable accuracy); x is the
-                                    last iterate */
+                                    within 100 x tol while the implicit estimate reached
+                                    tol (the attainable accuracy); x is the last iterate */
 #define PP_WARN_NONFINITE 3      /* NaN/Inf met; x is the last finite iterate */
 #define PP_WARN_CHOLESKY 4       /* power basis: Gram matrix not numerically positive definite */
 

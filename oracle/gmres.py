@@ -14,8 +14,12 @@ Readings taken where the paper is silent:
 * iterations are counted as Arnoldi steps (Section V counts the iterations
   of GMRES(50) this way);
 * attainable accuracy: once the true relative residual is below 100 * tol,
-  three consecutive cycles that each fail to reduce it by 10% end the solve
-  unconverged (the rounding floor of the true residual has been reached);
+  three consecutive cycles that each end on the implicit estimate (it reached
+  tol) but fail to reduce the true residual by 10% end the solve unconverged:
+  the Krylov recurrence believes it has converged and the true residual no
+  longer follows (its rounding floor).  A cycle that runs all m steps without
+  its estimate reaching tol is slow convergence, not a floor, and never
+  counts (Section VI's first example: GMRES(50) does converge, slowly);
 * counters: per Arnoldi step d products with A (d-1 for p, one for A) and 3
   dots; per cycle end d-1 products for the update p(A) u, one for the new
   residual and one norm; the initial residual costs one product and one
@@ -164,7 +168,7 @@ def pp_gmres(A, b, m, tol, roots=None, x0=None, max_iters=100000, v0=None, d=Non
         st.true_history.append(st.relres_true)
         if not np.isfinite(st.relres_true):
             break
-        if (st.relres_true < STAGNATION_BAND * tol
+        if (res < tol * st._bnorm and st.relres_true < STAGNATION_BAND * tol
                 and st.relres_true > STAGNATION_FACTOR * prev):
             stagnant += 1
         else:

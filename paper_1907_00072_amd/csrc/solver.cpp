@@ -43,7 +43,8 @@ constexpr int kMaxM = 256;
 constexpr int kMaxD = 256;
 constexpr double kBreakdownRtol = 1e-12;
 // Attainable accuracy: below kStagnationBand * tol, kStagnationCycles consecutive
-// restart cycles that each leave the true residual above kStagnationFactor times
+// restart cycles that each end on the implicit estimate (it reached tol) and leave
+// the true residual above kStagnationFactor times
 // its previous value end the solve (PP_WARN_NOT_CONVERGED).
 constexpr double kStagnationBand = 100.0;
 constexpr double kStagnationFactor = 0.9;
@@ -1153,7 +1154,10 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
     }
     beta = nb;
     relres = beta / bnorm;
-    stagnant = (relres < kStagnationBand * in.tol && relres > kStagnationFactor * prev)
+    // only a cycle whose estimate reached tol counts: one that ran all m steps is
+    // converging slowly, not stuck at the rounding floor
+    stagnant = (res < in.tol * bnorm && relres < kStagnationBand * in.tol &&
+                relres > kStagnationFactor * prev)
                    ? stagnant + 1
                    : 0;
   }

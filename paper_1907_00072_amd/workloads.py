@@ -44,7 +44,7 @@ import numpy as np
 __all__ = [
     "CSR", "Problem", "convection_diffusion", "stencil27_random", "bidiag1",
     "bidiag2", "laplacian5", "uniform", "normal", "config", "CONFIG_NAMES",
-    "random_csr", "recirculating_flow", "ILU_WORKLOAD",
+    "random_csr", "recirculating_flow", "ILU_WORKLOAD", "EX1_WORKLOAD",
 ]
 
 
@@ -298,6 +298,11 @@ CONFIG_NAMES = {
 # roots), on an N x N grid (the paper's mesh has 1025^2 vertices).
 ILU_WORKLOAD = {"name": "recirc2d_257_eps200_ilu0", "N": 257, "eps": 1.0 / 200.0, "m": 50,
                 "d": 13, "tol": 1e-8, "v0_seed": 106}
+# Section VI, first example: the same flow with eps = 1/2, GMRES(50) at tol 1e-8
+# without a preconditioner and with the paper's degrees 4 and 9 (d = 5 and 10
+# roots), on the paper's size (1025^2 unknowns).
+EX1_WORKLOAD = {"name": "recirc2d_1025_eps2", "N": 1025, "eps": 0.5, "m": 50,
+                "degrees": [0, 5, 10], "tol": 1e-8, "v0_seed": 107}
 
 
 def _rhs_from_solution(A: CSR, x: np.ndarray) -> np.ndarray:

@@ -594,3 +594,27 @@ def test_auto_layout_keeps_csr_for_a_short_apply(B):
     for lay, y in ys.items():
         assert _rel(y, ref) <= 1e-13, lay
     assert np.array_equal(ys["auto"], ys["csr"])
+
+
+# ---- Section VI's first example (recirculating flow, eps = 1/2) at a reduced grid
+@pytest.mark.parametrize("d", [5, 10])
+def test_recirculating_flow_example1_matches_oracle(B, d):
+    Ah, b = W.recirculating_flow(65, 0.5)
+    v0 = W.uniform(Ah.n, 107)
+    A = B.CSRMatrix.from_host(Ah)
+    x, st = B.pp_gmres_solve(A, _up(b), m=50, d=d, tol=1e-8, v0=_up(v0), max_iters=5000)
+    xo, so = ogmres.pp_gmres(Ah.to_scipy(), b, 50, 1e-8, v0=v0, d=d, max_iters=5000)
+    assert so.converged and st.relres_true < 1e-8
+    assert abs(st.iters - so.iters) <= max(1, round(0.02 * so.iters)), (st.iters, so.iters)
+    if st.iters == so.iters:
+        assert _rel(x.cpu().numpy(), xo) <= 1e-8
+
+
+def test_slow_convergence_is_not_stopped_as_stagnation(B):
+    # many cycles each gain < 10% just above tol, but none ends on the estimate
+    Ah, b = W.recirculating_flow(33, 0.5)
+    A = B.CSRMatrix.from_host(Ah)
+    x, st = B.pp_gmres_solve(A, _up(b), m=5, d=0, tol=1e-8, max_iters=60000)
+    xo, so = ogmres.pp_gmres(Ah.to_scipy(), b, 5, 1e-8, max_iters=60000)
+    assert so.converged and st.status == B.PP_OK and st.relres_true < 1e-8
+    assert abs(st.iters - so.iters) <= max(1, round(0.02 * so.iters)), (st.iters, so.iters)

@@ -178,3 +178,20 @@ def test_stagnation_at_attainable_accuracy_ends_the_solve():
     assert st.relres_true < 1e-14
     th = np.asarray(st.true_history)
     assert np.all(th[-3:] > 0.9 * th[-4:-1])
+
+
+def test_slow_convergence_near_tol_is_not_taken_for_stagnation():
+    """GMRES(5) on the eps = 1/2 recirculating flow (Section VI's first example, which
+    converges without a preconditioner) gains less than 10% per cycle for dozens of
+    cycles just above tol.  Those cycles run all m steps without their estimate
+    reaching tol, so the attainable-accuracy rule must not end the solve."""
+    A, b = W.recirculating_flow(33, 0.5)
+    x, st = gmres.pp_gmres(A.to_scipy(), b, 5, 1e-8, max_iters=60000)
+    assert st.converged
+    th = np.asarray(st.true_history)
+    slow = (th[1:] > 0.9 * th[:-1]) & (th[1:] < 1e-6)
+    run = best = 0
+    for v in slow:
+        run = run + 1 if v else 0
+        best = max(best, run)
+    assert best >= 3, best
