@@ -152,6 +152,16 @@ typedef struct pp_opts {
                              x = p(M^-1 A) y, the polynomial is built for M^-1 A, and the
                              solve stops on ||M^-1 (b - A x)|| / ||M^-1 b|| < tol.  FP64
                              only; not together with left_jacobi or F32_IR (PP_ERR_ARG). */
+  int32_t chain_group;    /* >= 2: run each Arnoldi step's chain (operator form) in a
+                             slab-skewed order, chain_group launches at a time over row
+                             slabs of chain_slab_rows rows, each launch one matrix
+                             bandwidth behind the previous (a matrix-powers style schedule,
+                             Section VII): a slab's matrix and vectors are read chain_group
+                             times in a row while they may still be cached.  Results are
+                             bit-identical to the default.  0 or 1: full-range launches.
+                             Ignored with left_ilu (M^-1 couples all rows). */
+  int32_t chain_slab_rows; /* rows per slab (rounded down to whole launch tiles, at least
+                              one); 0 -> 2^21 */
 } pp_opts;
 
 /* Solve statistics (all counts follow Section III: a dot is one block inner

@@ -45,7 +45,8 @@ class pp_opts(ctypes.Structure):
                 ("v0", ctypes.c_void_p), ("poly", ctypes.c_void_p), ("vals_f32", ctypes.c_void_p),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("op_form", ctypes.c_int32),
-                ("left_jacobi", ctypes.c_int32), ("left_ilu", ctypes.c_void_p)]
+                ("left_jacobi", ctypes.c_int32), ("left_ilu", ctypes.c_void_p),
+                ("chain_group", ctypes.c_int32), ("chain_slab_rows", ctypes.c_int32)]
 
 
 class pp_stats(ctypes.Structure):
@@ -388,12 +389,15 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
                    v0=None, poly: Optional[Poly] = None, precision: str = "f64",
                    max_iters: int = 0, inner_tol: float = 0.0, max_outer: int = 0,
                    vals_f32=None, history: int = 0, timing: bool = False, op_form: str = "pi",
-                   left_jacobi: bool = False, left_ilu: Optional[ILU0] = None, stream=None):
+                   left_jacobi: bool = False, left_ilu: Optional[ILU0] = None,
+                   chain_group: int = 0, chain_slab_rows: int = 0, stream=None):
     """Solve A x = b; returns (x, Stats).  ``x`` (if given) is the start guess and is overwritten.
 
     ``op_form``: "pi" applies A p(A) v as v - pi(A) v (default), "p" as A (p(A) v).
     ``left_ilu``: an ILU(0) of A (pp_ilu0_factor) applied on the left, the
     polynomial built for M^-1 A on the right.
+    ``chain_group`` >= 2: the slab-skewed chain schedule (pp_opts.chain_group), over
+    slabs of ``chain_slab_rows`` rows.
     """
     torch = _torch()
     _dev_vec(b, torch.float64, A.n, "b")
@@ -423,6 +427,8 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
     o.left_jacobi = 1 if left_jacobi else 0
     if left_ilu is not None:
         o.left_ilu = left_ilu.handle.value
+    o.chain_group = int(chain_group)
+    o.chain_slab_rows = int(chain_slab_rows)
     st = pp_stats()
     rc = lib().pp_gmres_solve(ctypes.byref(A.c()), _ptr(b), _ptr(x), int(m), int(d), float(tol),
                               ctypes.byref(o), _stream(stream), ctypes.byref(st))

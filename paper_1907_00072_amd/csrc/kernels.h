@@ -69,7 +69,16 @@ struct ChainArgs {
   T *y_out;
   double c1, c2, cf;
   const double *yscale;  // scale of y_in in the operator form's last step (nullptr = 1)
+  int tile0 = 0;         // first tile (chain_tile_rows rows each) the launch covers
+  int ntiles = 0;        // tiles it covers (0 = through the last row)
 };
+
+// Rows of one tile of the product launches (one workgroup): 256, or 512 for FP32
+// products on the sliced copy (two slices per wavefront).
+template <typename T>
+inline int chain_tile_rows(const SpMat<T> &A) {
+  return (A.sdesc && sizeof(T) == sizeof(float)) ? 2 * kBlock : kBlock;
+}
 
 // `fold` and `last` select the variants above (fold: kinds 0 and 2; last: kinds 1, 2, 3).
 template <typename T>
@@ -81,10 +90,16 @@ template <typename T>
 hipError_t launch_axpy(int n, double c, const T *g, const double *gscale, const T *y_in, T *y_out,
                        hipStream_t stream);
 
-// out = A * (gscale * g).
+// out = A * (gscale * g), on the rows of tiles [tile0, tile0 + ntiles) (ntiles = 0:
+// through the last row).
 template <typename T>
 hipError_t launch_spmv(const SpMat<T> &A, const T *g, const double *gscale, T *out,
-                       hipStream_t stream);
+                       hipStream_t stream, int tile0 = 0, int ntiles = 0);
+
+// *out = max over stored entries of |column - row| (the matrix bandwidth); *out
+// zeroed by the caller.
+hipError_t launch_bandwidth(int n, const int32_t *rp, const int32_t *ci, int32_t *out,
+                            hipStream_t stream);
 
 // out = b - A x (out may be a T-typed vector of the same type as A), and
 // partial[tile] = sum over the tile of out^2 (double).  Returns the tile count.

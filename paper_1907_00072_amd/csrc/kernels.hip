@@ -361,7 +361,7 @@ __device__ __forceinline__ void chain_row(const ChainArgs<T> &a, int i, T acc, T
 template <typename T, int KIND, bool FOLD, bool LAST, bool SELL, int R>
 __global__ __launch_bounds__(kBlock) void k_chain(SpMat<T> A, ChainArgs<T> a) {
   static_assert(R == 1 || (R == 2 && SELL), "two rows per thread need the sliced copy");
-  const int r0 = xcd_tile(blockIdx.x, gridDim.x) * kBlock * R;
+  const int r0 = (a.tile0 + xcd_tile(blockIdx.x, gridDim.x)) * kBlock * R;
   const int t = threadIdx.x;
   constexpr bool kReadY = (KIND == 0) || (KIND == 1) || (KIND == 2 && (FOLD || LAST)) ||
                           (KIND == 3 && LAST);
@@ -401,9 +401,10 @@ __global__ __launch_bounds__(kBlock) void k_chain(SpMat<T> A, ChainArgs<T> a) {
 // R rows per thread as in k_chain (R = 2 only on the sliced copy).
 template <typename T, bool SELL, int R>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpMat<T> A, const T *__restrict__ g,
-                                                 const double *gscale, T *__restrict__ out) {
+                                                 const double *gscale, T *__restrict__ out,
+                                                 int tile0) {
   static_assert(R == 1 || (R == 2 && SELL), "two rows per thread need the sliced copy");
-  const int r0 = xcd_tile(blockIdx.x, gridDim.x) * kBlock * R;
+  const int r0 = (tile0 + xcd_tile(blockIdx.x, gridDim.x)) * kBlock * R;
   const int t = threadIdx.x;
   T acc[R];
   if constexpr (R == 1) {
@@ -1063,7 +1064,9 @@ hipError_t launch_chain(const SpMat<T> &A, int kind, bool fold, bool last, const
   // FP32 on the sliced copy: two rows per thread (measured +8% on the FP32 step;
   // no gain in FP64, whose single-slice loads already fill the memory pipes)
   const bool two = A.sdesc && sizeof(T) == sizeof(float);
-  const dim3 grid(tiles_of(A.n)), grid2((A.n + 2 * kBlock - 1) / (2 * kBlock)), block(kBlock);
+  const dim3 grid(a.ntiles > 0 ? a.ntiles : tiles_of(A.n) - a.tile0),
+      grid2(a.ntiles > 0 ? a.ntiles : (A.n + 2 * kBlock - 1) / (2 * kBlock) - a.tile0),
+      block(kBlock);
 #define PP_CHAIN(K, F, L)                                                                     \
   do {                                                                                        \
     if (two)                                                                                  \
@@ -1108,16 +1111,33 @@ hipError_t launch_axpy(int n, double c, const T *g, const double *gscale, const 
 
 template <typename T>
 hipError_t launch_spmv(const SpMat<T> &A, const T *g, const double *gscale, T *out,
-                       hipStream_t stream) {
+                       hipStream_t stream, int tile0, int ntiles) {
+  const int all = (A.n + chain_tile_rows(A) - 1) / chain_tile_rows(A);
+  const dim3 grid(ntiles > 0 ? ntiles : all - tile0), block(kBlock);
   if (A.sdesc && sizeof(T) == sizeof(float))
-    hipLaunchKernelGGL((k_spmv<T, true, 2>), dim3((A.n + 2 * kBlock - 1) / (2 * kBlock)),
-                       dim3(kBlock), 0, stream, A, g, gscale, out);
+    hipLaunchKernelGGL((k_spmv<T, true, 2>), grid, block, 0, stream, A, g, gscale, out, tile0);
   else if (A.sdesc)
-    hipLaunchKernelGGL((k_spmv<T, true, 1>), dim3(tiles_of(A.n)), dim3(kBlock), 0, stream, A, g,
-                       gscale, out);
+    hipLaunchKernelGGL((k_spmv<T, true, 1>), grid, block, 0, stream, A, g, gscale, out, tile0);
   else
-    hipLaunchKernelGGL((k_spmv<T, false, 1>), dim3(tiles_of(A.n)), dim3(kBlock), 0, stream, A, g,
-                       gscale, out);
+    hipLaunchKernelGGL((k_spmv<T, false, 1>), grid, block, 0, stream, A, g, gscale, out, tile0);
+  return hipGetLastError();
+}
+
+namespace {
+__global__ __launch_bounds__(kBlock) void k_bandwidth(int n, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci,
+                                                      int32_t *out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int w = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) w = max(w, abs(ci[p] - i));
+  if (w > 0) atomicMax(out, w);
+}
+}  // namespace
+
+hipError_t launch_bandwidth(int n, const int32_t *rp, const int32_t *ci, int32_t *out,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL(k_bandwidth, dim3(tiles_of(n)), dim3(kBlock), 0, stream, n, rp, ci, out);
   return hipGetLastError();
 }
 
@@ -1364,7 +1384,7 @@ hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, cons
   template hipError_t launch_axpy<T>(int, double, const T *, const double *, const T *, T *,    \
                                      hipStream_t);                                              \
   template hipError_t launch_spmv<T>(const SpMat<T> &, const T *, const double *, T *,           \
-                                     hipStream_t);                                              \
+                                     hipStream_t, int, int);                                    \
   template hipError_t launch_residual<T>(const SpMat<T> &, const T *, const T *, T *, double *,  \
                                          int *, hipStream_t);                                   \
   template hipError_t launch_dots<T>(int, int, const T *, int64_t, int, int, const T *, double *, \

@@ -261,6 +261,10 @@ template <typename T>
 struct Opr : SpMat<T> {
   const pp_ilu *ilu = nullptr;
   T *prod = nullptr;
+  // slab-skewed schedule of the Arnoldi step's chain (group >= 2: on)
+  int blk_group = 0;
+  int blk_slab_rows = 0;
+  int blk_bw_rows = 0;  // the matrix bandwidth max |col - row|
   Opr(const SpMat<T> &m) : SpMat<T>(m) {}  // NOLINT: a plain matrix is an operator
 };
 
@@ -398,6 +402,58 @@ int run_horner(const Opr<T> &A, const std::vector<double> &c, const T *g, const 
   return PP_OK;
 }
 
+// One launch of the operator-form chain: a plain product (t = A p) or a fused
+// product + root update (ChainArgs kind).
+template <typename T>
+struct OpLaunch {
+  bool product;
+  int kind;
+  bool last;
+  ppk::ChainArgs<T> a;  // for a product: g, gscale and out only
+};
+
+// The launches of run_op_chain in slab-skewed order, a matrix-powers style
+// schedule (Section VII): the launches are taken `group` at a time, and inside a
+// group slab b of the group's k-th launch covers the tiles [b S - k w, (b+1) S - k w)
+// (S tiles per slab, w = the bandwidth rounded up to whole tiles), run for
+// b = 0, 1, ... with the group's launches in order inside each slab.  Launch k reads
+// launch k-1's output only within the bandwidth of its own rows, all of which is
+// written by then, and a ping-pong buffer is overwritten only at rows every later
+// reader of its old contents has passed.  So each slab's matrix and vectors are
+// read group times while they may still sit in cache, with results bit-identical
+// to the full-range launches.
+template <typename T>
+int run_op_launches_blocked(const Opr<T> &A, const std::vector<OpLaunch<T>> &L,
+                            hipStream_t s) {
+  const int tr = ppk::chain_tile_rows(A);
+  const int ntile = (A.n + tr - 1) / tr;
+  const int S = std::max(1, A.blk_slab_rows / tr);
+  const int w = (A.blk_bw_rows + tr - 1) / tr;
+  const int K = (int)L.size();
+  for (int k0 = 0; k0 < K; k0 += A.blk_group) {
+    const int k1 = std::min(K, k0 + A.blk_group);
+    const int64_t span = (int64_t)ntile + (int64_t)(k1 - 1 - k0) * w;
+    for (int64_t b = 0; b * S < span; ++b) {
+      for (int k = k0; k < k1; ++k) {
+        const int64_t shift = (int64_t)(k - k0) * w;
+        const int t0 = (int)std::max<int64_t>(0, b * S - shift);
+        const int t1 = (int)std::min<int64_t>(ntile, (b + 1) * S - shift);
+        if (t1 <= t0) continue;
+        const OpLaunch<T> &l = L[k];
+        if (l.product) {
+          PP_TRY_HIP(ppk::launch_spmv<T>(A, l.a.g, l.a.gscale, l.a.out, s, t0, t1 - t0));
+        } else {
+          ppk::ChainArgs<T> a = l.a;
+          a.tile0 = t0;
+          a.ntiles = t1 - t0;
+          PP_TRY_HIP(ppk::launch_chain<T>(A, l.kind, false, l.last, a, s));
+        }
+      }
+    }
+  }
+  return PP_OK;
+}
+
 // w_out = A p(A) (gscale * g), evaluated as v - pi(A) v with v = gscale * g:
 // one fused root-update launch per real root (p' = p - A p / theta) and two per
 // conjugate pair (t = A p, then p' = p - c1 t + c2 A t), the last launch writing
@@ -406,6 +462,38 @@ template <typename T>
 int run_op_chain(const Opr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
                  const double *gscale, T *w_out, T *P0, T *P1, T *Tb, hipStream_t s,
                  Counters *cnt, double *bytes = nullptr, int64_t *launches = nullptr) {
+  if (A.blk_group >= 2 && !A.ilu) {
+    std::vector<OpLaunch<T>> L;
+    const int K = (int)steps.size();
+    const T *cur = g;
+    const double *cs = gscale;
+    T *bufs[2] = {P0, P1};
+    int pb = 0;
+    for (int k = 0; k < K; ++k) {
+      const ppn::Step &st = steps[k];
+      const bool last = (k == K - 1);
+      T *dst = last ? w_out : bufs[pb];
+      if (st.kind == 0) {
+        L.push_back({false, 3, last, ppk::ChainArgs<T>{cur, cs, nullptr, nullptr, dst,
+                                                       last ? g : nullptr, nullptr, st.c1, 0.0,
+                                                       0.0, last ? gscale : nullptr}});
+        if (bytes) *bytes += product_bytes(A, 1 + (last ? 1 : 0));
+      } else {
+        L.push_back({true, 0, false, ppk::ChainArgs<T>{cur, cs, nullptr, nullptr, Tb, nullptr,
+                                                       nullptr, 0.0, 0.0, 0.0, nullptr}});
+        L.push_back({false, 2, last, ppk::ChainArgs<T>{Tb, nullptr, cur, cs, dst,
+                                                       last ? g : nullptr, nullptr, st.c1,
+                                                       st.c2, 0.0, last ? gscale : nullptr}});
+        if (bytes) *bytes += product_bytes(A, 1) + product_bytes(A, 2 + (last ? 1 : 0));
+      }
+      cur = dst;
+      cs = nullptr;
+      pb ^= 1;
+    }
+    if (launches) *launches += (int64_t)L.size();
+    if (cnt) cnt->spmvs += (int64_t)L.size();
+    return run_op_launches_blocked<T>(A, L, s);
+  }
   auto account = [&](int vec_rw) {
     if (bytes) *bytes += product_bytes(A, vec_rw);
     if (launches) ++*launches;
@@ -1037,6 +1125,22 @@ int residual_f64(const Opr<double> &A, Work<double> &w, const double *b, const d
   return PP_OK;
 }
 
+// Turn on the slab-skewed chain schedule of an operator when the options ask for
+// it: the matrix bandwidth comes from one pass over the column indices.
+template <typename T>
+int set_blocking(Opr<T> &A, const SolveIn &in, int32_t *scratch, hipStream_t s) {
+  if (in.o.chain_group < 2 || in.ilu) return PP_OK;
+  PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, scratch, s));
+  PP_TRY_HIP(ppk::launch_bandwidth(A.n, in.A->row_ptr, in.A->col_ind, scratch, s));
+  int32_t bw = 0;
+  PP_TRY_HIP(hipMemcpyAsync(&bw, scratch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  A.blk_group = in.o.chain_group;
+  A.blk_slab_rows = in.o.chain_slab_rows > 0 ? in.o.chain_slab_rows : (1 << 21);
+  A.blk_bw_rows = bw;
+  return PP_OK;
+}
+
 int solve_f64(const SolveIn &in, pp_stats *st) {
   const double t_start = now_s();
   Arena *ar = nullptr;
@@ -1051,15 +1155,18 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
   w.carve(meas, n, L);
   double *xsave = meas.take<double>(n);
   double *prod = in.ilu ? meas.take<double>(n) : nullptr;
+  int32_t *iscratch = meas.take<int32_t>(64);
   PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
   Carver c(ar->dev);
   w.carve(c, n, L);
   xsave = c.take<double>(n);
   prod = in.ilu ? c.take<double>(n) : nullptr;
+  iscratch = c.take<int32_t>(64);
   w.host = ar->host;
   Opr<double> A(with_sell(view<double>(in.A, in.A->vals), sc));
   A.ilu = in.ilu;
   A.prod = prod;
+  PP_TRY(set_blocking<double>(A, in, iscratch, in.s));
   hipStream_t s = in.s;
   Counters cnt;
   cnt.history = in.o.history;
@@ -1185,19 +1292,22 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
   w64.carve(meas, n, 1);
   float *vals32 = cast32 ? meas.take<float>(nnz > 0 ? nnz : 1) : nullptr;
   double *xsave = meas.take<double>(n);
+  int32_t *iscratch = meas.take<int32_t>(64);
   PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles() + 16));
   Carver c(ar->dev);
   w.carve(c, n, L);
   w64.carve(c, n, 1);
   vals32 = cast32 ? c.take<float>(nnz > 0 ? nnz : 1) : nullptr;
   xsave = c.take<double>(n);
+  iscratch = c.take<int32_t>(64);
   w.host = ar->host;
   w64.host = ar->host;
   hipStream_t s = in.s;
   const SpMat<double> A64 = with_sell(view<double>(in.A, in.A->vals), sc);
   if (cast32) PP_TRY_HIP(ppk::launch_cast_f32(nnz, (const double *)in.A->vals, vals32, s));
-  const SpMat<float> A32 = with_sell(
-      view<float>(in.A, in.o.vals_f32 ? (const void *)in.o.vals_f32 : (const void *)vals32), sc);
+  Opr<float> A32(with_sell(
+      view<float>(in.A, in.o.vals_f32 ? (const void *)in.o.vals_f32 : (const void *)vals32), sc));
+  PP_TRY(set_blocking<float>(A32, in, iscratch, s));
   Counters cnt;
   cnt.history = in.o.history;
   cnt.history_cap = in.o.history ? in.o.history_cap : 0;

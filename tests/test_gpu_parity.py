@@ -618,3 +618,27 @@ def test_slow_convergence_is_not_stopped_as_stagnation(B):
     xo, so = ogmres.pp_gmres(Ah.to_scipy(), b, 5, 1e-8, max_iters=60000)
     assert so.converged and st.status == B.PP_OK and st.relres_true < 1e-8
     assert abs(st.iters - so.iters) <= max(1, round(0.02 * so.iters)), (st.iters, so.iters)
+
+
+# ---- slab-skewed chain schedule (matrix-powers style, Section VII): same bits
+@pytest.mark.parametrize("group,slab", [(2, 2048), (5, 4096), (40, 1024), (3, 1 << 21)])
+@pytest.mark.parametrize("precision", ["f64", "f32_ir"])
+def test_blocked_chain_gives_identical_results(B, group, slab, precision):
+    P = W.config(2, N=32)  # bandwidth 1024 rows, complex root pairs
+    A = B.CSRMatrix.from_host(P.A)
+    kw = dict(m=20, d=10, tol=1e-10, v0=_up(P.v0), precision=precision)
+    x0, s0 = B.pp_gmres_solve(A, _up(P.b), **kw)
+    x1, s1 = B.pp_gmres_solve(A, _up(P.b), chain_group=group, chain_slab_rows=slab, **kw)
+    assert s0.relres_true < 1e-10
+    assert s1.iters == s0.iters and torch.equal(x0, x1)
+
+
+def test_blocked_chain_with_wide_bandwidth(B):
+    # bandwidth about n: each launch trails the previous by more than a slab
+    Ah = W.random_csr(3000, 6, seed=12, diag_shift=8.0)
+    A = B.CSRMatrix.from_host(Ah)
+    kw = dict(m=15, d=6, tol=1e-10, v0=_up(W.uniform(3000, 13)))
+    x0, s0 = B.pp_gmres_solve(A, _up(W.normal(3000, 14)), **kw)
+    x1, s1 = B.pp_gmres_solve(A, _up(W.normal(3000, 14)), chain_group=4, chain_slab_rows=512,
+                              **kw)
+    assert s1.iters == s0.iters and torch.equal(x0, x1)
