@@ -27,12 +27,15 @@ namespace ppk {
 constexpr int kRunThreads = 1024;  // threads of the one workgroup that steps through a run
 constexpr int kRunRows = 1024;     // widest level handled inside a run
 constexpr int kPipeSlots = 8;      // most waited-for entries per row of the pipelined run
+constexpr int kRing = 4;           // levels of solved values a run keeps in LDS
+constexpr int kRingSlots = 4;      // most entries per row of the LDS-ring run kernel
 
 // A span of consecutive levels [l0, l1): a run (narrow levels, one workgroup) or
 // a single wide level.
 struct LevelSpan {
   int l0, l1;
   bool run;
+  int width;  // rows of the span's widest level
 };
 
 // Level schedule of one triangular sweep and its level-ordered copy of the factor.
@@ -54,6 +57,14 @@ struct Sweep {
   int width = 0;            // most entries one row waits for
   int32_t *ecol = nullptr;  // [width * n] slot-major copy (nullptr: width > kPipeSlots)
   double *eval = nullptr;   // [width * n]
+  // [width * n] where the run kernel finds each entry's solved value: its slot in the
+  // run's LDS ring ((level % kRing) * kRunRows + position in the level) when the
+  // column was solved in the same run at most kRing - 1 levels earlier, -1 when it
+  // was solved by an earlier launch; nullptr when some entry is neither (then the
+  // run kernel reads every solved value from global memory)
+  int32_t *esrc = nullptr;
+  int32_t *lglob = nullptr;  // [nlev] 1 when a level of a run has an entry read from global
+  const double *zero = nullptr;  // a 0.0 nothing writes: the target of unneeded loads
   std::vector<int32_t> lbeg_host;
   std::vector<LevelSpan> spans;
 };
@@ -107,6 +118,18 @@ hipError_t launch_sweep_fill(int n, const int32_t *row, const int32_t *rp, const
                              const int32_t *dpos, const double *lu, bool upper,
                              const int32_t *ptr, int32_t *col, double *val, double *diag,
                              hipStream_t stream);
+
+// qpos[row[q]] = q.
+hipError_t launch_sweep_inverse(int n, const int32_t *row, int32_t *qpos, hipStream_t stream);
+// esrc of a slot-major sweep (see Sweep); runstart[l] = first level of the run that
+// holds level l, or -1 for a level launched on its own; lglob[l] = 1 (zeroed by the
+// caller) when a row of run level l reads a value solved by an earlier launch;
+// *flag = 1 when an entry's column was solved in the same run but kRing or more
+// levels earlier.
+hipError_t launch_sweep_sources(int n, int width, int nlev, const int32_t *lbeg,
+                                const int32_t *ecol, const int32_t *qpos,
+                                const int32_t *runstart, int32_t *esrc, int32_t *lglob,
+                                int32_t *flag, hipStream_t stream);
 
 // Elementwise chain step with the operator's product given (prod = Op g, unscaled):
 // the kinds of ChainArgs with (A g)(i) replaced by prod(i).

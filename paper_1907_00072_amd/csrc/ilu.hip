@@ -367,6 +367,160 @@ __global__ __launch_bounds__(kRunThreads) void k_sweep_pipe(
   }
 }
 
+// Level of position q: the last l with lbeg[l] <= q.
+__device__ __forceinline__ int level_of(int q, int nlev, const int32_t *__restrict__ lbeg) {
+  int lo = 0, hi = nlev - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (lbeg[mid] <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kB) void k_sweep_inverse(int n, const int32_t *__restrict__ row,
+                                                      int32_t *__restrict__ qpos) {
+  const int q = blockIdx.x * kB + threadIdx.x;
+  if (q < n) qpos[row[q]] = q;
+}
+
+__global__ __launch_bounds__(kB) void k_sweep_sources(int n, int width, int nlev,
+                                                      const int32_t *__restrict__ lbeg,
+                                                      const int32_t *__restrict__ ecol,
+                                                      const int32_t *__restrict__ qpos,
+                                                      const int32_t *__restrict__ runstart,
+                                                      int32_t *__restrict__ esrc,
+                                                      int32_t *__restrict__ lglob, int32_t *flag) {
+  const int q = blockIdx.x * kB + threadIdx.x;
+  if (q >= n) return;
+  const int lq = level_of(q, nlev, lbeg);
+  const int rs = runstart[lq];
+  int far = 0, glob = 0;
+  for (int s = 0; s < width; ++s) {
+    const int64_t e = (int64_t)s * n + q;
+    const int c = ecol[e];
+    int src = -1;
+    if (c >= 0 && rs >= 0) {
+      const int qc = qpos[c];
+      const int lc = level_of(qc, nlev, lbeg);
+      if (lc >= rs) {  // solved inside this run
+        if (lq - lc < kRing) src = (lc % kRing) * kRunRows + (qc - lbeg[lc]);
+        else far = 1;
+      } else {
+        glob = 1;  // solved by an earlier launch
+      }
+    }
+    esrc[e] = src;
+  }
+  if (glob) lglob[lq] = 1;
+  if (far) atomicOr(flag, 1);
+}
+
+// Registers of one row of a run level (see k_sweep_ring).
+template <int W>
+struct RingRow {
+  bool ok;         // this thread has a row at the level
+  int i;           // the row
+  int c[W], x[W];  // entries: column and ring slot (-1: not in the ring)
+  double v[W], d, r;
+};
+
+// The pipelined run with the solved values of the last kRing levels in an LDS ring
+// (each entry's esrc says where its value is).  Only LDS is exchanged between the
+// run's waves, so the barrier between levels fences LDS alone and the global
+// loads issued ahead stay in flight across it.  The level loop is unrolled by
+// three over three register sets (the level being solved, the next one, the one
+// after), so a prefetched value lands in the register that later uses it and no
+// copy waits for it; every load is unconditional (clamped indices, results
+// selected at use).  Global gathers, of values solved by earlier launches, are
+// issued only on the levels that have them (lglob, uniform per level).
+template <int W, bool BACK>
+__global__ __launch_bounds__(kRunThreads) void k_sweep_ring(
+    int l0, int l1, int n, const int32_t *__restrict__ lbeg, const int32_t *__restrict__ lglob,
+    const int32_t *__restrict__ row, const int32_t *__restrict__ ecol,
+    const int32_t *__restrict__ esrc, const double *__restrict__ eval,
+    const double *__restrict__ diag, const double *__restrict__ zero, const double *rhs,
+    double *out) {
+  // the last slot is never written: the target of ring loads a row does not need
+  __shared__ double ring[kRing * kRunRows + 1];
+  constexpr int kNoSlot = kRing * kRunRows;
+  __shared__ int32_t s_lb[kLbegChunk + 8];
+  __shared__ int32_t s_gf[kLbegChunk + 8];
+  const int t = threadIdx.x;
+  int base = l0;
+  auto stage = [&]() {
+    for (int k = t; k < kLbegChunk + 8; k += (int)blockDim.x) {
+      const int l = base + k;
+      s_lb[k] = lbeg[min(l, l1)];
+      s_gf[k] = l < l1 ? lglob[l] : 0;
+    }
+    __syncthreads();
+  };
+  auto pos = [&](int l) -> int {
+    if (l >= l1) return -1;
+    const int q = s_lb[l - base] + t;
+    return q < s_lb[l - base + 1] ? q : -1;
+  };
+  auto load = [&](int l, RingRow<W> &R) {
+    const int q = pos(l);
+    R.ok = q >= 0;
+    const int qc = R.ok ? q : 0;
+    R.i = row[qc];
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      R.c[s] = ecol[(int64_t)s * n + qc];
+      R.x[s] = esrc[(int64_t)s * n + qc];
+      R.v[s] = eval[(int64_t)s * n + qc];
+    }
+    if constexpr (BACK) R.d = diag[qc];
+  };
+  // level l: solve S0, fetch the right-hand side of S1 (level l + 1) and the
+  // entries of level l + 2 into S2
+  auto step = [&](int l, RingRow<W> &S0, RingRow<W> &S1, RingRow<W> &S2) {
+    const bool glob = __builtin_amdgcn_readfirstlane(s_gf[l - base]) != 0;
+    double gg[W], gi[W];
+    if (glob) {
+#pragma unroll
+      for (int s = 0; s < W; ++s)
+        gg[s] = *((S0.ok && S0.x[s] < 0 && S0.c[s] >= 0) ? out + S0.c[s] : zero);
+    }
+#pragma unroll
+    for (int s = 0; s < W; ++s) gi[s] = ring[S0.x[s] >= 0 ? S0.x[s] : kNoSlot];
+    S1.r = *(S1.ok ? rhs + S1.i : zero);
+    load(l + 2, S2);
+    if (S0.ok) {
+      double acc = S0.r;
+#pragma unroll
+      for (int s = 0; s < W; ++s) {
+        const double g = S0.x[s] >= 0 ? gi[s] : ((glob && S0.c[s] >= 0) ? gg[s] : 0.0);
+        acc -= S0.v[s] * g;
+      }
+      const double val = BACK ? acc / S0.d : acc;
+      ring[(l % kRing) * kRunRows + t] = val;
+      out[S0.i] = val;
+    }
+    // level l's ring slots are written before level l + 1 reads them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  };
+  stage();
+  RingRow<W> A, Bv, C;
+  load(l0, A);
+  A.r = *(A.ok ? rhs + A.i : zero);
+  load(l0 + 1, Bv);
+  // levels past l1 are empty (no row), so the loop may run up to two of them
+  for (int l = l0; l < l1; l += 3) {
+    if (l - base >= kLbegChunk) {  // uniform: every thread restages
+      base = l;
+      stage();
+    }
+    step(l, A, Bv, C);
+    step(l + 1, Bv, C, A);
+    step(l + 2, C, A, Bv);
+  }
+}
+
 // ------------------------------------------------------------- composed operator
 // The chain step kinds of ChainArgs with (A g)(i) replaced by the given prod(i).
 template <int KIND, bool FOLD, bool LAST>
@@ -515,13 +669,39 @@ hipError_t launch_sweep_ell(int n, int width, const int32_t *ptr, const int32_t 
   return hipGetLastError();
 }
 
-// The pipelined run for the sweep's slot count (1..kPipeSlots).
+hipError_t launch_sweep_inverse(int n, const int32_t *row, int32_t *qpos, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sweep_inverse, dim3(blocks(n)), dim3(kB), 0, stream, n, row, qpos);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_sources(int n, int width, int nlev, const int32_t *lbeg,
+                                const int32_t *ecol, const int32_t *qpos,
+                                const int32_t *runstart, int32_t *esrc, int32_t *lglob,
+                                int32_t *flag, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sweep_sources, dim3(blocks(n)), dim3(kB), 0, stream, n, width, nlev,
+                     lbeg, ecol, qpos, runstart, esrc, lglob, flag);
+  return hipGetLastError();
+}
+
+// The pipelined run for the sweep's slot count (1..kPipeSlots): with the LDS ring
+// when every in-run dependency is recent enough, else on global memory.
 template <bool BACK>
 static void launch_pipe(const Sweep &S, const LevelSpan &sp, int n, const double *rhs,
                         double *out, hipStream_t stream) {
 #define PP_PIPE(W)                                                                            \
-  hipLaunchKernelGGL((k_sweep_pipe<W, BACK>), dim3(1), dim3(kRunThreads), 0, stream, sp.l0, \
-                     sp.l1, n, S.lbeg, S.row, S.ecol, S.eval, S.diag, rhs, out)
+  do {                                                                                        \
+    if constexpr (W <= kRingSlots) {                                                          \
+      if (S.esrc) {                                                                           \
+        hipLaunchKernelGGL((k_sweep_ring<(W <= kRingSlots ? W : 1), BACK>), dim3(1),          \
+                           dim3((sp.width + 63) / 64 * 64), 0, stream, sp.l0, sp.l1, n,       \
+                           S.lbeg, S.lglob,                                                   \
+                           S.row, S.ecol, S.esrc, S.eval, S.diag, S.zero, rhs, out);          \
+        break;                                                                                \
+      }                                                                                       \
+    }                                                                                         \
+    hipLaunchKernelGGL((k_sweep_pipe<W, BACK>), dim3(1), dim3(kRunThreads), 0, stream, sp.l0, \
+                       sp.l1, n, S.lbeg, S.row, S.ecol, S.eval, S.diag, rhs, out);            \
+  } while (0)
   switch (S.width) {
     case 1: PP_PIPE(1); break;
     case 2: PP_PIPE(2); break;

@@ -64,11 +64,13 @@ std::vector<LevelSpan> make_spans(const std::vector<int32_t> &lbeg) {
   std::vector<LevelSpan> spans;
   const int nlev = (int)lbeg.size() - 1;
   for (int l = 0; l < nlev; ++l) {
-    const bool narrow = lbeg[l + 1] - lbeg[l] <= ppk::kRunRows;
+    const int rows = lbeg[l + 1] - lbeg[l];
+    const bool narrow = rows <= ppk::kRunRows;
     if (narrow && !spans.empty() && spans.back().run && spans.back().l1 == l) {
       spans.back().l1 = l + 1;
+      spans.back().width = std::max(spans.back().width, rows);
     } else {
-      spans.push_back(LevelSpan{l, l + 1, narrow});
+      spans.push_back(LevelSpan{l, l + 1, narrow, rows});
     }
   }
   return spans;
@@ -146,6 +148,32 @@ int build_sweep(int n, const int32_t *rp, const int32_t *ci, const int32_t *dpos
     ILU_TRY(own.take(&S.ecol, (int64_t)w * n));
     ILU_TRY(own.take(&S.eval, (int64_t)w * n));
     ILU_TRY_HIP(ppk::launch_sweep_ell(n, w, S.ptr, S.col, S.val, S.ecol, S.eval, s));
+    // where the run kernel finds each entry's solved value (LDS ring or global)
+    std::vector<int32_t> runstart(S.nlev, -1);
+    for (const ppk::LevelSpan &sp : S.spans)
+      if (sp.run)
+        for (int l = sp.l0; l < sp.l1; ++l) runstart[l] = sp.l0;
+    int32_t *qpos = nullptr, *rs = nullptr, *flag = nullptr;
+    ILU_TRY(tmp.take(&qpos, n));
+    ILU_TRY(tmp.take(&rs, S.nlev));
+    ILU_TRY(tmp.take(&flag, 64));
+    ILU_TRY(own.take(&S.esrc, (int64_t)w * n));
+    ILU_TRY(own.take(&S.lglob, S.nlev));
+    ILU_TRY_HIP(ppk::launch_fill<int32_t>(S.nlev, 0, S.lglob, s));
+    double *zero = nullptr;
+    ILU_TRY(own.take(&zero, 8));
+    ILU_TRY_HIP(ppk::launch_fill<double>(8, 0.0, zero, s));
+    S.zero = zero;
+    ILU_TRY_HIP(hipMemcpyAsync(rs, runstart.data(), S.nlev * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
+    ILU_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, flag, s));
+    ILU_TRY_HIP(ppk::launch_sweep_inverse(n, S.row, qpos, s));
+    ILU_TRY_HIP(ppk::launch_sweep_sources(n, w, S.nlev, S.lbeg, S.ecol, qpos, rs, S.esrc,
+                                          S.lglob, flag, s));
+    int32_t far = 0;
+    ILU_TRY_HIP(hipMemcpyAsync(&far, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ILU_TRY_HIP(hipStreamSynchronize(s));
+    if (far) S.esrc = nullptr;  // (its buffer stays owned and is freed with the factor)
   }
   return PP_OK;
 }
