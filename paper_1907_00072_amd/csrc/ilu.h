@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "kernels.h"
@@ -69,11 +70,12 @@ struct Sweep {
   std::vector<LevelSpan> spans;
 };
 
-// z = L^-1 r (z may equal r): the forward sweep of the level-ordered L.
-hipError_t launch_ilu_forward(int n, const Sweep &L, const double *r, double *z,
+// z = L^-1 r (z may equal r): the forward sweep of the level-ordered L.  work
+// (n doubles) receives r in level order when the sweep has LDS-ring runs.
+hipError_t launch_ilu_forward(int n, const Sweep &L, const double *r, double *z, double *work,
                               hipStream_t stream);
-// x = U^-1 z, in place allowed (x == z).
-hipError_t launch_ilu_backward(int n, const Sweep &U, const double *z, double *x,
+// x = U^-1 z, in place allowed (x == z); work as above.
+hipError_t launch_ilu_backward(int n, const Sweep &U, const double *z, double *x, double *work,
                                hipStream_t stream);
 
 // Pattern check: dpos[i] = position of row i's diagonal (-1 if absent);
@@ -146,7 +148,9 @@ struct pp_ilu {
   int64_t n = 0, nnz = 0;
   double *lu = nullptr;                  // factors in A's CSR order
   ppk::Sweep fwd, bwd;
+  double *work = nullptr;                // [n] right-hand side in level order
   std::vector<void *> owned;             // every device allocation above
+  mutable std::mutex lock;               // held by every call that uses work, until it completes
 };
 
 namespace ppi {

@@ -439,8 +439,8 @@ __global__ __launch_bounds__(kRunThreads) void k_sweep_ring(
     int l0, int l1, int n, const int32_t *__restrict__ lbeg, const int32_t *__restrict__ lglob,
     const int32_t *__restrict__ row, const int32_t *__restrict__ ecol,
     const int32_t *__restrict__ esrc, const double *__restrict__ eval,
-    const double *__restrict__ diag, const double *__restrict__ zero, const double *rhs,
-    double *out) {
+    const double *__restrict__ diag, const double *__restrict__ zero,
+    const double *__restrict__ rq, double *out) {
   // the last slot is never written: the target of ring loads a row does not need
   __shared__ double ring[kRing * kRunRows + 1];
   constexpr int kNoSlot = kRing * kRunRows;
@@ -466,6 +466,7 @@ __global__ __launch_bounds__(kRunThreads) void k_sweep_ring(
     R.ok = q >= 0;
     const int qc = R.ok ? q : 0;
     R.i = row[qc];
+    R.r = rq[qc];
 #pragma unroll
     for (int s = 0; s < W; ++s) {
       R.c[s] = ecol[(int64_t)s * n + qc];
@@ -474,8 +475,8 @@ __global__ __launch_bounds__(kRunThreads) void k_sweep_ring(
     }
     if constexpr (BACK) R.d = diag[qc];
   };
-  // level l: solve S0, fetch the right-hand side of S1 (level l + 1) and the
-  // entries of level l + 2 into S2
+  // level l: solve S0 and fetch everything of level l + 2 into S2 (the right-hand
+  // side comes in level order, so no load waits for another)
   auto step = [&](int l, RingRow<W> &S0, RingRow<W> &S1, RingRow<W> &S2) {
     const bool glob = __builtin_amdgcn_readfirstlane(s_gf[l - base]) != 0;
     double gg[W], gi[W];
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(kRunThreads) void k_sweep_ring(
     }
 #pragma unroll
     for (int s = 0; s < W; ++s) gi[s] = ring[S0.x[s] >= 0 ? S0.x[s] : kNoSlot];
-    S1.r = *(S1.ok ? rhs + S1.i : zero);
+    (void)S1;
     load(l + 2, S2);
     if (S0.ok) {
       double acc = S0.r;
@@ -507,7 +508,6 @@ __global__ __launch_bounds__(kRunThreads) void k_sweep_ring(
   stage();
   RingRow<W> A, Bv, C;
   load(l0, A);
-  A.r = *(A.ok ? rhs + A.i : zero);
   load(l0 + 1, Bv);
   // levels past l1 are empty (no row), so the loop may run up to two of them
   for (int l = l0; l < l1; l += 3) {
@@ -683,11 +683,24 @@ hipError_t launch_sweep_sources(int n, int width, int nlev, const int32_t *lbeg,
   return hipGetLastError();
 }
 
+namespace {
+__global__ __launch_bounds__(kB) void k_gather_level(int n, const int32_t *__restrict__ row,
+                                                     const double *__restrict__ src,
+                                                     double *__restrict__ dst) {
+  const int q = blockIdx.x * kB + threadIdx.x;
+  if (q < n) dst[q] = src[row[q]];
+}
+}  // namespace
+
+// Whether a sweep runs LDS-ring kernels (they read the right-hand side in level order).
+static bool uses_ring(const Sweep &S) { return S.esrc && S.width <= kRingSlots; }
+
 // The pipelined run for the sweep's slot count (1..kPipeSlots): with the LDS ring
-// when every in-run dependency is recent enough, else on global memory.
+// when every in-run dependency is recent enough (rq: the right-hand side in level
+// order), else on global memory.
 template <bool BACK>
 static void launch_pipe(const Sweep &S, const LevelSpan &sp, int n, const double *rhs,
-                        double *out, hipStream_t stream) {
+                        const double *rq, double *out, hipStream_t stream) {
 #define PP_PIPE(W)                                                                            \
   do {                                                                                        \
     if constexpr (W <= kRingSlots) {                                                          \
@@ -695,7 +708,7 @@ static void launch_pipe(const Sweep &S, const LevelSpan &sp, int n, const double
         hipLaunchKernelGGL((k_sweep_ring<(W <= kRingSlots ? W : 1), BACK>), dim3(1),          \
                            dim3((sp.width + 63) / 64 * 64), 0, stream, sp.l0, sp.l1, n,       \
                            S.lbeg, S.lglob,                                                   \
-                           S.row, S.ecol, S.esrc, S.eval, S.diag, S.zero, rhs, out);          \
+                           S.row, S.ecol, S.esrc, S.eval, S.diag, S.zero, rq, out);           \
         break;                                                                                \
       }                                                                                       \
     }                                                                                         \
@@ -724,11 +737,13 @@ hipError_t launch_sweep_fill(int n, const int32_t *row, const int32_t *rp, const
   return hipGetLastError();
 }
 
-hipError_t launch_ilu_forward(int n, const Sweep &L, const double *r, double *z,
+hipError_t launch_ilu_forward(int n, const Sweep &L, const double *r, double *z, double *work,
                               hipStream_t stream) {
+  if (uses_ring(L))
+    hipLaunchKernelGGL(k_gather_level, dim3(blocks(n)), dim3(kB), 0, stream, n, L.row, r, work);
   for (const LevelSpan &sp : L.spans) {
     if (sp.run && L.ecol) {
-      launch_pipe<false>(L, sp, n, r, z, stream);
+      launch_pipe<false>(L, sp, n, r, work, z, stream);
     } else if (sp.run) {
       hipLaunchKernelGGL(k_forward_run, dim3(1), dim3(kRunThreads), 0, stream, sp.l0, sp.l1,
                          L.lbeg, L.row, L.ptr, L.col, L.val, r, z);
@@ -741,11 +756,13 @@ hipError_t launch_ilu_forward(int n, const Sweep &L, const double *r, double *z,
   return hipGetLastError();
 }
 
-hipError_t launch_ilu_backward(int n, const Sweep &U, const double *z, double *x,
+hipError_t launch_ilu_backward(int n, const Sweep &U, const double *z, double *x, double *work,
                                hipStream_t stream) {
+  if (uses_ring(U))
+    hipLaunchKernelGGL(k_gather_level, dim3(blocks(n)), dim3(kB), 0, stream, n, U.row, z, work);
   for (const LevelSpan &sp : U.spans) {
     if (sp.run && U.ecol) {
-      launch_pipe<true>(U, sp, n, z, x, stream);
+      launch_pipe<true>(U, sp, n, z, work, x, stream);
     } else if (sp.run) {
       hipLaunchKernelGGL(k_backward_run, dim3(1), dim3(kRunThreads), 0, stream, sp.l0, sp.l1,
                          U.lbeg, U.row, U.ptr, U.col, U.val, U.diag, z, x);

@@ -220,6 +220,7 @@ int factor(const pp_csr *A, hipStream_t s, pp_ilu *M) {
   if (hflag) return PP_ERR_SINGULAR;
   ILU_TRY(build_sweep(n, A->row_ptr, A->col_ind, dpos, M->lu, false, M->fwd, own, tmp, s));
   ILU_TRY(build_sweep(n, A->row_ptr, A->col_ind, dpos, M->lu, true, M->bwd, own, tmp, s));
+  ILU_TRY(own.take(&M->work, n));
   ILU_TRY_HIP(hipStreamSynchronize(s));
   M->owned = own.ptrs;
   own.ptrs.clear();
@@ -231,9 +232,9 @@ int factor(const pp_csr *A, hipStream_t s, pp_ilu *M) {
 namespace ppi {
 
 hipError_t ilu_solve(const pp_ilu &M, const double *r, double *z, hipStream_t s) {
-  const hipError_t e = ppk::launch_ilu_forward((int)M.n, M.fwd, r, z, s);
+  const hipError_t e = ppk::launch_ilu_forward((int)M.n, M.fwd, r, z, M.work, s);
   if (e != hipSuccess) return e;
-  return ppk::launch_ilu_backward((int)M.n, M.bwd, z, z, s);
+  return ppk::launch_ilu_backward((int)M.n, M.bwd, z, z, M.work, s);
 }
 
 double ilu_solve_bytes(const pp_ilu &M) {
@@ -269,6 +270,7 @@ int pp_ilu0_factor(const pp_csr *A, void *stream, pp_ilu **out) {
 
 int pp_ilu0_apply(const pp_ilu *M, const double *r, double *z, void *stream) {
   if (!M || !r || !z) return PP_ERR_ARG;
+  std::lock_guard<std::mutex> lk(M->lock);  // M->work, until the sweeps are done
   hipStream_t s = static_cast<hipStream_t>(stream);
   ILU_TRY_HIP(ppi::ilu_solve(*M, r, z, s));
   ILU_TRY_HIP(hipStreamSynchronize(s));
@@ -288,7 +290,11 @@ int pp_ilu0_levels(const pp_ilu *M, int32_t *nlev_forward, int32_t *nlev_backwar
   if (!M) return PP_ERR_ARG;
   if (nlev_forward) *nlev_forward = M->fwd.nlev;
   if (nlev_backward) *nlev_backward = M->bwd.nlev;
-  if (launches) *launches = (int32_t)(M->fwd.spans.size() + M->bwd.spans.size());
+  // the sweeps' spans, plus one level-order gather per sweep that has LDS-ring runs
+  auto gathers = [](const Sweep &S) { return (S.esrc && S.width <= ppk::kRingSlots) ? 1 : 0; };
+  if (launches)
+    *launches = (int32_t)(M->fwd.spans.size() + M->bwd.spans.size() + gathers(M->fwd) +
+                          gathers(M->bwd));
   return PP_OK;
 }
 

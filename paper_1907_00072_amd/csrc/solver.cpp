@@ -1462,6 +1462,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
   }
   std::lock_guard<std::mutex> lk(g_lock);
   Arena *ar = nullptr;
+  std::unique_lock<std::mutex> ilu_lock;
   if (in.o.left_ilu) {
     // Section VI, second example: ILU(0) on the left, the polynomial of M^-1 A on
     // the right; the solve runs on (M^-1 A, M^-1 b)
@@ -1472,6 +1473,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
     PP_TRY(current_arena(&ar));
     PP_TRY(ensure_aux(ar, (size_t)A->n * sizeof(double) + 256));
     double *bs = reinterpret_cast<double *>(ar->aux);
+    ilu_lock = std::unique_lock<std::mutex>(M->lock);  // M->work, for the whole solve
     PP_TRY_HIP(ppi::ilu_solve(*M, b, bs, in.s));
     in.b = bs;
     in.ilu = M;
