@@ -191,3 +191,29 @@ def test_composed_solve_rejects_other_modes(B):
     with pytest.raises(B.PPError) as e:
         B.pp_gmres_solve(Ad, _up(b), m=10, d=3, tol=1e-8, left_ilu=M2)
     assert e.value.code == B.PP_ERR_ARG
+
+
+def test_concurrent_applies_on_one_factor(B):
+    # two host threads, two streams, one pp_ilu: its work vector is taken in turn
+    import threading
+    A, LU, Ad, M = _case(B, "recirc_33")
+    n = A.shape[0]
+    rs = [_up(W.normal(n, 21)), _up(W.normal(n, 22))]
+    refs = [B.pp_ilu0_apply(M, r).clone() for r in rs]
+    outs = [[], []]
+
+    def work(k):
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            for _ in range(20):
+                z = torch.empty_like(rs[k])
+                B.pp_ilu0_apply(M, rs[k], z, stream=st)
+                outs[k].append(z)
+    ts = [threading.Thread(target=work, args=(k,)) for k in (0, 1)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    torch.cuda.synchronize()
+    for k in (0, 1):
+        assert len(outs[k]) == 20 and all(torch.equal(z, refs[k]) for z in outs[k])
