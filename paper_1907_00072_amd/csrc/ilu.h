@@ -12,7 +12,8 @@
 // Levels are found on the device by frontier expansion over the transposed
 // pattern.  A run of consecutive narrow levels (at most kRunRows rows each) goes
 // to one workgroup that steps through them with a barrier between levels; a
-// wide level gets a launch of its own.
+// wide level gets a launch of its own.  Inside a run the solved values of the
+// last kRing levels travel through LDS when every dependency allows it.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -6,8 +6,11 @@
 // The sweeps are bound by the chain of dependent levels, not by bandwidth: each
 // level needs the solved values of earlier levels.  Narrow levels therefore run
 // back to back inside one workgroup (a barrier between levels, no launch between
-// them), pipelined so that a level costs one round of gathers (k_sweep_pipe); a
-// level wider than kRunRows gets its own launch with one thread per row.
+// them); a level wider than kRunRows gets its own launch with one thread per row.
+// Three run kernels, fastest first: k_sweep_ring (solved values passed through an
+// LDS ring, LDS-only barriers, all loads of a level issued two levels ahead),
+// k_sweep_pipe (the same prefetching on global memory), and k_forward_run /
+// k_backward_run (level-ordered CSR, any row length).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
