@@ -334,7 +334,8 @@ int pp_ilu0_factor(const pp_csr *A, void *stream, pp_ilu **out);
 /* z = M^-1 r = U^-1 (L^-1 r): device FP64 vectors of n entries; z may equal r
  * (in place).  Synchronises the stream.  A pp_ilu holds one work vector, so the
  * calls that use it (this one, and solves with it as left_ilu) are serialised on
- * it.  Returns PP_OK, PP_ERR_ARG, PP_ERR_HIP. */
+ * it.  Returns PP_OK, PP_ERR_ARG (also when the current device is not the one M
+ * was made on), PP_ERR_HIP. */
 int pp_ilu0_apply(const pp_ilu *M, const double *r, double *z, void *stream);
 
 /* Copy the factors into lu (device FP64[nnz], A's CSR order): the strictly lower

@@ -147,6 +147,7 @@ hipError_t launch_sub_norm(int n, const double *b, const double *y, double *out,
 // The factor object behind pp_ilu: device arrays owned by it.
 struct pp_ilu {
   int64_t n = 0, nnz = 0;
+  int device = -1;                       // the device its arrays live on
   double *lu = nullptr;                  // factors in A's CSR order
   ppk::Sweep fwd, bwd;
   double *work = nullptr;                // [n] right-hand side in level order
@@ -159,4 +160,6 @@ namespace ppi {
 hipError_t ilu_solve(const pp_ilu &M, const double *r, double *z, hipStream_t s);
 // Algorithmic HBM bytes of one ilu_solve.
 double ilu_solve_bytes(const pp_ilu &M);
+// Whether the current device is the one the factor lives on.
+bool on_device(const pp_ilu &M);
 }  // namespace ppi

@@ -178,12 +178,11 @@ int build_sweep(int n, const int32_t *rp, const int32_t *ci, const int32_t *dpos
   return PP_OK;
 }
 
-int factor(const pp_csr *A, hipStream_t s, pp_ilu *M) {
+int factor_steps(const pp_csr *A, hipStream_t s, pp_ilu *M, Allocs &own, Allocs &tmp) {
   const int n = (int)A->n;
   const int64_t nnz = A->nnz;
   M->n = n;
   M->nnz = nnz;
-  Allocs own, tmp;
   int32_t *dpos, *indeg_l, *indeg_u, *flag, *cnt, *rp_t, *cursor, *rows_t, *scan;
   ILU_TRY(tmp.take(&dpos, n));
   ILU_TRY(tmp.take(&indeg_l, n));
@@ -221,7 +220,15 @@ int factor(const pp_csr *A, hipStream_t s, pp_ilu *M) {
   ILU_TRY(build_sweep(n, A->row_ptr, A->col_ind, dpos, M->lu, false, M->fwd, own, tmp, s));
   ILU_TRY(build_sweep(n, A->row_ptr, A->col_ind, dpos, M->lu, true, M->bwd, own, tmp, s));
   ILU_TRY(own.take(&M->work, n));
-  ILU_TRY_HIP(hipStreamSynchronize(s));
+  return PP_OK;
+}
+
+// The factorisation; on any error the stream is drained before the buffers go.
+int factor(const pp_csr *A, hipStream_t s, pp_ilu *M) {
+  Allocs own, tmp;
+  int rc = factor_steps(A, s, M, own, tmp);
+  if (hipStreamSynchronize(s) != hipSuccess && rc >= 0) rc = PP_ERR_HIP;
+  if (rc < 0) return rc;
   M->owned = own.ptrs;
   own.ptrs.clear();
   return PP_OK;
@@ -235,6 +242,11 @@ hipError_t ilu_solve(const pp_ilu &M, const double *r, double *z, hipStream_t s)
   const hipError_t e = ppk::launch_ilu_forward((int)M.n, M.fwd, r, z, M.work, s);
   if (e != hipSuccess) return e;
   return ppk::launch_ilu_backward((int)M.n, M.bwd, z, z, M.work, s);
+}
+
+bool on_device(const pp_ilu &M) {
+  int dev = -1;
+  return hipGetDevice(&dev) == hipSuccess && dev == M.device;
 }
 
 double ilu_solve_bytes(const pp_ilu &M) {
@@ -258,9 +270,12 @@ int pp_ilu0_factor(const pp_csr *A, void *stream, pp_ilu **out) {
     return PP_ERR_ARG;
   pp_ilu *M = new (std::nothrow) pp_ilu;
   if (!M) return PP_ERR_NOMEM;
+  if (hipGetDevice(&M->device) != hipSuccess) {
+    delete M;
+    return PP_ERR_HIP;
+  }
   const int rc = factor(A, static_cast<hipStream_t>(stream), M);
   if (rc < 0) {
-    (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
     free_ilu(M);
     return rc;
   }
@@ -269,7 +284,7 @@ int pp_ilu0_factor(const pp_csr *A, void *stream, pp_ilu **out) {
 }
 
 int pp_ilu0_apply(const pp_ilu *M, const double *r, double *z, void *stream) {
-  if (!M || !r || !z) return PP_ERR_ARG;
+  if (!M || !r || !z || !ppi::on_device(*M)) return PP_ERR_ARG;
   std::lock_guard<std::mutex> lk(M->lock);  // M->work, until the sweeps are done
   hipStream_t s = static_cast<hipStream_t>(stream);
   ILU_TRY_HIP(ppi::ilu_solve(*M, r, z, s));
@@ -278,7 +293,7 @@ int pp_ilu0_apply(const pp_ilu *M, const double *r, double *z, void *stream) {
 }
 
 int pp_ilu0_values(const pp_ilu *M, double *lu, void *stream) {
-  if (!M || !lu) return PP_ERR_ARG;
+  if (!M || !lu || !ppi::on_device(*M)) return PP_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ILU_TRY_HIP(hipMemcpyAsync(lu, M->lu, M->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
   ILU_TRY_HIP(hipStreamSynchronize(s));

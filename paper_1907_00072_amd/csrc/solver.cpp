@@ -1468,7 +1468,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
     // the right; the solve runs on (M^-1 A, M^-1 b)
     const pp_ilu *M = in.o.left_ilu;
     if (in.o.left_jacobi || in.o.precision != PP_PREC_F64 || in.o.vals_f32 || M->n != A->n ||
-        M->nnz != A->nnz)
+        M->nnz != A->nnz || !ppi::on_device(*M))
       return PP_ERR_ARG;
     PP_TRY(current_arena(&ar));
     PP_TRY(ensure_aux(ar, (size_t)A->n * sizeof(double) + 256));
