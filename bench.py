@@ -330,21 +330,26 @@ def sweep(B, W, torch, dev, steps):
         x = torch.zeros_like(b)
         rec = {"n": P.A.n, "nnz": P.A.nnz, "m": P.m, "tol": P.tol}
 
-        def timed(**kw):
+        def timed(tol=P.tol, **kw):
             with warnings.catch_warnings():
                 warnings.simplefilter("ignore")
                 x.zero_()
-                B.pp_gmres_solve(A, b, x, m=P.m, tol=P.tol, v0=v0, **kw)
+                B.pp_gmres_solve(A, b, x, m=P.m, tol=tol, v0=v0, **kw)
                 torch.cuda.synchronize()
                 ts = time.perf_counter()
                 for _ in range(steps):
                     x.zero_()
-                    _, st = B.pp_gmres_solve(A, b, x, m=P.m, tol=P.tol, v0=v0, **kw)
+                    _, st = B.pp_gmres_solve(A, b, x, m=P.m, tol=tol, v0=v0, **kw)
                 torch.cuda.synchronize()
             return {"time_s": (time.perf_counter() - ts) / steps, "iters": st.iters,
                     "relres": st.relres_true, "layout": st.layout_used}
         for d in P.extra.get("degrees", [P.d]):
             rec[f"pp_d{d}" if d else "gmres"] = timed(d=d)
+        if P.tol < 1e-8:
+            # the metric's time-to-1e-8 on a configuration with a tighter tolerance:
+            # the same solve stopped at 1e-8
+            rec[f"pp_d{P.d}_to_1e-8"] = timed(tol=1e-8, d=P.d)
+            rec["gmres_to_1e-8"] = timed(tol=1e-8, d=0, max_iters=30000)
         if "gmres" not in rec:
             rec["gmres"] = timed(d=0, max_iters=30000)
         if "inner_tol" in P.extra:
