@@ -38,6 +38,9 @@
  *    in pp_gmres_solve, which then holds the last finite iterate).
  *  - Reductions are two-stage in a fixed order without floating-point atomics,
  *    so repeated calls with the same inputs give bitwise-identical results.
+ *  - Tracing: the environment variable PP_LOG=1 prints one line per restart cycle
+ *    (or refinement step) and per ILU(0) factorisation to stderr, PP_LOG=2 also
+ *    every Arnoldi step's implicit residual; unset or 0 prints nothing.
  */
 #ifndef PP_H
 #define PP_H

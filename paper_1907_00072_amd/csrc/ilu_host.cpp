@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -279,6 +281,10 @@ int pp_ilu0_factor(const pp_csr *A, void *stream, pp_ilu **out) {
     free_ilu(M);
     return rc;
   }
+  if (const char *v = std::getenv("PP_LOG"); v && std::atoi(v) >= 1)
+    std::fprintf(stderr, "[pp] ilu0: n %lld, levels %d forward / %d backward, %zu + %zu spans\n",
+                 (long long)M->n, M->fwd.nlev, M->bwd.nlev, M->fwd.spans.size(),
+                 M->bwd.spans.size());
   *out = M;
   return PP_OK;
 }

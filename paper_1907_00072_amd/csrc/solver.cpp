@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -62,6 +63,17 @@ constexpr int kStagnationCycles = 3;
   } while (0)
 
 std::mutex g_lock;
+
+// Tracing to stderr, from the environment variable PP_LOG (read once): 0 (default)
+// silent; 1 one line per restart cycle / refinement step; 2 also every Arnoldi
+// step's implicit residual.
+int log_level() {
+  static const int level = [] {
+    const char *v = std::getenv("PP_LOG");
+    return v ? std::atoi(v) : 0;
+  }();
+  return level;
+}
 
 struct Arena {
   char *dev = nullptr;
@@ -816,6 +828,9 @@ int gmres_cycle(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int
     *res = ls.add(j, hcol.data());
     *k = j + 1;
     cnt.push(*res / bscale);
+    if (log_level() >= 2)
+      std::fprintf(stderr, "[pp] step %d (cycle step %d): implicit relres %.3e\n", cnt.iters,
+                   j + 1, *res / bscale);
     if (!finite(*res)) {
       *nonfinite = true;
       break;
@@ -1261,6 +1276,9 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
     }
     beta = nb;
     relres = beta / bnorm;
+    if (log_level() >= 1)
+      std::fprintf(stderr, "[pp] cycle %d: %d steps, true relres %.3e (implicit %.3e)\n",
+                   cycles, k, relres, relimp);
     // only a cycle whose estimate reached tol counts: one that ran all m steps is
     // converging slowly, not stuck at the rounding floor
     stagnant = (res < in.tol * bnorm && relres < kStagnationBand * in.tol &&
@@ -1373,6 +1391,9 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
     cnt.spmvs++;
     cnt.dots++;
     relres = beta / bnorm;
+    if (log_level() >= 1)
+      std::fprintf(stderr, "[pp] refinement step %d: true relres %.3e, %d inner steps so far\n",
+                   outer, relres, cnt.iters);
     if (!finite(relres)) {
       if (outer > 0) {
         PP_TRY_HIP(hipMemcpyAsync(in.x, xsave, n * sizeof(double), hipMemcpyDeviceToDevice, s));

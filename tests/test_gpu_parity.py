@@ -642,3 +642,25 @@ def test_blocked_chain_with_wide_bandwidth(B):
     x1, s1 = B.pp_gmres_solve(A, _up(W.normal(3000, 14)), chain_group=4, chain_slab_rows=512,
                               **kw)
     assert s1.iters == s0.iters and torch.equal(x0, x1)
+
+
+def test_pp_log_traces_cycles_and_steps(B):
+    # PP_LOG is read once per process: run a tiny solve in a child process
+    import subprocess
+    import sys
+    code = ("import numpy as np, torch\n"
+            "from paper_1907_00072_amd import binding as B, workloads as W\n"
+            "P = W.config(1, N=16)\n"
+            "A = B.CSRMatrix.from_host(P.A)\n"
+            "x, st = B.pp_gmres_solve(A, torch.from_numpy(P.b).cuda(), m=10, d=4, tol=1e-8,\n"
+            "                         v0=torch.from_numpy(P.v0).cuda())\n"
+            "print('iters', st.iters, 'cycles', st.cycles)\n")
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root,
+                       env=dict(os.environ, PP_LOG="2"), timeout=120)
+    assert r.returncode == 0, r.stderr[-1000:]
+    iters = int(r.stdout.split()[1])
+    cycles = int(r.stdout.split()[3])
+    assert r.stderr.count("[pp] cycle") == cycles
+    assert r.stderr.count("implicit relres") >= iters
