@@ -664,3 +664,53 @@ def test_pp_log_traces_cycles_and_steps(B):
     cycles = int(r.stdout.split()[3])
     assert r.stderr.count("[pp] cycle") == cycles
     assert r.stderr.count("implicit relres") >= iters
+
+
+def test_failure_paths(B):
+    P = W.config(1, N=16)
+    n = P.A.n
+    A = B.CSRMatrix.from_host(P.A)
+    b, v0 = _up(P.b), _up(P.v0)
+    for kw in (dict(tol=0.0), dict(tol=-1e-8), dict(d=n + 1), dict(d=257), dict(m=0)):
+        args = dict(m=10, d=4, tol=1e-8, v0=v0)
+        args.update(kw)
+        with pytest.raises(B.PPError) as e:
+            B.pp_gmres_solve(A, b, **args)
+        assert e.value.code == B.PP_ERR_ARG, kw
+    # a polynomial built for another size
+    with pytest.raises(B.PPError) as e:
+        B.pp_gmres_solve(A, b, m=10, tol=1e-8, poly=B.pp_poly_from_roots(n + 1, [2.0, 3.0]))
+    assert e.value.code == B.PP_ERR_ARG
+    # zero start vector: no Krylov space to build the polynomial from
+    with pytest.raises(B.PPError) as e:
+        B.pp_build_poly(A, torch.zeros_like(v0), 4)
+    assert e.value.code == B.PP_ERR_SINGULAR
+    # b = 0: x = 0 at once
+    x, st = B.pp_gmres_solve(A, torch.zeros_like(b), m=10, d=4, tol=1e-8, v0=v0)
+    assert st.status == B.PP_OK and st.iters == 0 and not torch.any(x)
+    # NaN in A's values: never reported as a success
+    vals = P.A.vals.copy()
+    vals[7] = np.nan
+    An = B.CSRMatrix.from_host(W.CSR(n, P.A.row_ptr, P.A.col_ind, vals))
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        try:
+            _, st = B.pp_gmres_solve(An, b, m=10, d=4, tol=1e-8, v0=v0)
+            assert st.status == B.PP_WARN_NONFINITE
+        except B.PPError as err:
+            assert err.code in (B.PP_ERR_SINGULAR, B.PP_ERR_ARG)
+
+
+def test_arnoldi_breakdown_reduces_the_degree(B):
+    # v0 an eigenvector of a diagonal matrix: the Krylov space is one-dimensional
+    n = 50
+    dg = np.linspace(1.0, 5.0, n)
+    Ah = W.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), dg)
+    A = B.CSRMatrix.from_host(Ah)
+    e3 = np.zeros(n)
+    e3[3] = 1.0
+    with pytest.warns(B.PPWarning):
+        p = B.pp_build_poly(A, _up(e3), 6)
+    roots = p.roots()
+    assert roots.size == 1 and abs(roots[0] - dg[3]) <= 1e-13 * dg[3]
