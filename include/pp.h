@@ -37,7 +37,13 @@
  *    < 0 = error, outputs are unspecified (inputs are never modified, except x
  *    in pp_gmres_solve, which then holds the last finite iterate).
  *  - Reductions are two-stage in a fixed order without floating-point atomics,
- *    so repeated calls with the same inputs give bitwise-identical results.
+ *    so repeated calls with the same inputs give bitwise-identical results.  With
+ *    PP_LAYOUT_AUTO, calls that run different numbers of products (a separate
+ *    pp_build_poly and a solve) may pick different layouts and so round
+ *    differently; fix pp_csr.layout when their results must agree bit for bit.
+ *  - Checkpoint / resume: a solve interrupted at a restart-cycle boundary
+ *    (max_iters a multiple of m) resumes exactly from the saved x (as x0) and the
+ *    polynomial rebuilt from pp_poly_roots by pp_poly_from_roots.
  *  - Tracing: the environment variable PP_LOG=1 prints one line per restart cycle
  *    (or refinement step) and per ILU(0) factorisation to stderr, PP_LOG=2 also
  *    every Arnoldi step's implicit residual; unset or 0 prints nothing.

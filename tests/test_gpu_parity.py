@@ -714,3 +714,30 @@ def test_arnoldi_breakdown_reduces_the_degree(B):
         p = B.pp_build_poly(A, _up(e3), 6)
     roots = p.roots()
     assert roots.size == 1 and abs(roots[0] - dg[3]) <= 1e-13 * dg[3]
+
+
+def test_checkpoint_and_resume_is_exact(B):
+    # a solve interrupted at a cycle boundary and resumed from (x, roots) ends with
+    # the same bits as the uninterrupted solve.  The layout is fixed: with "auto" a
+    # separate pp_build_poly (only d products) may keep CSR where the solve takes
+    # the sliced copy, and the two sum the products in different orders.
+    import warnings
+    P = W.config(1, N=32)
+    A = B.CSRMatrix.from_host(P.A, layout="sell")
+    b, v0 = _up(P.b), _up(P.v0)
+    m, d = 10, 4
+    x_full, s_full = B.pp_gmres_solve(A, b, m=m, d=d, tol=1e-10, v0=v0)
+    assert s_full.relres_true < 1e-10 and s_full.cycles >= 3
+    p = B.pp_build_poly(A, v0, d)
+    roots = p.roots()
+    k = 2 * m  # two complete cycles
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        x_part, s_part = B.pp_gmres_solve(A, b, m=m, tol=1e-10, poly=p, max_iters=k)
+    assert s_part.status == B.PP_WARN_NOT_CONVERGED and s_part.iters == k
+    saved_x = x_part.cpu().numpy().copy()
+    resumed = B.pp_poly_from_roots(P.A.n, roots)
+    x_res, s_res = B.pp_gmres_solve(A, b, _up(saved_x), m=m, tol=1e-10, poly=resumed)
+    assert s_res.relres_true < 1e-10
+    assert s_part.iters + s_res.iters == s_full.iters
+    assert torch.equal(x_res, x_full)
