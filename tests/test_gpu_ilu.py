@@ -179,6 +179,18 @@ def test_composed_solve_product_form_and_determinism(B):
     assert _rel(x3.cpu().numpy(), x1.cpu().numpy()) <= 1e-5
 
 
+def test_chain_schedule_is_ignored_with_ilu(B):
+    # M^-1 couples all rows, so the slab-skewed chain schedule does not apply
+    A, b = W.recirculating_flow(33)
+    Ad = B.CSRMatrix.from_host(A)
+    M = B.pp_ilu0_factor(Ad)
+    v0 = _up(W.uniform(A.n, 106))
+    x0, s0 = B.pp_gmres_solve(Ad, _up(b), m=50, d=8, tol=1e-8, v0=v0, left_ilu=M)
+    x1, s1 = B.pp_gmres_solve(Ad, _up(b), m=50, d=8, tol=1e-8, v0=v0, left_ilu=M,
+                              chain_group=4, chain_slab_rows=256)
+    assert s1.iters == s0.iters and torch.equal(x0, x1)
+
+
 def test_composed_solve_rejects_other_modes(B):
     A, b = W.recirculating_flow(9)
     Ad = B.CSRMatrix.from_host(A)

@@ -633,6 +633,18 @@ def test_blocked_chain_gives_identical_results(B, group, slab, precision):
     assert s1.iters == s0.iters and torch.equal(x0, x1)
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32_ir"])
+def test_blocked_chain_on_the_csr_layout(B, precision):
+    # CSR products tile by 256 rows in both precisions
+    P = W.config(2, N=24)
+    A = B.CSRMatrix.from_host(P.A, layout="csr")
+    kw = dict(m=20, d=8, tol=1e-10, v0=_up(P.v0), precision=precision)
+    x0, s0 = B.pp_gmres_solve(A, _up(P.b), **kw)
+    x1, s1 = B.pp_gmres_solve(A, _up(P.b), chain_group=3, chain_slab_rows=1500, **kw)
+    assert s0.layout_used == s1.layout_used == "csr"
+    assert s1.iters == s0.iters and torch.equal(x0, x1)
+
+
 def test_blocked_chain_with_wide_bandwidth(B):
     # bandwidth about n: each launch trails the previous by more than a slab
     Ah = W.random_csr(3000, 6, seed=12, diag_shift=8.0)
