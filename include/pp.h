@@ -348,11 +348,14 @@ int pp_ilu0_factor(const pp_csr *A, void *stream, pp_ilu **out);
 int pp_ilu0_apply(const pp_ilu *M, const double *r, double *z, void *stream);
 
 /* Copy the factors into lu (device FP64[nnz], A's CSR order): the strictly lower
- * entries hold L (its unit diagonal implied), the others U.  Synchronises. */
+ * entries hold L (its unit diagonal implied), the others U.  Synchronises.
+ * Returns PP_OK, PP_ERR_ARG (null pointer, or M made on another device),
+ * PP_ERR_HIP. */
 int pp_ilu0_values(const pp_ilu *M, double *lu, void *stream);
 
 /* Levels of the forward and backward sweeps, and the launches one pp_ilu0_apply
- * makes (any pointer may be NULL).  Host only. */
+ * makes (any output pointer may be NULL).  Host only.  Returns PP_OK, or
+ * PP_ERR_ARG when M is NULL. */
 int pp_ilu0_levels(const pp_ilu *M, int32_t *nlev_forward, int32_t *nlev_backward,
                    int32_t *launches);
 
