@@ -21,12 +21,21 @@ diagonal: values plus a 64-byte descriptor per slice, no column indices; 0.11% p
 this stencil); the copy is part of every timed solve.  The `csr` leg times the
 same solve on the caller's CSR arrays.
 
+The chain's launches follow the library's automatic schedule: at this size a
+launch's working set (73 B a row) is far beyond the 256 MiB Infinity Cache, so
+each Arnoldi step's launches run in the slab-skewed order (Section VII) over
+3.1M-row slabs with cached loads, every slab's matrix read from HBM once and
+re-read from the cache by the following launches.  The `fullrange` leg times
+the same solve with full-range, non-temporal launches (identical results).
+
 roofline: the fused product + root-update chain kernel dominates (39 of every
 40 products).  Its achieved bandwidth is the algorithmic bytes of the
 event-timed chain launches (8 nnz_stored + n bytes of matrix: the values and
 one 64-byte descriptor per 64-row slice; plus 16 n of vectors for a middle
 real-root step) over their event-timed duration, both accumulated by the
-library over the timed solves.
+library over the timed solves; a launch is one kernel launch (one slab's part
+of a product under the slab-skewed schedule).  With the cache re-reads this
+rate can exceed what HBM alone delivers.
 
 cpu_baseline: the CPU oracle (NumPy/SciPy, complex-arithmetic product form) on
 a bounded sample of the same solve (one p(A)v with the GPU's roots, one product,
@@ -60,8 +69,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=256, help="grid points per axis (256 = headline)")
-    ap.add_argument("--legs", default="ir,plain,power,csr,jacobi,blocked,ilu,adjoint",
-                    help="comma list of extra legs: ir, plain, power, csr, jacobi, blocked, ilu, "
+    ap.add_argument("--legs", default="ir,plain,power,csr,jacobi,fullrange,ilu,adjoint",
+                    help="comma list of extra legs: ir, plain, power, csr, jacobi, fullrange, ilu, "
                          "adjoint, none")
     ap.add_argument("--plain-max-iters", type=int, default=30000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -147,10 +156,11 @@ def main():
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(chain_gbps / HBM_PEAK_GBPS, 4) if chain_gbps else None,
-        "traffic": pmc_traffic(args.grid),
+        "traffic": pmc_traffic(args.grid, bc / nl if nl else None),
         "bytes_per_launch": bc / nl if nl else None,
         "avg_launch_us": tc / nl * 1e6 if nl else None,
         "launches": nl,
+        "schedule": {"slab_rows": st.chain_slab_rows, "cached": st.chain_cached},
     }
     phases = {
         "chain_GBps": chain_gbps,
@@ -230,20 +240,21 @@ def main():
                                        "relres_original": s6.relres_original}
         log(f"left jacobi: {tj:.3f}s iters {s6.iters} relres {s6.relres_original:.2e}")
 
-    if "blocked" in wanted:
-        # the matrix-powers style schedule (Section VII): the chain's launches two at a
-        # time over 4M-row slabs, each trailing by the bandwidth; identical results
-        kwb = dict(chain_group=2, chain_slab_rows=1 << 22)
+    if "fullrange" in wanted:
+        # the chain without Section VII's reuse: every launch over all rows, with
+        # non-temporal loads and stores; identical results
+        kwb = dict(chain_group=1)
         solve(**kwb)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         s7 = solve(**kwb)
         torch.cuda.synchronize()
         tb = time.perf_counter() - ts
-        legs["pp_fp64_chain_blocked"] = {"time_s": tb, "iters": s7.iters,
-                                         "relres": s7.relres_true, **kwb,
-                                         "same_x_as_default": bool(torch.equal(x, x_default))}
-        log(f"blocked chain (group 2, 4M-row slabs): {tb:.3f}s iters {s7.iters}")
+        legs["pp_fp64_chain_fullrange"] = {
+            "time_s": tb, "iters": s7.iters, "relres": s7.relres_true, **kwb,
+            "chain_GBps": s7.bytes_chain / s7.t_chain / 1e9 if s7.t_chain > 0 else None,
+            "same_x_as_default": bool(torch.equal(x, x_default))}
+        log(f"full-range non-temporal chain: {tb:.3f}s iters {s7.iters}")
 
     if "ilu" in wanted:
         legs["ilu0_left_recirc_257"] = ilu_leg(B, W, torch, dev)
@@ -541,13 +552,16 @@ def kernels_code_hash():
     return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
-def pmc_traffic(grid):
-    """HBM bytes per middle chain launch from the committed rocprofv3 counter runs.
+def pmc_traffic(grid, bytes_per_launch):
+    """L2-miss bytes per chain launch from the committed rocprofv3 counter runs:
+    the dominant kernel's FETCH_SIZE + WRITE_SIZE per row over its algorithmic
+    bytes per row (the launches are slabs of different sizes), times this run's
+    algorithmic bytes per launch.
 
     Only reported while kernels.hip's code is what those counters were taken
     from (kernels_code_hash is recorded with them); otherwise None.
     """
-    if grid != 256:
+    if grid != 256 or not bytes_per_launch:
         return None
     path = os.path.join(ROOT, "profiles", "k_chain_cd3d_256_pe100_traffic.json")
     try:
@@ -555,7 +569,9 @@ def pmc_traffic(grid):
         sha = kernels_code_hash()
     except OSError:
         return None
-    return rec["traffic_bytes_per_dispatch"] if rec.get("kernels_code_sha256_16") == sha else None
+    if rec.get("kernels_code_sha256_16") != sha:
+        return None
+    return rec["traffic_ratio"] * bytes_per_launch
 
 
 def torch_copy_rate(torch, nbytes=2 << 30, reps=5):

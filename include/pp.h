@@ -161,16 +161,27 @@ typedef struct pp_opts {
                              x = p(M^-1 A) y, the polynomial is built for M^-1 A, and the
                              solve stops on ||M^-1 (b - A x)|| / ||M^-1 b|| < tol.  FP64
                              only; not together with left_jacobi or F32_IR (PP_ERR_ARG). */
-  int32_t chain_group;    /* >= 2: run each Arnoldi step's chain (operator form) in a
-                             slab-skewed order, chain_group launches at a time over row
-                             slabs of chain_slab_rows rows, each launch one matrix
-                             bandwidth behind the previous (a matrix-powers style schedule,
-                             Section VII): a slab's matrix and vectors are read chain_group
-                             times in a row while they may still be cached.  Results are
-                             bit-identical to the default.  0 or 1: full-range launches.
-                             Ignored with left_ilu (M^-1 couples all rows). */
+  int32_t chain_group;    /* Schedule of each Arnoldi step's chain (operator form); every
+                             choice gives bit-identical results.  Section VII's reuse of
+                             the matrix across products: a launch's working set is its
+                             matrix rows plus two vectors (73 B a row for a 7-point
+                             stencil in FP64, 37 B in FP32), against a budget of 216 MiB
+                             of MI355X's 256 MiB Infinity Cache.
+                             0 (automatic): if the working set fits the budget, full-range
+                               launches with cached loads and stores; else the slab-skewed
+                               order below over all of a step's launches with slabs that
+                               fit the budget, when the matrix bandwidth is at most 1/8 of
+                               a slab; else full-range non-temporal launches.
+                             1: full-range launches, non-temporal loads and stores.
+                             >= 2: the slab-skewed order, chain_group launches at a time
+                               over row slabs of chain_slab_rows rows, each launch one
+                               matrix bandwidth behind the previous: a slab's matrix and
+                               vectors are read chain_group times in a row while cached.
+                             Negative: PP_ERR_ARG.  Ignored with left_ilu (M^-1 couples all
+                             rows).  pp_stats reports the choice. */
   int32_t chain_slab_rows; /* rows per slab (rounded down to whole launch tiles, at least
-                              one); 0 -> 2^21 */
+                              one); 0 -> the budget over the working set per row.
+                              Negative: PP_ERR_ARG */
 } pp_opts;
 
 /* Solve statistics (all counts follow Section III: a dot is one block inner
@@ -214,6 +225,10 @@ typedef struct pp_stats {
   int32_t layout_used;     /* PP_LAYOUT_CSR or PP_LAYOUT_SELL: what the products ran on */
   int64_t nnz_stored;      /* values one product streams: nnz (CSR) or the sliced copy's
                               stored values, padding included */
+  int32_t chain_slab_rows; /* the chain schedule used (the inner solve's with F32_IR): rows
+                              per slab of the slab-skewed order, 0 = full-range launches */
+  int32_t chain_cached;    /* 1: the chain's launches load and store through the caches;
+                              0: non-temporal (see pp_opts.chain_group) */
 } pp_stats;
 
 /* Build the polynomial for (A, v0) with d roots.

@@ -60,7 +60,8 @@ class pp_stats(ctypes.Structure):
                 ("t_host", ctypes.c_double), ("bytes_chain", ctypes.c_double),
                 ("bytes_spmv", ctypes.c_double), ("bytes_orth", ctypes.c_double),
                 ("launches_chain", ctypes.c_int64), ("relres_original", ctypes.c_double),
-                ("layout_used", ctypes.c_int32), ("nnz_stored", ctypes.c_int64)]
+                ("layout_used", ctypes.c_int32), ("nnz_stored", ctypes.c_int64),
+                ("chain_slab_rows", ctypes.c_int32), ("chain_cached", ctypes.c_int32)]
 
 
 _lib = None
@@ -383,6 +384,8 @@ class Stats:
     history: Optional[np.ndarray] = None
     layout_used: str = ""
     nnz_stored: int = 0
+    chain_slab_rows: int = 0  # slab-skewed chain schedule's slab rows (0: full-range)
+    chain_cached: bool = False  # chain launches through the caches
 
 
 def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float = 1e-8,
@@ -396,8 +399,8 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
     ``op_form``: "pi" applies A p(A) v as v - pi(A) v (default), "p" as A (p(A) v).
     ``left_ilu``: an ILU(0) of A (pp_ilu0_factor) applied on the left, the
     polynomial built for M^-1 A on the right.
-    ``chain_group`` >= 2: the slab-skewed chain schedule (pp_opts.chain_group), over
-    slabs of ``chain_slab_rows`` rows.
+    ``chain_group``: the chain's schedule (pp_opts.chain_group): 0 automatic, 1
+    full-range non-temporal, >= 2 slab-skewed over slabs of ``chain_slab_rows`` rows.
     """
     torch = _torch()
     _dev_vec(b, torch.float64, A.n, "b")
@@ -439,7 +442,7 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
               st.launches_chain, st.relres_original,
               hist[: st.history_len].copy() if hist is not None else None,
               {PP_LAYOUT_CSR: "csr", PP_LAYOUT_SELL: "sell"}.get(st.layout_used, ""),
-              st.nnz_stored)
+              st.nnz_stored, st.chain_slab_rows, bool(st.chain_cached))
     return x, s
 
 

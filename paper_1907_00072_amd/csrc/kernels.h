@@ -71,6 +71,10 @@ struct ChainArgs {
   const double *yscale;  // scale of y_in in the operator form's last step (nullptr = 1)
   int tile0 = 0;         // first tile (chain_tile_rows rows each) the launch covers
   int ntiles = 0;        // tiles it covers (0 = through the last row)
+  // host-side choice of the cache policy for kinds 2 and 3 without fold: false =
+  // non-temporal loads and stores of A and the vectors (a pass that touches each
+  // once), true = ordinary ones (the next launch re-reads them soon)
+  bool cached = false;
 };
 
 // Rows of one tile of the product launches (one workgroup): 256, or 512 for FP32
@@ -91,10 +95,10 @@ hipError_t launch_axpy(int n, double c, const T *g, const double *gscale, const 
                        hipStream_t stream);
 
 // out = A * (gscale * g), on the rows of tiles [tile0, tile0 + ntiles) (ntiles = 0:
-// through the last row).
+// through the last row); `cached` as ChainArgs::cached.
 template <typename T>
 hipError_t launch_spmv(const SpMat<T> &A, const T *g, const double *gscale, T *out,
-                       hipStream_t stream, int tile0 = 0, int ntiles = 0);
+                       hipStream_t stream, int tile0 = 0, int ntiles = 0, bool cached = false);
 
 // *out = max over stored entries of |column - row| (the matrix bandwidth); *out
 // zeroed by the caller.

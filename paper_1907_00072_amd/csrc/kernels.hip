@@ -85,11 +85,25 @@ template <typename T>
 __device__ __forceinline__ void stnt(T v, T *p) {
   __builtin_nontemporal_store(v, p);
 }
+// The product kernels' streamed operands (A and the vectors of one pass):
+// non-temporal by default, since a full-range pass touches each once; ordinary
+// loads and stores under KEEP, for launches whose data the next launch re-reads
+// while it may still sit in the L2 and the Infinity Cache.
+template <bool KEEP, typename T>
+__device__ __forceinline__ T ld_pass(const T *p) {
+  if constexpr (KEEP) return *p;
+  else return __builtin_nontemporal_load(p);
+}
+template <bool KEEP, typename T>
+__device__ __forceinline__ void st_pass(T v, T *p) {
+  if constexpr (KEEP) *p = v;
+  else __builtin_nontemporal_store(v, p);
+}
 
 // Row sums of A * g for the tile [r0, r0 + nrows) (thread t -> row r0 + t).
 // All threads of the workgroup must call it; rows past the tile return 0.
 // rb/re are the calling thread's row bounds (0, 0 for threads past the tile).
-template <typename T>
+template <typename T, bool KEEP = false>
 __device__ __forceinline__ T tile_row_sum(const SpMat<T> &A, const T *__restrict__ g, int r0,
                                           int nrows, int rb, int re, T *s_buf) {
   constexpr int CAP = LdsCap<T>::value;
@@ -105,8 +119,8 @@ __device__ __forceinline__ T tile_row_sum(const SpMat<T> &A, const T *__restrict
     for (int q = 0; q < PER; ++q) {
       const int k = c0 + q * kBlock + t;
       if (k < c1) {
-        vals[q] = ldnt(A.va + k);
-        cols[q] = ldnt(A.ci + k);
+        vals[q] = ld_pass<KEEP>(A.va + k);
+        cols[q] = ld_pass<KEEP>(A.ci + k);
       }
     }
 #pragma unroll
@@ -135,13 +149,13 @@ __device__ __forceinline__ void desc_barrier(const int *d) {
 // One batch of N slots of a diagonal slice: values at sva + 64 q, diagonal
 // offsets o[q]; the shifted loads are unconditional and kept in range, and an
 // absent entry (value 0) selects 0, so it never reaches the product.
-template <typename T, int N>
+template <typename T, int N, bool KEEP = false>
 __device__ __forceinline__ T dia_batch(const T *__restrict__ sva, const T *__restrict__ g, int row,
                                        int last, const int *o, T acc) {
   T v[N], gl[N];
 #pragma unroll
   for (int q = 0; q < N; ++q) {
-    v[q] = ldnt(sva + q * kSlice);
+    v[q] = ld_pass<KEEP>(sva + q * kSlice);
     // column in unsigned arithmetic: a present entry's column lies in [0, n); for an
     // absent one the sum may fall outside (or wrap) and is clamped to row n - 1
     const unsigned col = (unsigned)row + (unsigned)o[q];
@@ -153,15 +167,15 @@ __device__ __forceinline__ T dia_batch(const T *__restrict__ sva, const T *__res
 }
 
 // One batch of N slots of an explicit-column slice (padding: column -1).
-template <typename T, int N>
+template <typename T, int N, bool KEEP = false>
 __device__ __forceinline__ T ell_batch(const T *__restrict__ sva, const int32_t *__restrict__ sci,
                                        const T *__restrict__ g, T acc) {
   int c[N];
   T v[N], gv[N];
 #pragma unroll
   for (int q = 0; q < N; ++q) {
-    v[q] = ldnt(sva + q * kSlice);
-    c[q] = ldnt(sci + q * kSlice);
+    v[q] = ld_pass<KEEP>(sva + q * kSlice);
+    c[q] = ld_pass<KEEP>(sci + q * kSlice);
   }
 #pragma unroll
   for (int q = 0; q < N; ++q) gv[q] = c[q] >= 0 ? g[c[q]] : T(0);
@@ -174,7 +188,7 @@ __device__ __forceinline__ T ell_batch(const T *__restrict__ sva, const int32_t 
 // wavefront -> the 64 rows of one slice).  Rows past n return 0.  Slot counts
 // are uniform across the wavefront, so each batch of up to kSellBatch slots
 // runs a specialisation whose loads are all issued before any is used.
-template <typename T>
+template <typename T, bool KEEP = false>
 __device__ __forceinline__ T sell_row_sum(const SpMat<T> &A, const T *__restrict__ g, int row) {
   // the slice is uniform across the wavefront (tiles are 64-row aligned); saying
   // so puts the slice metadata in scalar registers and makes the branches uniform
@@ -207,7 +221,7 @@ __device__ __forceinline__ T sell_row_sum(const SpMat<T> &A, const T *__restrict
       }
 #define PP_DIA(N)                                         \
   case N:                                                 \
-    acc = dia_batch<T, N>(sv, g, row, last, o, acc);      \
+    acc = dia_batch<T, N, KEEP>(sv, g, row, last, o, acc);\
     break;
       switch (cnt) { PP_DIA(8) PP_DIA(7) PP_DIA(6) PP_DIA(5) PP_DIA(4) PP_DIA(3) PP_DIA(2) PP_DIA(1) }
 #undef PP_DIA
@@ -215,7 +229,7 @@ __device__ __forceinline__ T sell_row_sum(const SpMat<T> &A, const T *__restrict
       const int32_t *sc = A.sci + base + j0 * kSlice + lane;
 #define PP_ELL(N)                                         \
   case N:                                                 \
-    acc = ell_batch<T, N>(sv, sc, g, acc);                \
+    acc = ell_batch<T, N, KEEP>(sv, sc, g, acc);          \
     break;
       switch (cnt) { PP_ELL(8) PP_ELL(7) PP_ELL(6) PP_ELL(5) PP_ELL(4) PP_ELL(3) PP_ELL(2) PP_ELL(1) }
 #undef PP_ELL
@@ -228,7 +242,7 @@ __device__ __forceinline__ T sell_row_sum(const SpMat<T> &A, const T *__restrict
 // loads of both slices in flight together when both are diagonal slices of at
 // most kSellBatch slots (a slice past n counts as an empty diagonal slice);
 // otherwise one slice after the other.
-template <typename T>
+template <typename T, bool KEEP = false>
 __device__ __forceinline__ void sell_row_sum2(const SpMat<T> &A, const T *__restrict__ g,
                                               int rowA, int rowB, T *accA, T *accB) {
   const int sA = __builtin_amdgcn_readfirstlane(rowA / kSlice);
@@ -256,8 +270,8 @@ __device__ __forceinline__ void sell_row_sum2(const SpMat<T> &A, const T *__rest
   const int baseA = ddA[0], wA = inA ? ddA[1] : 0, dA = inA ? ddA[2] : 1;
   const int baseB = ddB[0], wB = inB ? ddB[1] : 0, dB = inB ? ddB[2] : 1;
   if (!(dA && dB && wA <= kSellBatch && wB <= kSellBatch)) {
-    *accA = inA ? sell_row_sum(A, g, rowA) : T(0);
-    *accB = inB ? sell_row_sum(A, g, rowB) : T(0);
+    *accA = inA ? sell_row_sum<T, KEEP>(A, g, rowA) : T(0);
+    *accB = inB ? sell_row_sum<T, KEEP>(A, g, rowB) : T(0);
     return;
   }
   const int laneA = rowA - sA * kSlice, laneB = rowB - sB * kSlice;
@@ -267,11 +281,11 @@ __device__ __forceinline__ void sell_row_sum2(const SpMat<T> &A, const T *__rest
   for (int q = 0; q < kSellBatch; ++q) {
     vA[q] = gA[q] = vB[q] = gB[q] = T(0);
     if (q < wA) {  // uniform branches
-      vA[q] = ldnt(A.sva + baseA + q * kSlice + laneA);
+      vA[q] = ld_pass<KEEP>(A.sva + baseA + q * kSlice + laneA);
       gA[q] = g[min((unsigned)rowA + (unsigned)oA[q], last)];
     }
     if (q < wB) {
-      vB[q] = ldnt(A.sva + baseB + q * kSlice + laneB);
+      vB[q] = ld_pass<KEEP>(A.sva + baseB + q * kSlice + laneB);
       gB[q] = g[min((unsigned)rowB + (unsigned)oB[q], last)];
     }
   }
@@ -298,20 +312,20 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 
 // Row sum of A * g for the calling thread's row r0 + threadIdx.x from the view's
 // layout.  All threads of the workgroup must call it.
-template <typename T, bool SELL>
+template <typename T, bool SELL, bool KEEP = false>
 __device__ __forceinline__ T row_product(const SpMat<T> &A, const T *__restrict__ g, int r0,
                                          int nrows, int rb, int re) {
   if constexpr (SELL) {
-    return sell_row_sum(A, g, r0 + (int)threadIdx.x);
+    return sell_row_sum<T, KEEP>(A, g, r0 + (int)threadIdx.x);
   } else {
     __shared__ T s_buf[LdsCap<T>::value];
-    return tile_row_sum(A, g, r0, nrows, rb, re, s_buf);
+    return tile_row_sum<T, KEEP>(A, g, r0, nrows, rb, re, s_buf);
   }
 }
 
 // ------------------------------------------------------------------ chain
 // Epilogue of one chain row (see ChainArgs for the kinds): acc = (A g)(i).
-template <typename T, int KIND, bool FOLD, bool LAST>
+template <typename T, int KIND, bool FOLD, bool LAST, bool KEEP = false>
 __device__ __forceinline__ void chain_row(const ChainArgs<T> &a, int i, T acc, T own, T yv, T sf,
                                           T gs) {
   const T c1 = (T)a.c1, c2 = (T)a.c2, cf = (T)a.cf;
@@ -323,42 +337,42 @@ __device__ __forceinline__ void chain_row(const ChainArgs<T> &a, int i, T acc, T
     if constexpr (FOLD) {
       y += cf * pn;
     } else {
-      stnt(pn, a.out + i);
+      st_pass<KEEP>(pn, a.out + i);
     }
-    stnt(y, a.y_out + i);
+    st_pass<KEEP>(y, a.y_out + i);
   } else if constexpr (KIND == 1) {
     const T p = gs * own;
     const T tt = gs * acc;
-    stnt(yv + c1 * p - c2 * tt, a.y_out + i);
-    if constexpr (!LAST) stnt(tt, a.out + i);
+    st_pass<KEEP>(yv + c1 * p - c2 * tt, a.y_out + i);
+    if constexpr (!LAST) st_pass<KEEP>(tt, a.out + i);
   } else if constexpr (KIND == 2) {
     const T ss = a.sscale ? (T)(*a.sscale) : T(1);
     const T pn = ss * sf - c1 * (gs * own) + c2 * (gs * acc);
     if constexpr (FOLD) {
-      stnt(yv + cf * pn, a.y_out + i);
+      st_pass<KEEP>(yv + cf * pn, a.y_out + i);
     } else if constexpr (LAST) {
       const T ys = a.yscale ? (T)(*a.yscale) : T(1);
-      stnt(ys * yv - pn, a.out + i);
+      st_pass<KEEP>(ys * yv - pn, a.out + i);
     } else {
-      stnt(pn, a.out + i);
+      st_pass<KEEP>(pn, a.out + i);
     }
   } else if constexpr (KIND == 4) {
     const T ss = a.sscale ? (T)(*a.sscale) : T(1);
-    stnt(c2 * (gs * acc) + c1 * (ss * sf), a.out + i);
+    st_pass<KEEP>(c2 * (gs * acc) + c1 * (ss * sf), a.out + i);
   } else {
     const T pn = gs * own - c1 * (gs * acc);
     if constexpr (LAST) {
       const T ys = a.yscale ? (T)(*a.yscale) : T(1);
-      stnt(ys * yv - pn, a.out + i);
+      st_pass<KEEP>(ys * yv - pn, a.out + i);
     } else {
-      stnt(pn, a.out + i);
+      st_pass<KEEP>(pn, a.out + i);
     }
   }
 }
 
 // R rows per thread: rows r0 + t + 256 r of a tile of 256 R rows (R = 2 only on
 // the sliced copy, where it lets a wavefront keep two slices' loads in flight).
-template <typename T, int KIND, bool FOLD, bool LAST, bool SELL, int R>
+template <typename T, int KIND, bool FOLD, bool LAST, bool SELL, int R, bool KEEP = false>
 __global__ __launch_bounds__(kBlock) void k_chain(SpMat<T> A, ChainArgs<T> a) {
   static_assert(R == 1 || (R == 2 && SELL), "two rows per thread need the sliced copy");
   const int r0 = (a.tile0 + xcd_tile(blockIdx.x, gridDim.x)) * kBlock * R;
@@ -379,27 +393,27 @@ __global__ __launch_bounds__(kBlock) void k_chain(SpMat<T> A, ChainArgs<T> a) {
         re = A.rp[i + 1];
       }
       own[r] = a.g[i];
-      if (kReadY) yv[r] = a.y_in ? ldnt(a.y_in + i) : T(0);
-      if (kReadSelf) sf[r] = ldnt(a.self + i);
+      if (kReadY) yv[r] = a.y_in ? ld_pass<KEEP>(a.y_in + i) : T(0);
+      if (kReadSelf) sf[r] = ld_pass<KEEP>(a.self + i);
     }
   }
   T acc[R];
   if constexpr (R == 1) {
-    acc[0] = row_product<T, SELL>(A, a.g, r0, min(kBlock, A.n - r0), rb, re);
+    acc[0] = row_product<T, SELL, KEEP>(A, a.g, r0, min(kBlock, A.n - r0), rb, re);
   } else {
-    sell_row_sum2(A, a.g, r0 + t, r0 + kBlock + t, &acc[0], &acc[1]);
+    sell_row_sum2<T, KEEP>(A, a.g, r0 + t, r0 + kBlock + t, &acc[0], &acc[1]);
   }
   // read after the product's loads are issued, so its latency is not on their path
   const T gs = a.gscale ? (T)(*a.gscale) : T(1);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = r0 + r * kBlock + t;
-    if (i < A.n) chain_row<T, KIND, FOLD, LAST>(a, i, acc[r], own[r], yv[r], sf[r], gs);
+    if (i < A.n) chain_row<T, KIND, FOLD, LAST, KEEP>(a, i, acc[r], own[r], yv[r], sf[r], gs);
   }
 }
 
 // R rows per thread as in k_chain (R = 2 only on the sliced copy).
-template <typename T, bool SELL, int R>
+template <typename T, bool SELL, int R, bool KEEP = false>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpMat<T> A, const T *__restrict__ g,
                                                  const double *gscale, T *__restrict__ out,
                                                  int tile0) {
@@ -416,15 +430,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpMat<T> A, const T *__restrict
         re = A.rp[r0 + t + 1];
       }
     }
-    acc[0] = row_product<T, SELL>(A, g, r0, nrows, rb, re);
+    acc[0] = row_product<T, SELL, KEEP>(A, g, r0, nrows, rb, re);
   } else {
-    sell_row_sum2(A, g, r0 + t, r0 + kBlock + t, &acc[0], &acc[1]);
+    sell_row_sum2<T, KEEP>(A, g, r0 + t, r0 + kBlock + t, &acc[0], &acc[1]);
   }
   const T gs = gscale ? (T)(*gscale) : T(1);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = r0 + r * kBlock + t;
-    if (i < A.n) stnt(gs * acc[r], out + i);
+    if (i < A.n) st_pass<KEEP>(gs * acc[r], out + i);
   }
 }
 
@@ -1067,14 +1081,21 @@ hipError_t launch_chain(const SpMat<T> &A, int kind, bool fold, bool last, const
   const dim3 grid(a.ntiles > 0 ? a.ntiles : tiles_of(A.n) - a.tile0),
       grid2(a.ntiles > 0 ? a.ntiles : (A.n + 2 * kBlock - 1) / (2 * kBlock) - a.tile0),
       block(kBlock);
-#define PP_CHAIN(K, F, L)                                                                     \
+#define PP_CHAIN_P(K, F, L, C)                                                                \
   do {                                                                                        \
     if (two)                                                                                  \
-      hipLaunchKernelGGL((k_chain<T, K, F, L, true, 2>), grid2, block, 0, stream, A, a);      \
+      hipLaunchKernelGGL((k_chain<T, K, F, L, true, 2, C>), grid2, block, 0, stream, A, a);   \
     else if (A.sdesc)                                                                         \
-      hipLaunchKernelGGL((k_chain<T, K, F, L, true, 1>), grid, block, 0, stream, A, a);       \
+      hipLaunchKernelGGL((k_chain<T, K, F, L, true, 1, C>), grid, block, 0, stream, A, a);    \
     else                                                                                      \
-      hipLaunchKernelGGL((k_chain<T, K, F, L, false, 1>), grid, block, 0, stream, A, a);      \
+      hipLaunchKernelGGL((k_chain<T, K, F, L, false, 1, C>), grid, block, 0, stream, A, a);   \
+  } while (0)
+#define PP_CHAIN(K, F, L) PP_CHAIN_P(K, F, L, false)
+// the operator-form steps also come with cached loads and stores (a.cached)
+#define PP_CHAIN_C(K, F, L)                        \
+  do {                                             \
+    if (a.cached) PP_CHAIN_P(K, F, L, true);       \
+    else PP_CHAIN_P(K, F, L, false);               \
   } while (0)
   switch (kind) {
     case 0:
@@ -1085,11 +1106,11 @@ hipError_t launch_chain(const SpMat<T> &A, int kind, bool fold, bool last, const
       break;
     case 2:
       if (fold) PP_CHAIN(2, true, false);
-      else if (last) PP_CHAIN(2, false, true);
-      else PP_CHAIN(2, false, false);
+      else if (last) PP_CHAIN_C(2, false, true);
+      else PP_CHAIN_C(2, false, false);
       break;
     case 3:
-      if (last) PP_CHAIN(3, false, true); else PP_CHAIN(3, false, false);
+      if (last) PP_CHAIN_C(3, false, true); else PP_CHAIN_C(3, false, false);
       break;
     case 4:
       PP_CHAIN(4, false, false);
@@ -1097,7 +1118,9 @@ hipError_t launch_chain(const SpMat<T> &A, int kind, bool fold, bool last, const
     default:
       return hipErrorInvalidValue;
   }
+#undef PP_CHAIN_C
 #undef PP_CHAIN
+#undef PP_CHAIN_P
   return hipGetLastError();
 }
 
@@ -1111,15 +1134,24 @@ hipError_t launch_axpy(int n, double c, const T *g, const double *gscale, const 
 
 template <typename T>
 hipError_t launch_spmv(const SpMat<T> &A, const T *g, const double *gscale, T *out,
-                       hipStream_t stream, int tile0, int ntiles) {
+                       hipStream_t stream, int tile0, int ntiles, bool cached) {
   const int all = (A.n + chain_tile_rows(A) - 1) / chain_tile_rows(A);
   const dim3 grid(ntiles > 0 ? ntiles : all - tile0), block(kBlock);
-  if (A.sdesc && sizeof(T) == sizeof(float))
-    hipLaunchKernelGGL((k_spmv<T, true, 2>), grid, block, 0, stream, A, g, gscale, out, tile0);
-  else if (A.sdesc)
-    hipLaunchKernelGGL((k_spmv<T, true, 1>), grid, block, 0, stream, A, g, gscale, out, tile0);
-  else
-    hipLaunchKernelGGL((k_spmv<T, false, 1>), grid, block, 0, stream, A, g, gscale, out, tile0);
+#define PP_SPMV(C)                                                                            \
+  do {                                                                                        \
+    if (A.sdesc && sizeof(T) == sizeof(float))                                                \
+      hipLaunchKernelGGL((k_spmv<T, true, 2, C>), grid, block, 0, stream, A, g, gscale, out,  \
+                         tile0);                                                              \
+    else if (A.sdesc)                                                                         \
+      hipLaunchKernelGGL((k_spmv<T, true, 1, C>), grid, block, 0, stream, A, g, gscale, out,  \
+                         tile0);                                                              \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_spmv<T, false, 1, C>), grid, block, 0, stream, A, g, gscale, out, \
+                         tile0);                                                              \
+  } while (0)
+  if (cached) PP_SPMV(true);
+  else PP_SPMV(false);
+#undef PP_SPMV
   return hipGetLastError();
 }
 
@@ -1384,7 +1416,7 @@ hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, cons
   template hipError_t launch_axpy<T>(int, double, const T *, const double *, const T *, T *,    \
                                      hipStream_t);                                              \
   template hipError_t launch_spmv<T>(const SpMat<T> &, const T *, const double *, T *,           \
-                                     hipStream_t, int, int);                                    \
+                                     hipStream_t, int, int, bool);                              \
   template hipError_t launch_residual<T>(const SpMat<T> &, const T *, const T *, T *, double *,  \
                                          int *, hipStream_t);                                   \
   template hipError_t launch_dots<T>(int, int, const T *, int64_t, int, int, const T *, double *, \

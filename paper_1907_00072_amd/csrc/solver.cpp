@@ -50,6 +50,17 @@ constexpr double kBreakdownRtol = 1e-12;
 constexpr double kStagnationBand = 100.0;
 constexpr double kStagnationFactor = 0.9;
 constexpr int kStagnationCycles = 3;
+// Working set of one chain launch (its matrix rows and two vectors) that MI355X's
+// 256 MiB Infinity Cache still returns to the next launch: 27/32 of it.  Measured
+// on the 256^3 stencil: the slab-skewed schedule gains up to 3.0M rows per slab in
+// FP64 (73 B a row, 219 MiB) and 6.3M in FP32 (37 B, 222 MiB), and loses it all
+// at 3.5M rows in FP64 (255 MiB).
+constexpr double kCacheBudget = 216.0 * 1024 * 1024;
+// the slab-skewed schedule is chosen only when the bandwidth is at most this
+// fraction of a slab (the rest of a slab is re-read from cache)
+constexpr int kSlabPerBandwidth = 8;
+// group size standing for "all of a step's launches"
+constexpr int kAllLaunches = 1 << 20;
 
 #define PP_TRY_HIP(expr)                              \
   do {                                                \
@@ -277,13 +288,16 @@ struct Opr : SpMat<T> {
   int blk_group = 0;
   int blk_slab_rows = 0;
   int blk_bw_rows = 0;  // the matrix bandwidth max |col - row|
+  // full-range operator-form launches with cached loads and stores (a launch's
+  // matrix and vectors fit the last-level cache)
+  bool keep = false;
   Opr(const SpMat<T> &m) : SpMat<T>(m) {}  // NOLINT: a plain matrix is an operator
 };
 
 // out = Op (gscale * g).
 template <typename T>
 int op_product(const Opr<T> &A, const T *g, const double *gscale, T *out, hipStream_t s) {
-  PP_TRY_HIP(ppk::launch_spmv<T>(A, g, gscale, out, s));
+  PP_TRY_HIP(ppk::launch_spmv<T>(A, g, gscale, out, s, 0, 0, A.keep));
   if constexpr (sizeof(T) == sizeof(double)) {
     if (A.ilu) PP_TRY_HIP(ppi::ilu_solve(*A.ilu, out, out, s));
   }
@@ -302,7 +316,13 @@ int op_chain(const Opr<T> &A, int kind, bool fold, bool last, const ppk::ChainAr
       return PP_OK;
     }
   }
-  PP_TRY_HIP(ppk::launch_chain<T>(A, kind, fold, last, a, s));
+  if (A.keep) {
+    ppk::ChainArgs<T> c = a;
+    c.cached = true;
+    PP_TRY_HIP(ppk::launch_chain<T>(A, kind, fold, last, c, s));
+  } else {
+    PP_TRY_HIP(ppk::launch_chain<T>(A, kind, fold, last, a, s));
+  }
   return PP_OK;
 }
 
@@ -433,10 +453,12 @@ struct OpLaunch {
 // written by then, and a ping-pong buffer is overwritten only at rows every later
 // reader of its old contents has passed.  So each slab's matrix and vectors are
 // read group times while they may still sit in cache, with results bit-identical
-// to the full-range launches.
+// to the full-range launches.  The launches use ordinary (cached) loads and stores:
+// with the non-temporal ones of the full-range chain, a slab's second pass came
+// back from HBM.
 template <typename T>
-int run_op_launches_blocked(const Opr<T> &A, const std::vector<OpLaunch<T>> &L,
-                            hipStream_t s) {
+int run_op_launches_blocked(const Opr<T> &A, const std::vector<OpLaunch<T>> &L, hipStream_t s,
+                            int64_t *launched) {
   const int tr = ppk::chain_tile_rows(A);
   const int ntile = (A.n + tr - 1) / tr;
   const int S = std::max(1, A.blk_slab_rows / tr);
@@ -453,13 +475,15 @@ int run_op_launches_blocked(const Opr<T> &A, const std::vector<OpLaunch<T>> &L,
         if (t1 <= t0) continue;
         const OpLaunch<T> &l = L[k];
         if (l.product) {
-          PP_TRY_HIP(ppk::launch_spmv<T>(A, l.a.g, l.a.gscale, l.a.out, s, t0, t1 - t0));
+          PP_TRY_HIP(ppk::launch_spmv<T>(A, l.a.g, l.a.gscale, l.a.out, s, t0, t1 - t0, true));
         } else {
           ppk::ChainArgs<T> a = l.a;
           a.tile0 = t0;
           a.ntiles = t1 - t0;
+          a.cached = true;
           PP_TRY_HIP(ppk::launch_chain<T>(A, l.kind, false, l.last, a, s));
         }
+        if (launched) ++*launched;
       }
     }
   }
@@ -502,9 +526,8 @@ int run_op_chain(const Opr<T> &A, const std::vector<ppn::Step> &steps, const T *
       cs = nullptr;
       pb ^= 1;
     }
-    if (launches) *launches += (int64_t)L.size();
     if (cnt) cnt->spmvs += (int64_t)L.size();
-    return run_op_launches_blocked<T>(A, L, s);
+    return run_op_launches_blocked<T>(A, L, s, launches);
   }
   auto account = [&](int vec_rw) {
     if (bytes) *bytes += product_bytes(A, vec_rw);
@@ -1142,18 +1165,50 @@ int residual_f64(const Opr<double> &A, Work<double> &w, const double *b, const d
 
 // Turn on the slab-skewed chain schedule of an operator when the options ask for
 // it: the matrix bandwidth comes from one pass over the column indices.
+// Cache policy and order of the Arnoldi step's chain launches (Section VII's
+// reuse of the matrix across several products).  One launch streams its matrix
+// rows and two vectors; when all of that fits kCacheBudget, chain_group 0
+// (automatic) runs full-range launches with cached loads and stores, so each
+// launch finds the matrix where the previous one left it.  Larger matrices get
+// the slab-skewed order over all of a step's launches with slabs that fit the
+// budget, when the bandwidth is small beside a slab; otherwise full-range,
+// non-temporal launches.  chain_group 1: full-range, non-temporal; >= 2: the
+// slab-skewed order with that group and chain_slab_rows (0: budget-sized slabs).
 template <typename T>
 int set_blocking(Opr<T> &A, const SolveIn &in, int32_t *scratch, hipStream_t s) {
-  if (in.o.chain_group < 2 || in.ilu) return PP_OK;
+  if (in.ilu || in.o.chain_group == 1) return PP_OK;
+  const double per_row = product_bytes(A, 1) / (double)A.n;
+  const int64_t tr = ppk::chain_tile_rows(A);
+  const int64_t fit = std::max<int64_t>(tr, (int64_t)(kCacheBudget / per_row) / tr * tr);
+  if (in.o.chain_group == 0 && fit >= A.n) {
+    A.keep = true;
+    return PP_OK;
+  }
+  const int slab = in.o.chain_slab_rows > 0 ? in.o.chain_slab_rows
+                                            : (int)std::min<int64_t>(fit, 1 << 30);
   PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, scratch, s));
   PP_TRY_HIP(ppk::launch_bandwidth(A.n, in.A->row_ptr, in.A->col_ind, scratch, s));
   int32_t bw = 0;
   PP_TRY_HIP(hipMemcpyAsync(&bw, scratch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   PP_TRY_HIP(hipStreamSynchronize(s));
-  A.blk_group = in.o.chain_group;
-  A.blk_slab_rows = in.o.chain_slab_rows > 0 ? in.o.chain_slab_rows : (1 << 21);
+  if (in.o.chain_group == 0) {
+    if ((int64_t)bw * kSlabPerBandwidth > slab) return PP_OK;
+    A.blk_group = kAllLaunches;
+  } else {
+    A.blk_group = in.o.chain_group;
+  }
+  A.blk_slab_rows = slab;
   A.blk_bw_rows = bw;
   return PP_OK;
+}
+
+// What set_blocking chose, for pp_stats.
+template <typename T>
+void note_schedule(pp_stats *st, const Opr<T> &A) {
+  if (!st) return;
+  const bool blocked = A.blk_group >= 2;
+  st->chain_slab_rows = blocked ? A.blk_slab_rows : 0;
+  st->chain_cached = (blocked || A.keep) ? 1 : 0;
 }
 
 int solve_f64(const SolveIn &in, pp_stats *st) {
@@ -1182,6 +1237,7 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
   A.ilu = in.ilu;
   A.prod = prod;
   PP_TRY(set_blocking<double>(A, in, iscratch, in.s));
+  note_schedule(st, A);
   hipStream_t s = in.s;
   Counters cnt;
   cnt.history = in.o.history;
@@ -1326,6 +1382,7 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
   Opr<float> A32(with_sell(
       view<float>(in.A, in.o.vals_f32 ? (const void *)in.o.vals_f32 : (const void *)vals32), sc));
   PP_TRY(set_blocking<float>(A32, in, iscratch, s));
+  note_schedule(st, A32);
   Counters cnt;
   cnt.history = in.o.history;
   cnt.history_cap = in.o.history ? in.o.history_cap : 0;
@@ -1476,6 +1533,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
   if (opt) in.o = *opt;
   if (in.o.precision != PP_PREC_F64 && in.o.precision != PP_PREC_F32_IR) return PP_ERR_ARG;
   if (in.o.op_form != PP_OP_RESIDUAL_POLY && in.o.op_form != PP_OP_PRODUCT) return PP_ERR_ARG;
+  if (in.o.chain_group < 0 || in.o.chain_slab_rows < 0) return PP_ERR_ARG;
   if (in.o.poly) {
     if (in.o.poly->n != A->n) return PP_ERR_ARG;
   } else if (d > A->n) {

@@ -149,6 +149,17 @@ def test_cd3d_256_sampled_chain_rows_and_solve(B, refs):
     ref = refs.get("cd3d_256_pe100_d40")
     assert ref is not None, "run tests/golden/make_fullsize_refs.py --only cd3d_256_pe100_d40"
     _check_against_ref(ref, st, x, P.tol)
+    # the automatic chain schedule at this size: slab-skewed over cache-sized slabs
+    # with cached loads; the same bits as full-range non-temporal launches
+    assert st.chain_cached and 0 < st.chain_slab_rows < P.A.n
+    x1, st1 = B.pp_gmres_solve(A, _up(P.b), m=P.m, d=d, tol=P.tol, v0=_up(P.v0), chain_group=1)
+    assert st1.chain_slab_rows == 0 and not st1.chain_cached
+    assert st1.iters == st.iters and torch.equal(x1, x)
+    kw = dict(m=P.m, d=d, tol=P.tol, v0=_up(P.v0), precision="f32_ir", inner_tol=1e-5)
+    x2, st2 = B.pp_gmres_solve(A, _up(P.b), **kw)
+    x3, st3 = B.pp_gmres_solve(A, _up(P.b), chain_group=1, **kw)
+    assert st2.chain_cached and st2.chain_slab_rows > st.chain_slab_rows  # 37 B a row
+    assert st3.iters == st2.iters and torch.equal(x2, x3) and st2.relres_true < P.tol
 
 
 def test_adjoint_512(B):

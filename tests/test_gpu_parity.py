@@ -629,8 +629,14 @@ def test_blocked_chain_gives_identical_results(B, group, slab, precision):
     kw = dict(m=20, d=10, tol=1e-10, v0=_up(P.v0), precision=precision)
     x0, s0 = B.pp_gmres_solve(A, _up(P.b), **kw)
     x1, s1 = B.pp_gmres_solve(A, _up(P.b), chain_group=group, chain_slab_rows=slab, **kw)
+    x2, s2 = B.pp_gmres_solve(A, _up(P.b), chain_group=1, **kw)
     assert s0.relres_true < 1e-10
     assert s1.iters == s0.iters and torch.equal(x0, x1)
+    assert s2.iters == s0.iters and torch.equal(x0, x2)
+    # automatic: this matrix fits the cache, so full-range cached launches
+    assert (s0.chain_slab_rows, s0.chain_cached) == (0, True)
+    assert (s1.chain_slab_rows, s1.chain_cached) == (slab, True)
+    assert (s2.chain_slab_rows, s2.chain_cached) == (0, False)
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32_ir"])
@@ -643,6 +649,15 @@ def test_blocked_chain_on_the_csr_layout(B, precision):
     x1, s1 = B.pp_gmres_solve(A, _up(P.b), chain_group=3, chain_slab_rows=1500, **kw)
     assert s0.layout_used == s1.layout_used == "csr"
     assert s1.iters == s0.iters and torch.equal(x0, x1)
+
+
+def test_chain_schedule_options_are_checked(B):
+    P = W.config(1, N=16)
+    A = B.CSRMatrix.from_host(P.A)
+    for kw in (dict(chain_group=-1), dict(chain_slab_rows=-5)):
+        with pytest.raises(B.PPError) as e:
+            B.pp_gmres_solve(A, _up(P.b), m=10, d=4, tol=1e-8, v0=_up(P.v0), **kw)
+        assert e.value.code == B.PP_ERR_ARG
 
 
 def test_blocked_chain_with_wide_bandwidth(B):
