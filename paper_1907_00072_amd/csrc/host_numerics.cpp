@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <cstdint>
 #include <cmath>
 #include <numeric>
 
@@ -328,6 +329,25 @@ void cholesky_solve(const std::vector<double> &R, int k, const double *rhs, doub
     double acc = z[i];
     for (int q = i + 1; q < k; ++q) acc -= R[i + (size_t)q * k] * y[q];
     y[i] = acc / R[i + (size_t)i * k];
+  }
+}
+
+void slab_order(int ntile, int S, int w, int K, int group, std::vector<SlabPart> &out) {
+  out.clear();
+  S = std::max(S, 1);
+  w = std::max(w, 0);
+  group = std::max(group, 1);
+  for (int k0 = 0; k0 < K; k0 += group) {
+    const int k1 = std::min(K, k0 + group);
+    const int64_t span = (int64_t)ntile + (int64_t)(k1 - 1 - k0) * w;
+    for (int64_t b = 0; b * S < span; ++b) {
+      for (int k = k0; k < k1; ++k) {
+        const int64_t shift = (int64_t)(k - k0) * w;
+        const int t0 = (int)std::max<int64_t>(0, b * S - shift);
+        const int t1 = (int)std::min<int64_t>(ntile, (b + 1) * S - shift);
+        if (t1 > t0) out.push_back(SlabPart{k, t0, t1});
+      }
+    }
   }
 }
 

@@ -45,4 +45,18 @@ int cholesky_upper(const double *G, int ldg, int k, std::vector<double> &R);
 // Solve R^T R y = rhs (R from cholesky_upper, k x k).
 void cholesky_solve(const std::vector<double> &R, int k, const double *rhs, double *y);
 
+// One launch of a slab-skewed chain schedule: chain launch k over tiles [t0, t1).
+struct SlabPart {
+  int k, t0, t1;
+};
+
+// The slab-skewed order of K chain launches over ntile tiles (a matrix-powers
+// style schedule, Section VII): the launches are taken `group` at a time; inside a
+// group, slab b of the group's i-th launch covers the tiles [b S - i w, (b+1) S - i w)
+// clipped to [0, ntile), for b = 0, 1, ... with the group's launches in order inside
+// each slab (S >= 1 tiles a slab, w >= 0 tiles of bandwidth, group >= 1).  Every
+// launch covers each tile exactly once, and launch k reaches a tile only after
+// launch k - 1 has covered every tile within w of it.
+void slab_order(int ntile, int S, int w, int K, int group, std::vector<SlabPart> &out);
+
 }  // namespace ppn

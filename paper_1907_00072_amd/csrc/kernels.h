@@ -71,9 +71,9 @@ struct ChainArgs {
   const double *yscale;  // scale of y_in in the operator form's last step (nullptr = 1)
   int tile0 = 0;         // first tile (chain_tile_rows rows each) the launch covers
   int ntiles = 0;        // tiles it covers (0 = through the last row)
-  // host-side choice of the cache policy for kinds 2 and 3 without fold: false =
-  // non-temporal loads and stores of A and the vectors (a pass that touches each
-  // once), true = ordinary ones (the next launch re-reads them soon)
+  // host-side choice of the cache policy: false = non-temporal loads and stores of
+  // A and the vectors (a pass that touches each once), true = ordinary ones (the
+  // next launch re-reads them soon)
   bool cached = false;
 };
 

@@ -1090,9 +1090,8 @@ hipError_t launch_chain(const SpMat<T> &A, int kind, bool fold, bool last, const
     else                                                                                      \
       hipLaunchKernelGGL((k_chain<T, K, F, L, false, 1, C>), grid, block, 0, stream, A, a);   \
   } while (0)
-#define PP_CHAIN(K, F, L) PP_CHAIN_P(K, F, L, false)
-// the operator-form steps also come with cached loads and stores (a.cached)
-#define PP_CHAIN_C(K, F, L)                        \
+// cached (a.cached) or non-temporal loads and stores
+#define PP_CHAIN(K, F, L)                          \
   do {                                             \
     if (a.cached) PP_CHAIN_P(K, F, L, true);       \
     else PP_CHAIN_P(K, F, L, false);               \
@@ -1106,11 +1105,11 @@ hipError_t launch_chain(const SpMat<T> &A, int kind, bool fold, bool last, const
       break;
     case 2:
       if (fold) PP_CHAIN(2, true, false);
-      else if (last) PP_CHAIN_C(2, false, true);
-      else PP_CHAIN_C(2, false, false);
+      else if (last) PP_CHAIN(2, false, true);
+      else PP_CHAIN(2, false, false);
       break;
     case 3:
-      if (last) PP_CHAIN_C(3, false, true); else PP_CHAIN_C(3, false, false);
+      if (last) PP_CHAIN(3, false, true); else PP_CHAIN(3, false, false);
       break;
     case 4:
       PP_CHAIN(4, false, false);
@@ -1118,7 +1117,6 @@ hipError_t launch_chain(const SpMat<T> &A, int kind, bool fold, bool last, const
     default:
       return hipErrorInvalidValue;
   }
-#undef PP_CHAIN_C
 #undef PP_CHAIN
 #undef PP_CHAIN_P
   return hipGetLastError();

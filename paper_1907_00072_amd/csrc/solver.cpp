@@ -342,6 +342,90 @@ double product_bytes(const Opr<T> &A, int vec_rw) {
   return (double)A.nnz * (sizeof(T) + sizeof(int32_t)) + 4.0 * (A.n + 1) + vecs;
 }
 
+// One launch of a chain: a plain product (t = A p) or a fused product + update
+// (ChainArgs kind, with its fold / last variant).
+template <typename T>
+struct OpLaunch {
+  bool product;
+  int kind;
+  bool last;
+  ppk::ChainArgs<T> a;  // for a product: g, gscale and out only
+  bool fold = false;
+};
+
+// A chain's launches in slab-skewed order (ppn::slab_order, a matrix-powers style
+// schedule, Section VII): the launches taken `group` at a time, and inside a group
+// slab b of the group's k-th launch covers the tiles [b S - k w, (b+1) S - k w)
+// (S tiles per slab, w = the bandwidth rounded up to whole tiles), for b = 0, 1, ...
+// with the group's launches in order inside each slab.  Launch k reads launch k-1's
+// output only within the bandwidth of its own rows, all of which is written by
+// then; a buffer read by launch k (gathered or elementwise) is next overwritten by
+// launch k + 2 or later, only at rows every later reader of its old contents has
+// passed; and accumulators read and written elementwise see each row's launches
+// in chain order.  So each slab's matrix and vectors are read group times while
+// they may still sit in cache, with results bit-identical to the full-range
+// launches.  The launches use ordinary (cached) loads and stores: with the
+// non-temporal ones of the full-range chain, a slab's second pass came back from
+// HBM.  *launched counts the kernel launches issued.
+template <typename T>
+int run_op_launches_blocked(const Opr<T> &A, const std::vector<OpLaunch<T>> &L, hipStream_t s,
+                            int64_t *launched) {
+  const int tr = ppk::chain_tile_rows(A);
+  const int ntile = (A.n + tr - 1) / tr;
+  const int S = std::max(1, A.blk_slab_rows / tr);
+  const int w = (A.blk_bw_rows + tr - 1) / tr;
+  std::vector<ppn::SlabPart> order;
+  ppn::slab_order(ntile, S, w, (int)L.size(), A.blk_group, order);
+  for (const ppn::SlabPart &part : order) {
+    const OpLaunch<T> &l = L[part.k];
+    const int t0 = part.t0, t1 = part.t1;
+    if (l.product) {
+      PP_TRY_HIP(ppk::launch_spmv<T>(A, l.a.g, l.a.gscale, l.a.out, s, t0, t1 - t0, true));
+    } else {
+      ppk::ChainArgs<T> a = l.a;
+      a.tile0 = t0;
+      a.ntiles = t1 - t0;
+      a.cached = true;
+      PP_TRY_HIP(ppk::launch_chain<T>(A, l.kind, l.fold, l.last, a, s));
+    }
+    if (launched) ++*launched;
+  }
+  return PP_OK;
+}
+
+// The launches of a chain as they are produced: run at once, or collected for
+// the slab-skewed order when the operator asks for it (A.blk_group >= 2, no M^-1).
+template <typename T>
+struct ChainEmitter {
+  const Opr<T> &A;
+  hipStream_t s;
+  Counters *cnt;
+  double *bytes;
+  int64_t *launches;
+  bool blocked;
+  std::vector<OpLaunch<T>> L;
+  ChainEmitter(const Opr<T> &A_, hipStream_t s_, Counters *cnt_, double *bytes_,
+               int64_t *launches_)
+      : A(A_), s(s_), cnt(cnt_), bytes(bytes_), launches(launches_),
+        blocked(A_.blk_group >= 2 && !A_.ilu) {}
+  // one fused launch; vec_rw as for product_bytes
+  int chain(int kind, bool fold, bool last, const ppk::ChainArgs<T> &a, int vec_rw) {
+    if (bytes) *bytes += product_bytes(A, vec_rw);
+    if (cnt) cnt->spmvs++;
+    if (blocked) {
+      L.push_back(OpLaunch<T>{false, kind, last, a, fold});
+      return PP_OK;
+    }
+    if (launches) ++*launches;
+    return op_chain<T>(A, kind, fold, last, a, s);
+  }
+  // the collected launches, if any
+  int finish() {
+    if (!blocked || L.empty()) return PP_OK;
+    return run_op_launches_blocked<T>(A, L, s, launches);
+  }
+};
+
 // y_out = y_in + p(A) (gscale * g) for the step table; y_in may be nullptr
 // (zero) or equal y_out.  Uses P0, P1, Tb as chain temporaries.  Adds the
 // launches and their algorithmic bytes to *bytes / *launches when given.
@@ -350,10 +434,7 @@ int run_chain(const Opr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
               const double *gscale, const T *y_in, T *y_out, T *P0, T *P1, T *Tb,
               hipStream_t s, Counters *cnt, double *bytes = nullptr,
               int64_t *launches = nullptr) {
-  auto account = [&](int vec_rw) {
-    if (bytes) *bytes += product_bytes(A, vec_rw);
-    if (launches) ++*launches;
-  };
+  ChainEmitter<T> em(A, s, cnt, bytes, launches);
   const int K = (int)steps.size();
   const T *cur = g;
   const double *cs = gscale;
@@ -372,9 +453,7 @@ int run_chain(const Opr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
       }
       ppk::ChainArgs<T> a{cur, cs, nullptr, nullptr, fold ? nullptr : bufs[pb], yi, y_out,
                           st.c1, 0.0, cf};
-      PP_TRY(op_chain<T>(A, 0, fold, false, a, s));
-      if (cnt) cnt->spmvs++;
-      account((yi ? 1 : 0) + 1 + (fold ? 0 : 1));
+      PP_TRY(em.chain(0, fold, false, a, (yi ? 1 : 0) + 1 + (fold ? 0 : 1)));
       yi = y_out;
       if (fold) break;
       cur = bufs[pb];
@@ -383,23 +462,19 @@ int run_chain(const Opr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
     } else {
       ppk::ChainArgs<T> a{cur, cs, nullptr, nullptr, last ? nullptr : Tb, yi, y_out,
                           st.c1, st.c2, 0.0};
-      PP_TRY(op_chain<T>(A, 1, false, last, a, s));
-      if (cnt) cnt->spmvs++;
-      account((yi ? 1 : 0) + 1 + (last ? 0 : 1));
+      PP_TRY(em.chain(1, false, last, a, (yi ? 1 : 0) + 1 + (last ? 0 : 1)));
       yi = y_out;
       if (last) break;
       ppk::ChainArgs<T> b{Tb, nullptr, cur, cs, fold ? nullptr : bufs[pb], yi, y_out,
                           st.c1, st.c2, cf};
-      PP_TRY(op_chain<T>(A, 2, fold, false, b, s));
-      if (cnt) cnt->spmvs++;
-      account(1 + (fold ? 2 : 1));
+      PP_TRY(em.chain(2, fold, false, b, 1 + (fold ? 2 : 1)));
       if (fold) break;
       cur = bufs[pb];
       cs = nullptr;
       pb ^= 1;
     }
   }
-  return PP_OK;
+  return em.finish();
 }
 
 // out = p(A) (gscale * g) for p(A) = sum_k c[k] A^k by Horner's rule,
@@ -415,6 +490,7 @@ int run_horner(const Opr<T> &A, const std::vector<double> &c, const T *g, const 
     PP_TRY_HIP(ppk::launch_axpy<T>(A.n, c[0], g, gscale, nullptr, out, s));
     return PP_OK;
   }
+  ChainEmitter<T> em(A, s, cnt, bytes, launches);
   T *bufs[2] = {P0, P1};
   int pb = 0;
   const T *z = g;
@@ -423,71 +499,12 @@ int run_horner(const Opr<T> &A, const std::vector<double> &c, const T *g, const 
     T *dst = (k == 0) ? out : bufs[pb];
     ppk::ChainArgs<T> a{z, zs, g, gscale, dst, nullptr, nullptr, c[k],
                         k == deg - 1 ? c[deg] : 1.0, 0.0, nullptr};
-    PP_TRY(op_chain<T>(A, 4, false, false, a, s));
-    if (bytes) *bytes += product_bytes(A, 2);
-    if (launches) ++*launches;
-    if (cnt) cnt->spmvs++;
+    PP_TRY(em.chain(4, false, false, a, 2));
     z = dst;
     zs = nullptr;
     pb ^= 1;
   }
-  return PP_OK;
-}
-
-// One launch of the operator-form chain: a plain product (t = A p) or a fused
-// product + root update (ChainArgs kind).
-template <typename T>
-struct OpLaunch {
-  bool product;
-  int kind;
-  bool last;
-  ppk::ChainArgs<T> a;  // for a product: g, gscale and out only
-};
-
-// The launches of run_op_chain in slab-skewed order, a matrix-powers style
-// schedule (Section VII): the launches are taken `group` at a time, and inside a
-// group slab b of the group's k-th launch covers the tiles [b S - k w, (b+1) S - k w)
-// (S tiles per slab, w = the bandwidth rounded up to whole tiles), run for
-// b = 0, 1, ... with the group's launches in order inside each slab.  Launch k reads
-// launch k-1's output only within the bandwidth of its own rows, all of which is
-// written by then, and a ping-pong buffer is overwritten only at rows every later
-// reader of its old contents has passed.  So each slab's matrix and vectors are
-// read group times while they may still sit in cache, with results bit-identical
-// to the full-range launches.  The launches use ordinary (cached) loads and stores:
-// with the non-temporal ones of the full-range chain, a slab's second pass came
-// back from HBM.
-template <typename T>
-int run_op_launches_blocked(const Opr<T> &A, const std::vector<OpLaunch<T>> &L, hipStream_t s,
-                            int64_t *launched) {
-  const int tr = ppk::chain_tile_rows(A);
-  const int ntile = (A.n + tr - 1) / tr;
-  const int S = std::max(1, A.blk_slab_rows / tr);
-  const int w = (A.blk_bw_rows + tr - 1) / tr;
-  const int K = (int)L.size();
-  for (int k0 = 0; k0 < K; k0 += A.blk_group) {
-    const int k1 = std::min(K, k0 + A.blk_group);
-    const int64_t span = (int64_t)ntile + (int64_t)(k1 - 1 - k0) * w;
-    for (int64_t b = 0; b * S < span; ++b) {
-      for (int k = k0; k < k1; ++k) {
-        const int64_t shift = (int64_t)(k - k0) * w;
-        const int t0 = (int)std::max<int64_t>(0, b * S - shift);
-        const int t1 = (int)std::min<int64_t>(ntile, (b + 1) * S - shift);
-        if (t1 <= t0) continue;
-        const OpLaunch<T> &l = L[k];
-        if (l.product) {
-          PP_TRY_HIP(ppk::launch_spmv<T>(A, l.a.g, l.a.gscale, l.a.out, s, t0, t1 - t0, true));
-        } else {
-          ppk::ChainArgs<T> a = l.a;
-          a.tile0 = t0;
-          a.ntiles = t1 - t0;
-          a.cached = true;
-          PP_TRY_HIP(ppk::launch_chain<T>(A, l.kind, false, l.last, a, s));
-        }
-        if (launched) ++*launched;
-      }
-    }
-  }
-  return PP_OK;
+  return em.finish();
 }
 
 // w_out = A p(A) (gscale * g), evaluated as v - pi(A) v with v = gscale * g:
@@ -1049,6 +1066,45 @@ SpMat<T> view(const pp_csr *A, const void *vals) {
   return SpMat<T>{(int)A->n, (int)A->nnz, A->row_ptr, A->col_ind, static_cast<const T *>(vals)};
 }
 
+// Cache policy and order of an operator's chain launches (Section VII's reuse of
+// the matrix across several products): the Arnoldi step's operator, the
+// cycle-end update and pp_apply's product form, the power basis' Horner chain.
+// One launch streams its matrix rows and two vectors; when all of that fits
+// kCacheBudget, group 0 (automatic) runs full-range launches with cached loads and
+// stores, so each launch finds the matrix where the previous one left it.  Larger
+// matrices get the slab-skewed order over all of a chain's launches with slabs
+// that fit the budget, when the bandwidth (one pass over csr's column indices) is
+// small beside a slab; otherwise full-range, non-temporal launches.  group 1:
+// full-range, non-temporal; >= 2: the slab-skewed order with that group and
+// slab_rows (0: budget-sized slabs).  Not for M^-1 A (M^-1 couples all rows).
+template <typename T>
+int choose_schedule(Opr<T> &A, const pp_csr *csr, int group, int slab_rows, int32_t *scratch,
+                    hipStream_t s) {
+  if (A.ilu || group == 1) return PP_OK;
+  const double per_row = product_bytes(A, 1) / (double)A.n;
+  const int64_t tr = ppk::chain_tile_rows(A);
+  const int64_t fit = std::max<int64_t>(tr, (int64_t)(kCacheBudget / per_row) / tr * tr);
+  if (group == 0 && fit >= A.n) {
+    A.keep = true;
+    return PP_OK;
+  }
+  const int slab = slab_rows > 0 ? slab_rows : (int)std::min<int64_t>(fit, 1 << 30);
+  PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, scratch, s));
+  PP_TRY_HIP(ppk::launch_bandwidth(A.n, csr->row_ptr, csr->col_ind, scratch, s));
+  int32_t bw = 0;
+  PP_TRY_HIP(hipMemcpyAsync(&bw, scratch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  if (group == 0) {
+    if ((int64_t)bw * kSlabPerBandwidth > slab) return PP_OK;
+    A.blk_group = kAllLaunches;
+  } else {
+    A.blk_group = group;
+  }
+  A.blk_slab_rows = slab;
+  A.blk_bw_rows = bw;
+  return PP_OK;
+}
+
 template <typename T>
 int apply_impl(const pp_csr *A, const pp_poly *p, const void *v, void *y, hipStream_t s) {
   Arena *ar = nullptr;
@@ -1060,10 +1116,13 @@ int apply_impl(const pp_csr *A, const pp_poly *p, const void *v, void *y, hipStr
   Carver meas(nullptr);
   T *bufs[3];
   for (auto &b : bufs) b = meas.take<T>(pad_ld(n));
+  int32_t *isc = meas.take<int32_t>(64);
   PP_TRY(ensure_arena(ar, meas.off + 256, 64));
   Carver c(ar->dev);
   for (auto &b : bufs) b = c.take<T>(pad_ld(n));
-  const SpMat<T> M = with_sell(view<T>(A, A->vals), sc);
+  isc = c.take<int32_t>(64);
+  Opr<T> M(with_sell(view<T>(A, A->vals), sc));
+  if (products > 0) PP_TRY(choose_schedule<T>(M, A, 0, 0, isc, s));
   const T *vv = static_cast<const T *>(v);
   T *yy = static_cast<T *>(y);
   if (p->kind == 1) {
@@ -1163,43 +1222,11 @@ int residual_f64(const Opr<double> &A, Work<double> &w, const double *b, const d
   return PP_OK;
 }
 
-// Turn on the slab-skewed chain schedule of an operator when the options ask for
-// it: the matrix bandwidth comes from one pass over the column indices.
-// Cache policy and order of the Arnoldi step's chain launches (Section VII's
-// reuse of the matrix across several products).  One launch streams its matrix
-// rows and two vectors; when all of that fits kCacheBudget, chain_group 0
-// (automatic) runs full-range launches with cached loads and stores, so each
-// launch finds the matrix where the previous one left it.  Larger matrices get
-// the slab-skewed order over all of a step's launches with slabs that fit the
-// budget, when the bandwidth is small beside a slab; otherwise full-range,
-// non-temporal launches.  chain_group 1: full-range, non-temporal; >= 2: the
-// slab-skewed order with that group and chain_slab_rows (0: budget-sized slabs).
+// The solve's choice (pp_opts.chain_group / chain_slab_rows).
 template <typename T>
 int set_blocking(Opr<T> &A, const SolveIn &in, int32_t *scratch, hipStream_t s) {
-  if (in.ilu || in.o.chain_group == 1) return PP_OK;
-  const double per_row = product_bytes(A, 1) / (double)A.n;
-  const int64_t tr = ppk::chain_tile_rows(A);
-  const int64_t fit = std::max<int64_t>(tr, (int64_t)(kCacheBudget / per_row) / tr * tr);
-  if (in.o.chain_group == 0 && fit >= A.n) {
-    A.keep = true;
-    return PP_OK;
-  }
-  const int slab = in.o.chain_slab_rows > 0 ? in.o.chain_slab_rows
-                                            : (int)std::min<int64_t>(fit, 1 << 30);
-  PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, scratch, s));
-  PP_TRY_HIP(ppk::launch_bandwidth(A.n, in.A->row_ptr, in.A->col_ind, scratch, s));
-  int32_t bw = 0;
-  PP_TRY_HIP(hipMemcpyAsync(&bw, scratch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  PP_TRY_HIP(hipStreamSynchronize(s));
-  if (in.o.chain_group == 0) {
-    if ((int64_t)bw * kSlabPerBandwidth > slab) return PP_OK;
-    A.blk_group = kAllLaunches;
-  } else {
-    A.blk_group = in.o.chain_group;
-  }
-  A.blk_slab_rows = slab;
-  A.blk_bw_rows = bw;
-  return PP_OK;
+  if (in.ilu) return PP_OK;
+  return choose_schedule<T>(A, in.A, in.o.chain_group, in.o.chain_slab_rows, scratch, s);
 }
 
 // What set_blocking chose, for pp_stats.

@@ -651,6 +651,24 @@ def test_blocked_chain_on_the_csr_layout(B, precision):
     assert s1.iters == s0.iters and torch.equal(x0, x1)
 
 
+@pytest.mark.parametrize("group,slab", [(2, 2048), (40, 1024)])
+def test_blocked_horner_and_product_form_chains(B, group, slab):
+    # the power basis' Horner chain and the product-form operator (A (p(A) v)) in
+    # the slab-skewed order: the same bits as full-range launches
+    P = W.config(2, N=32)
+    A = B.CSRMatrix.from_host(P.A)
+    p, _ = B.pp_build_poly_power(A, _up(P.v0), 8)
+    runs = [dict(poly=p), dict(d=10, op_form="p")]
+    for extra in runs:
+        kw = dict(m=20, d=extra.pop("d", 8), tol=1e-10, v0=_up(P.v0), **extra)
+        x0, s0 = B.pp_gmres_solve(A, _up(P.b), chain_group=1, **kw)
+        x1, s1 = B.pp_gmres_solve(A, _up(P.b), chain_group=group, chain_slab_rows=slab, **kw)
+        x2, s2 = B.pp_gmres_solve(A, _up(P.b), **kw)
+        assert s0.relres_true < 1e-10, extra
+        assert s1.iters == s0.iters and torch.equal(x0, x1), extra
+        assert s2.iters == s0.iters and torch.equal(x0, x2), extra
+
+
 def test_chain_schedule_options_are_checked(B):
     P = W.config(1, N=16)
     A = B.CSRMatrix.from_host(P.A)
