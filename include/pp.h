@@ -161,15 +161,17 @@ typedef struct pp_opts {
                              x = p(M^-1 A) y, the polynomial is built for M^-1 A, and the
                              solve stops on ||M^-1 (b - A x)|| / ||M^-1 b|| < tol.  FP64
                              only; not together with left_jacobi or F32_IR (PP_ERR_ARG). */
-  int32_t chain_group;    /* Schedule of each Arnoldi step's chain (operator form); every
-                             choice gives bit-identical results.  Section VII's reuse of
+  int32_t chain_group;    /* Schedule of the solve's chains (each Arnoldi step's operator,
+                             the cycle-end update, the power basis' Horner chain; pp_apply
+                             always chooses automatically); every choice gives
+                             bit-identical results.  Section VII's reuse of
                              the matrix across products: a launch's working set is its
                              matrix rows plus two vectors (73 B a row for a 7-point
                              stencil in FP64, 37 B in FP32), against a budget of 216 MiB
                              of MI355X's 256 MiB Infinity Cache.
                              0 (automatic): if the working set fits the budget, full-range
                                launches with cached loads and stores; else the slab-skewed
-                               order below over all of a step's launches with slabs that
+                               order below over all of a chain's launches with slabs that
                                fit the budget, when the matrix bandwidth is at most 1/8 of
                                a slab; else full-range non-temporal launches.
                              1: full-range launches, non-temporal loads and stores.
@@ -248,7 +250,8 @@ int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_pol
 /* y = p(A) v.  Passage: Section II (the polynomial object applies p(A) to a vector).
  * Product form in Leja order: for a real root theta, y += prod/theta and
  * prod -= A prod / theta; a pair a +- ib is one real quadratic step with
- * c1 = 2a/|theta|^2, c2 = 1/|theta|^2.  d-1 fused CSR-product + update kernels.
+ * c1 = 2a/|theta|^2, c2 = 1/|theta|^2.  d-1 fused sparse-product + update kernels,
+ * in the schedule pp_opts.chain_group = 0 would choose (bit-identical results).
  *   v, y : device[n] of A's dtype; may not alias.  y is overwritten.
  * Returns PP_OK, PP_ERR_ARG (poly built for another n), PP_ERR_HIP, PP_ERR_NOMEM. */
 int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *stream);
