@@ -150,7 +150,10 @@ def main():
     layout_name = {"sell": "sliced (diagonal slices)", "csr": "CSR"}.get(st.layout_used,
                                                                        st.layout_used)
     roofline = {
-        "kernel": f"k_chain (fused {layout_name} product + Leja root update), FP64",
+        "kernel": f"k_chain (fused {layout_name} product + Leja root update), FP64, "
+                  + (f"slab-skewed over {st.chain_slab_rows:,}-row slabs, cached loads"
+                     if st.chain_slab_rows else
+                     "full-range, " + ("cached" if st.chain_cached else "non-temporal") + " loads"),
         "bound": "hbm",
         "achieved": round(chain_gbps, 1) if chain_gbps else None,
         "peak": HBM_PEAK_GBPS,

@@ -419,6 +419,19 @@ struct ChainEmitter {
     if (launches) ++*launches;
     return op_chain<T>(A, kind, fold, last, a, s);
   }
+  // one plain product out = A (gscale * g); vec_rw as for product_bytes
+  int product(const T *g, const double *gscale, T *out, int vec_rw) {
+    if (bytes) *bytes += product_bytes(A, vec_rw);
+    if (cnt) cnt->spmvs++;
+    if (blocked) {
+      L.push_back(OpLaunch<T>{true, 0, false,
+                              ppk::ChainArgs<T>{g, gscale, nullptr, nullptr, out, nullptr,
+                                                nullptr, 0.0, 0.0, 0.0, nullptr}});
+      return PP_OK;
+    }
+    if (launches) ++*launches;
+    return op_product<T>(A, g, gscale, out, s);
+  }
   // the collected launches, if any
   int finish() {
     if (!blocked || L.empty()) return PP_OK;
@@ -515,42 +528,7 @@ template <typename T>
 int run_op_chain(const Opr<T> &A, const std::vector<ppn::Step> &steps, const T *g,
                  const double *gscale, T *w_out, T *P0, T *P1, T *Tb, hipStream_t s,
                  Counters *cnt, double *bytes = nullptr, int64_t *launches = nullptr) {
-  if (A.blk_group >= 2 && !A.ilu) {
-    std::vector<OpLaunch<T>> L;
-    const int K = (int)steps.size();
-    const T *cur = g;
-    const double *cs = gscale;
-    T *bufs[2] = {P0, P1};
-    int pb = 0;
-    for (int k = 0; k < K; ++k) {
-      const ppn::Step &st = steps[k];
-      const bool last = (k == K - 1);
-      T *dst = last ? w_out : bufs[pb];
-      if (st.kind == 0) {
-        L.push_back({false, 3, last, ppk::ChainArgs<T>{cur, cs, nullptr, nullptr, dst,
-                                                       last ? g : nullptr, nullptr, st.c1, 0.0,
-                                                       0.0, last ? gscale : nullptr}});
-        if (bytes) *bytes += product_bytes(A, 1 + (last ? 1 : 0));
-      } else {
-        L.push_back({true, 0, false, ppk::ChainArgs<T>{cur, cs, nullptr, nullptr, Tb, nullptr,
-                                                       nullptr, 0.0, 0.0, 0.0, nullptr}});
-        L.push_back({false, 2, last, ppk::ChainArgs<T>{Tb, nullptr, cur, cs, dst,
-                                                       last ? g : nullptr, nullptr, st.c1,
-                                                       st.c2, 0.0, last ? gscale : nullptr}});
-        if (bytes) *bytes += product_bytes(A, 1) + product_bytes(A, 2 + (last ? 1 : 0));
-      }
-      cur = dst;
-      cs = nullptr;
-      pb ^= 1;
-    }
-    if (cnt) cnt->spmvs += (int64_t)L.size();
-    return run_op_launches_blocked<T>(A, L, s, launches);
-  }
-  auto account = [&](int vec_rw) {
-    if (bytes) *bytes += product_bytes(A, vec_rw);
-    if (launches) ++*launches;
-    if (cnt) cnt->spmvs++;
-  };
+  ChainEmitter<T> em(A, s, cnt, bytes, launches);
   const int K = (int)steps.size();
   const T *cur = g;
   const double *cs = gscale;
@@ -563,21 +541,18 @@ int run_op_chain(const Opr<T> &A, const std::vector<ppn::Step> &steps, const T *
     if (st.kind == 0) {
       ppk::ChainArgs<T> a{cur, cs, nullptr, nullptr, dst, last ? g : nullptr, nullptr,
                           st.c1, 0.0, 0.0, last ? gscale : nullptr};
-      PP_TRY(op_chain<T>(A, 3, false, last, a, s));
-      account(1 + (last ? 1 : 0));
+      PP_TRY(em.chain(3, false, last, a, 1 + (last ? 1 : 0)));
     } else {
-      PP_TRY(op_product<T>(A, cur, cs, Tb, s));
-      account(1);
+      PP_TRY(em.product(cur, cs, Tb, 1));
       ppk::ChainArgs<T> b{Tb, nullptr, cur, cs, dst, last ? g : nullptr, nullptr,
                           st.c1, st.c2, 0.0, last ? gscale : nullptr};
-      PP_TRY(op_chain<T>(A, 2, false, last, b, s));
-      account(2 + (last ? 1 : 0));
+      PP_TRY(em.chain(2, false, last, b, 2 + (last ? 1 : 0)));
     }
     cur = dst;
     cs = nullptr;
     pb ^= 1;
   }
-  return PP_OK;
+  return em.finish();
 }
 
 template <typename T>
