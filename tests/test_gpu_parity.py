@@ -669,6 +669,31 @@ def test_blocked_horner_and_product_form_chains(B, group, slab):
         assert s2.iters == s0.iters and torch.equal(x0, x2), extra
 
 
+def test_automatic_schedule_past_the_cache_budget(B):
+    # a 160^3 stencil (4.1M rows) is past the cache budget: in natural order
+    # (bandwidth 25,600 rows) the automatic choice is the slab-skewed order; under
+    # a random symmetric permutation (bandwidth ~ n) it falls back to full-range
+    # non-temporal launches.  Both give the bits of chain_group 1.
+    import warnings
+    P = W.config(2, N=160)
+    S = P.A.to_scipy()
+    perm = np.random.default_rng(3).permutation(S.shape[0])
+    Sp = S[perm][:, perm].tocsr()
+    Sp.sort_indices()
+    for Ah, b, v0, blocked in ((S, P.b, P.v0, True), (Sp, P.b[perm], P.v0[perm], False)):
+        A = B.CSRMatrix.from_host(Ah)
+        kw = dict(m=10, d=6, tol=1e-12, v0=_up(v0), max_iters=20)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", B.PPWarning)  # stopped at max_iters
+            x0, s0 = B.pp_gmres_solve(A, _up(b), **kw)
+            x1, s1 = B.pp_gmres_solve(A, _up(b), chain_group=1, **kw)
+        assert s0.iters >= 10 and s1.iters == s0.iters and torch.equal(x0, x1)
+        if blocked:
+            assert s0.chain_cached and 0 < s0.chain_slab_rows < S.shape[0]
+        else:
+            assert (s0.chain_slab_rows, s0.chain_cached) == (0, False)
+
+
 def test_chain_schedule_options_are_checked(B):
     P = W.config(1, N=16)
     A = B.CSRMatrix.from_host(P.A)
