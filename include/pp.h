@@ -45,8 +45,9 @@
  *    (max_iters a multiple of m) resumes exactly from the saved x (as x0) and the
  *    polynomial rebuilt from pp_poly_roots by pp_poly_from_roots.
  *  - Tracing: the environment variable PP_LOG=1 prints one line per restart cycle
- *    (or refinement step) and per ILU(0) factorisation to stderr, PP_LOG=2 also
- *    every Arnoldi step's implicit residual; unset or 0 prints nothing.
+ *    (or refinement step), per ILU(0) factorisation and per solve's chain schedule
+ *    to stderr, PP_LOG=2 also every Arnoldi step's implicit residual; unset or 0
+ *    prints nothing.
  */
 #ifndef PP_H
 #define PP_H

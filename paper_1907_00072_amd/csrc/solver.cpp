@@ -1204,11 +1204,19 @@ int set_blocking(Opr<T> &A, const SolveIn &in, int32_t *scratch, hipStream_t s) 
   return choose_schedule<T>(A, in.A, in.o.chain_group, in.o.chain_slab_rows, scratch, s);
 }
 
-// What set_blocking chose, for pp_stats.
+// What set_blocking chose, for pp_stats and the PP_LOG trace.
 template <typename T>
 void note_schedule(pp_stats *st, const Opr<T> &A) {
-  if (!st) return;
   const bool blocked = A.blk_group >= 2;
+  if (log_level() >= 1) {
+    if (blocked)
+      std::fprintf(stderr, "[pp] chain: slab-skewed, %d-row slabs, bandwidth %d, cached (%s)\n",
+                   A.blk_slab_rows, A.blk_bw_rows, sizeof(T) == 4 ? "FP32" : "FP64");
+    else
+      std::fprintf(stderr, "[pp] chain: full-range, %s (%s)\n",
+                   A.keep ? "cached" : "non-temporal", sizeof(T) == 4 ? "FP32" : "FP64");
+  }
+  if (!st) return;
   st->chain_slab_rows = blocked ? A.blk_slab_rows : 0;
   st->chain_cached = (blocked || A.keep) ? 1 : 0;
 }

@@ -733,6 +733,7 @@ def test_pp_log_traces_cycles_and_steps(B):
     iters = int(r.stdout.split()[1])
     cycles = int(r.stdout.split()[3])
     assert r.stderr.count("[pp] cycle") == cycles
+    assert "[pp] chain: full-range, cached (FP64)" in r.stderr  # the matrix fits the cache
     assert r.stderr.count("implicit relres") >= iters
 
 
