@@ -20,7 +20,10 @@
 //   to keep more bytes in flight.  The root update of the polynomial chain is
 //   fused into the epilogue, so one launch reads A once and the chain vectors
 //   once; streamed data use non-temporal loads and stores so the L2 keeps the
-//   gathered vector.
+//   gathered vector.  A launch may cover a range of tiles only (one slab of a
+//   slab-skewed chain schedule); such launches, and launches over a matrix that
+//   fits the Infinity Cache, take the KEEP instances, whose ordinary loads and
+//   stores leave the slab in the cache for the next launch of the chain.
 // * The CSR path (matrices whose slices would need heavy padding) is a
 //   "CSR-stream" tile: a workgroup owns 256 consecutive rows; its threads
 //   stream the tile's nonzeros contiguously (all index and value loads of a
