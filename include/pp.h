@@ -387,7 +387,10 @@ void pp_release_workspace(void);
 /* Human-readable name of a status code (static string). */
 const char *pp_status_string(int code);
 
-/* Library version string, e.g. "libpp 0.1.0 gfx950". */
+/* Library version string, e.g. "libpp 0.2.0 gfx950".  The minor version changes
+ * whenever a struct of this header changes size or layout (0.2.0: pp_stats gained
+ * chain_slab_rows and chain_cached), so a caller can check it matches the header
+ * it was built with. */
 const char *pp_version(void);
 
 #ifdef __cplusplus

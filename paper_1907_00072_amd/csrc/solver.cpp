@@ -1796,6 +1796,6 @@ const char *pp_status_string(int code) {
   }
 }
 
-const char *pp_version(void) { return "libpp 0.1.0 gfx950"; }
+const char *pp_version(void) { return "libpp 0.2.0 gfx950"; }
 
 }  // extern "C"
