@@ -202,6 +202,10 @@ def test_order_shape(order_tool):
     assert parts[:5] == [(0, 0, 3), (1, 0, 2), (2, 0, 1), (0, 3, 6), (1, 2, 5)]
     # group 1 is the full-range order
     assert order_tool([(7, 100, 2, 3, 1)])[0] == [(0, 0, 7), (1, 0, 7), (2, 0, 7)]
+    # edge cases: no launch; one tile; a diagonal matrix (w = 0: slabs are not skewed)
+    none, one, diag = order_tool([(5, 2, 1, 0, 4), (1, 1, 0, 2, 8), (4, 2, 0, 2, 8)])
+    assert none == [] and one == [(0, 0, 1), (1, 0, 1)]
+    assert diag == [(0, 0, 2), (1, 0, 2), (0, 2, 4), (1, 2, 4)]
 
 
 def test_a_planted_schedule_error_is_caught(order_tool):
