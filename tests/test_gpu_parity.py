@@ -703,6 +703,20 @@ def test_chain_schedule_options_are_checked(B):
         assert e.value.code == B.PP_ERR_ARG
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32_ir"])
+def test_blocked_chain_with_a_ragged_tail(B, precision):
+    # n = 27000: a partial last slice (64 rows), FP64 tile (256) and FP32 tile (512),
+    # and slabs that are not whole tiles (rounded down)
+    P = W.config(2, N=30)
+    A = B.CSRMatrix.from_host(P.A)
+    kw = dict(m=20, d=9, tol=1e-10, v0=_up(P.v0), precision=precision)
+    x0, s0 = B.pp_gmres_solve(A, _up(P.b), chain_group=1, **kw)
+    assert s0.relres_true < 1e-10
+    for group, slab in ((2, 1000), (40, 777), (5, 27000)):
+        x1, s1 = B.pp_gmres_solve(A, _up(P.b), chain_group=group, chain_slab_rows=slab, **kw)
+        assert s1.iters == s0.iters and torch.equal(x0, x1), (group, slab)
+
+
 def test_blocked_chain_with_wide_bandwidth(B):
     # bandwidth about n: each launch trails the previous by more than a slab
     Ah = W.random_csr(3000, 6, seed=12, diag_shift=8.0)
