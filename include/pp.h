@@ -141,8 +141,11 @@ typedef struct pp_opts {
   int32_t precision;      /* PP_PREC_F64 (0) or PP_PREC_F32_IR */
   double inner_tol;       /* F32_IR: inner cycle stops at this relative reduction; 0 -> 1e-5 */
   int32_t max_outer;      /* F32_IR: cap on refinement steps; 0 -> 100 */
-  const double *v0;       /* device[n] start vector for the polynomial; NULL -> use b.
-                             Section V recommends a random vector (e.g. U(-1,1)). */
+  const double *v0;       /* device[n] start vector for the polynomial; NULL -> the
+                             seeded U(-1, 1) vector pp_uniform_vector(n, v0_seed) drawn
+                             on the device.  Section V shows why not b: the polynomial
+                             built from b can swing far below zero on the spectrum
+                             (GMRES(50) then stalls), one from a random vector does not. */
   const pp_poly *poly;    /* reuse this polynomial instead of building one (d ignored) */
   const float *vals_f32;  /* F32_IR: device[nnz] FP32 copy of A's values; NULL -> made internally */
   double *history;        /* host[history_cap]: implicit relative residual after each step */
@@ -185,6 +188,7 @@ typedef struct pp_opts {
   int32_t chain_slab_rows; /* rows per slab (rounded down to whole launch tiles, at least
                               one); 0 -> the budget over the working set per row.
                               Negative: PP_ERR_ARG */
+  uint64_t v0_seed;        /* seed of the start vector drawn when v0 is NULL (0 default) */
 } pp_opts;
 
 /* Solve statistics (all counts follow Section III: a dot is one block inner
@@ -241,7 +245,8 @@ typedef struct pp_stats {
  * in FP64 the harmonic Ritz eigenproblem (Francis double-shift QR) and the
  * modified Leja order.
  *   A   : matrix (PP_F64 or PP_F32)
- *   v0  : device[n] FP64 start vector (cast to A's dtype for the Arnoldi); not modified
+ *   v0  : device[n] FP64 start vector (cast to A's dtype for the Arnoldi); not
+ *         modified.  NULL -> the seeded vector pp_uniform_vector(n, 0).
  *   d   : 1 <= d <= min(n, 256)
  *   out : receives a new pp_poly on success or warning
  * Returns PP_OK, PP_WARN_DEGREE_REDUCED (fewer roots), PP_ERR_ARG, PP_ERR_SINGULAR
@@ -283,7 +288,8 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
  * the normal equations (W^T W) y = W^T v0 solved by a Cholesky factorisation on
  * the host; p(A) = sum_{k=0}^{deg} y_k A^k, applied by Horner's rule (deg fused
  * product + axpy launches).  deg+1 products and two block inner products build it.
- *   A, v0    : as for pp_build_poly (v0 device FP64, not normalised)
+ *   A, v0    : as for pp_build_poly (v0 device FP64, not normalised; NULL -> the
+ *              seeded vector pp_uniform_vector(n, 0))
  *   deg      : 0 <= deg <= 62 and deg + 1 <= n
  *   auto_degree : nonzero -> Section IV's heuristic: factor the Gram matrices of
  *              degrees 0, 1, ..., deg (leading blocks of one matrix) and keep the
@@ -304,13 +310,18 @@ int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_deg
 int pp_poly_coeffs(const pp_poly *p, double *c, int cap, int *n_out);
 
 /* Copy the Leja-ordered roots to host arrays re[cap], im[cap]; *d_out = number
- * of roots.  A complex pair appears as (Im > 0, its conjugate) in adjacent slots.
+ * of roots.  Passage: the paper does not define this call.  The roots are the
+ * harmonic Ritz values that define the polynomial (root form above); exporting
+ * them serves checkpoint/resume (save the roots with x at a restart boundary) and
+ * inspection of alpha p(alpha) on the spectrum as in Section V's figures.  A complex pair appears as (Im > 0, its conjugate) in adjacent slots.
  * Returns PP_ERR_ARG if cap is too small, a pointer is NULL, or p is a
  * power-basis polynomial. */
 int pp_poly_roots(const pp_poly *p, double *re, double *im, int cap, int *d_out);
 
 /* Make a polynomial from given roots (host arrays), e.g. to resume a solve with
- * the roots of an earlier build.  The roots are used in the order given; a
+ * the roots of an earlier build.  Passage: not defined by the paper; the inverse
+ * of pp_poly_roots for checkpoint/resume (p(alpha) is fixed by its roots through
+ * pi(alpha) = prod (1 - alpha/theta_i) = 1 - alpha p(alpha)).  The roots are used in the order given; a
  * complex root must be immediately followed by its exact conjugate, with the
  * Im > 0 member first.  dtype is the value type it will be applied in.
  * Returns PP_ERR_ARG on malformed pairs, PP_ERR_SINGULAR on a zero or
@@ -328,14 +339,22 @@ void pp_poly_free(pp_poly *p);
 int pp_roots_from_hessenberg(const double *Hbar, int ldh, int s, double *re, double *im);
 
 /* Transpose of A in CSR form (the adjoint operator for the backward solve).
+ * Passage: not in the paper.  The backward (adjoint) solve A^T lam = dL/dx of a
+ * differentiable solve is an addition to the paper's method; it runs the same
+ * PP-GMRES on A^T with a polynomial built for A^T.
  * Outputs are caller-allocated device arrays: rp_t[n+1], ci_t[nnz], vals_t[nnz]
- * (A's dtype).  Columns of each output row come out sorted ascending.
+ * (A's dtype).  Columns of each output row come out sorted ascending, entries
+ * with equal columns (duplicates) in A's row order, so the output is the same
+ * on every call.  A column index outside [0, n) is PP_ERR_ARG (checked on the
+ * device before any entry is placed).
  * Returns PP_OK, PP_ERR_ARG, PP_ERR_HIP, PP_ERR_NOMEM. */
 int pp_csr_transpose(const pp_csr *A, int32_t *rp_t, int32_t *ci_t, void *vals_t, void *stream);
 
 /* Gradient of a loss with respect to A's stored values, given the adjoint
  * solution lam (A^T lam = dL/dx) and the forward solution x:
  * g_vals[k] = -lam[row(k)] * x[col(k)] for every stored entry k.
+ * Passage: not in the paper (the adjoint of x = A^-1 b: dL/dA = -lam x^T,
+ * taken on A's stored pattern).
  * All pointers device FP64 (lam[n], x[n], g_vals[nnz]); A's dtype is ignored
  * (only the pattern is read).  Returns PP_OK, PP_ERR_ARG, PP_ERR_HIP. */
 int pp_csr_grad(const pp_csr *A, const double *lam, const double *x, double *g_vals,
@@ -381,16 +400,28 @@ int pp_ilu0_levels(const pp_ilu *M, int32_t *nlev_forward, int32_t *nlev_backwar
 /* Free a factorisation (NULL is ignored); waits for the device first. */
 void pp_ilu0_free(pp_ilu *M);
 
+/* The seeded random start vector of Section V (entries uniform on (-1, 1)), the
+ * one the build and the solve draw when they are given no v0.  Generator:
+ * Philox4x64-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC 2011), a counter-based generator: entry i is word i mod 4 of
+ * the block at counter floor(i/4) + 1 with key (seed, 0) -- the stream of
+ * numpy's Philox(key=(seed, 0)) bit generator -- mapped to 2 (w >> 11) 2^-53 - 1,
+ * so the vector is a pure function of (n, seed), bit for bit on any device.
+ *   out : device[n] FP64, written; 0 < n < 2^40
+ * Synchronises the stream.  Returns PP_OK, PP_ERR_ARG, PP_ERR_HIP. */
+int pp_uniform_vector(int64_t n, uint64_t seed, double *out, void *stream);
+
 /* Free the library's device and pinned-host arena on every device. */
 void pp_release_workspace(void);
 
 /* Human-readable name of a status code (static string). */
 const char *pp_status_string(int code);
 
-/* Library version string, e.g. "libpp 0.2.0 gfx950".  The minor version changes
+/* Library version string, e.g. "libpp 0.3.0 gfx950".  The minor version changes
  * whenever a struct of this header changes size or layout (0.2.0: pp_stats gained
- * chain_slab_rows and chain_cached), so a caller can check it matches the header
- * it was built with. */
+ * chain_slab_rows and chain_cached; 0.3.0: pp_opts gained v0_seed, and a NULL v0
+ * draws the seeded vector instead of using b), so a caller can check it matches
+ * the header it was built with. */
 const char *pp_version(void);
 
 #ifdef __cplusplus

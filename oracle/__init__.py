@@ -21,6 +21,9 @@ adjoint  -- direct-solve adjoint gradient and Sherman-Morrison central
 ilu      -- ILU(0) factors, their triangular solves and dependency levels,
             and GMRES(m) with ILU(0) on the left and the polynomial on the
             right (Section VI, second example).
+rng      -- the seeded U(-1, 1) start vector (Section V) drawn when the
+            caller gives none: Philox4x64-10, written from its published
+            definition.
 
 Every function works in the floating-point type of its vector inputs
 (float64 unless a float32 vector is passed), with all small dense algebra
@@ -32,4 +35,4 @@ numbers printed in Section V (the Laplacian worked example).  Parity
 unpinned: Table I and the counts of Sections III-IV (their Matrix Market
 matrices and random vectors are not available).
 """
-from . import poly, gmres, adjoint, ilu  # noqa: F401
+from . import poly, gmres, adjoint, ilu, rng  # noqa: F401

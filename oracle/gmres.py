@@ -37,6 +37,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .poly import BREAKDOWN_RTOL, apply_poly, apply_power, build_poly, matvec
+from .rng import uniform_pm1
 
 STAGNATION_BAND = 100.0    # the stagnation test applies below this multiple of tol
 STAGNATION_FACTOR = 0.9    # a cycle must reduce the true residual at least this much
@@ -125,18 +126,22 @@ def gmres_cycle(A, r0, roots, m, tol_abs, max_steps, st: GmresStats, coeffs=None
 
 
 def pp_gmres(A, b, m, tol, roots=None, x0=None, max_iters=100000, v0=None, d=None,
-             coeffs=None):
+             coeffs=None, v0_seed=0):
     """Restarted GMRES(m) with p(A) as right preconditioner.
 
     Either pass Leja-ordered ``roots`` (None or empty: no preconditioning), or
     a start vector ``v0`` and the number of roots ``d`` to build them, or the
     power-basis coefficients ``coeffs`` (p(A) = sum_k coeffs[k] A^k; degree
-    len(coeffs)-1, so d = len(coeffs) products per step).
+    len(coeffs)-1, so d = len(coeffs) products per step).  With ``d`` and no
+    ``v0`` the polynomial is built from the seeded U(-1, 1) vector of
+    ``rng.uniform_pm1(n, v0_seed)`` (Section V's random start vector).
     Works in b's dtype.  Returns (x, GmresStats).
     """
     st = GmresStats()
     b = np.asarray(b)
     dt = b.dtype
+    if roots is None and d and v0 is None:
+        v0 = uniform_pm1(b.size, v0_seed)
     if roots is None and d:
         roots, s = build_poly(A, np.asarray(v0, dtype=dt), d)
         st.spmvs += s
@@ -178,7 +183,7 @@ def pp_gmres(A, b, m, tol, roots=None, x0=None, max_iters=100000, v0=None, d=Non
     return x, st
 
 
-def pp_gmres_ir(A, b, m, d, tol, v0, inner_tol=1e-5, max_outer=200, x0=None):
+def pp_gmres_ir(A, b, m, d, tol, v0, inner_tol=1e-5, max_outer=200, x0=None, v0_seed=0):
     """FP32 inner PP-GMRES inside an FP64 iterative-refinement loop.
 
     Outer loop (float64): r = b - A x; stop when ||r||/||b|| < tol; otherwise
@@ -187,10 +192,13 @@ def pp_gmres_ir(A, b, m, d, tol, v0, inner_tol=1e-5, max_outer=200, x0=None):
     update x += ||r|| * p32(A32) V y (update accumulated in float64).
     The float32 polynomial is built once, from a float32 Arnoldi on
     float32(v0); its roots come from the float64 eigen-solve of that Hessenberg.
+    v0 = None draws the seeded vector ``rng.uniform_pm1(n, v0_seed)``.
     Returns (x, GmresStats) with ``st.outer`` = number of refinement steps.
     """
     import scipy.sparse as sp
     b = np.asarray(b, dtype=np.float64)
+    if v0 is None and d:
+        v0 = uniform_pm1(b.size, v0_seed)
     A32 = (sp.csr_matrix(A, dtype=np.float32) if sp.issparse(A)
            else np.asarray(A, dtype=np.float32))
     st = GmresStats()

@@ -22,10 +22,12 @@ class SolveConfig:
     d: int = 15
     tol: float = 1e-12
     v0: Optional[torch.Tensor] = None       # start vector for the forward polynomial
+    v0_seed: int = 0                        # v0 None: seed of the drawn U(-1, 1) vector
     adj_m: Optional[int] = None             # adjoint solve; None -> forward value
     adj_d: Optional[int] = None
     adj_tol: Optional[float] = None
     adj_v0: Optional[torch.Tensor] = None   # start vector for the A^T polynomial
+    adj_v0_seed: int = 0                    # adj_v0 None: seed of the drawn vector
     max_iters: int = 0
     stats: list = field(default_factory=list)  # (phase, Stats) appended per solve
 
@@ -35,7 +37,7 @@ class _PPSolve(torch.autograd.Function):
     def forward(ctx, vals, b, pattern: CSRMatrix, cfg: SolveConfig):
         A = pattern.with_vals(vals.detach().contiguous())
         x, st = pp_gmres_solve(A, b.detach().contiguous(), m=cfg.m, d=cfg.d, tol=cfg.tol,
-                               v0=cfg.v0, max_iters=cfg.max_iters)
+                               v0=cfg.v0, v0_seed=cfg.v0_seed, max_iters=cfg.max_iters)
         cfg.stats.append(("forward", st))
         ctx.save_for_backward(vals, x)
         ctx.pattern = pattern
@@ -51,7 +53,8 @@ class _PPSolve(torch.autograd.Function):
         lam, st = pp_gmres_solve(
             At, gx.detach().contiguous().to(torch.float64),
             m=cfg.adj_m or cfg.m, d=cfg.d if cfg.adj_d is None else cfg.adj_d,
-            tol=cfg.adj_tol or cfg.tol, v0=cfg.adj_v0, max_iters=cfg.max_iters)
+            tol=cfg.adj_tol or cfg.tol, v0=cfg.adj_v0, v0_seed=cfg.adj_v0_seed,
+            max_iters=cfg.max_iters)
         cfg.stats.append(("adjoint", st))
         g_vals = pp_csr_grad(A, lam, x) if ctx.needs_input_grad[0] else None
         g_b = lam if ctx.needs_input_grad[1] else None

@@ -30,7 +30,7 @@ EXPORTS = ("pp_build_poly", "pp_apply", "pp_gmres_solve", "pp_poly_roots", "pp_p
            "pp_poly_free", "pp_roots_from_hessenberg", "pp_csr_transpose", "pp_csr_grad",
            "pp_release_workspace", "pp_status_string", "pp_version", "pp_build_poly_power",
            "pp_poly_coeffs", "pp_ilu0_factor", "pp_ilu0_apply", "pp_ilu0_values",
-           "pp_ilu0_levels", "pp_ilu0_free")
+           "pp_ilu0_levels", "pp_ilu0_free", "pp_uniform_vector")
 
 
 class pp_csr(ctypes.Structure):
@@ -46,7 +46,8 @@ class pp_opts(ctypes.Structure):
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("op_form", ctypes.c_int32),
                 ("left_jacobi", ctypes.c_int32), ("left_ilu", ctypes.c_void_p),
-                ("chain_group", ctypes.c_int32), ("chain_slab_rows", ctypes.c_int32)]
+                ("chain_group", ctypes.c_int32), ("chain_slab_rows", ctypes.c_int32),
+                ("v0_seed", ctypes.c_uint64)]
 
 
 class pp_stats(ctypes.Structure):
@@ -104,11 +105,12 @@ def lib():
     L.pp_ilu0_levels.argtypes = [VP, P(I32), P(I32), P(I32)]
     L.pp_ilu0_free.argtypes = [VP]
     L.pp_ilu0_free.restype = None
+    L.pp_uniform_vector.argtypes = [I64, ctypes.c_uint64, VP, VP]
     for name in ("pp_build_poly", "pp_build_poly_power", "pp_poly_coeffs", "pp_apply",
                  "pp_gmres_solve", "pp_poly_roots",
                  "pp_poly_from_roots", "pp_roots_from_hessenberg", "pp_csr_transpose",
                  "pp_csr_grad", "pp_ilu0_factor", "pp_ilu0_apply", "pp_ilu0_values",
-                 "pp_ilu0_levels"):
+                 "pp_ilu0_levels", "pp_uniform_vector"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -320,9 +322,22 @@ def pp_ilu0_values(M: ILU0, stream=None):
     return lu
 
 
-def pp_build_poly(A: CSRMatrix, v0, d: int, stream=None) -> Poly:
+def pp_uniform_vector(n: int, seed: int = 0, out=None, device="cuda", stream=None):
+    """The seeded U(-1, 1) start vector the library draws when given no v0."""
     torch = _torch()
-    _dev_vec(v0, torch.float64, A.n, "v0")
+    if out is None:
+        out = torch.empty(int(n), dtype=torch.float64, device=device)
+    _dev_vec(out, torch.float64, int(n), "out")
+    _check(lib().pp_uniform_vector(int(n), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out),
+                                   _stream(stream)), "pp_uniform_vector")
+    return out
+
+
+def pp_build_poly(A: CSRMatrix, v0, d: int, stream=None) -> Poly:
+    """Polynomial with d roots from start vector v0 (None: the seeded vector, seed 0)."""
+    torch = _torch()
+    if v0 is not None:
+        _dev_vec(v0, torch.float64, A.n, "v0")
     h = ctypes.c_void_p()
     _check(lib().pp_build_poly(ctypes.byref(A.c()), _ptr(v0), int(d), _stream(stream),
                                ctypes.byref(h)), "pp_build_poly")
@@ -332,7 +347,8 @@ def pp_build_poly(A: CSRMatrix, v0, d: int, stream=None) -> Poly:
 def pp_build_poly_power(A: CSRMatrix, v0, deg: int, auto_degree: bool = False, stream=None):
     """The paper's power-basis polynomial; returns (Poly, info) with info = POTRF's status."""
     torch = _torch()
-    _dev_vec(v0, torch.float64, A.n, "v0")
+    if v0 is not None:
+        _dev_vec(v0, torch.float64, A.n, "v0")
     h = ctypes.c_void_p()
     info = ctypes.c_int()
     _check(lib().pp_build_poly_power(ctypes.byref(A.c()), _ptr(v0), int(deg),
@@ -393,8 +409,12 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
                    max_iters: int = 0, inner_tol: float = 0.0, max_outer: int = 0,
                    vals_f32=None, history: int = 0, timing: bool = False, op_form: str = "pi",
                    left_jacobi: bool = False, left_ilu: Optional[ILU0] = None,
-                   chain_group: int = 0, chain_slab_rows: int = 0, stream=None):
+                   chain_group: int = 0, chain_slab_rows: int = 0, v0_seed: int = 0,
+                   stream=None):
     """Solve A x = b; returns (x, Stats).  ``x`` (if given) is the start guess and is overwritten.
+
+    ``v0``: start vector of the polynomial; None draws the seeded U(-1, 1) vector
+    ``pp_uniform_vector(n, v0_seed)`` on the device.
 
     ``op_form``: "pi" applies A p(A) v as v - pi(A) v (default), "p" as A (p(A) v).
     ``left_ilu``: an ILU(0) of A (pp_ilu0_factor) applied on the left, the
@@ -432,6 +452,7 @@ def pp_gmres_solve(A: CSRMatrix, b, x=None, m: int = 50, d: int = 10, tol: float
         o.left_ilu = left_ilu.handle.value
     o.chain_group = int(chain_group)
     o.chain_slab_rows = int(chain_slab_rows)
+    o.v0_seed = int(v0_seed) & 0xFFFFFFFFFFFFFFFF
     st = pp_stats()
     rc = lib().pp_gmres_solve(ctypes.byref(A.c()), _ptr(b), _ptr(x), int(m), int(d), float(tol),
                               ctypes.byref(o), _stream(stream), ctypes.byref(st))

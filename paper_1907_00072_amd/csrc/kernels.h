@@ -100,6 +100,12 @@ template <typename T>
 hipError_t launch_spmv(const SpMat<T> &A, const T *g, const double *gscale, T *out,
                        hipStream_t stream, int tile0 = 0, int ntiles = 0, bool cached = false);
 
+// *bad |= 1 when the CSR structure is malformed (row_ptr[0] != 0, row_ptr[n] !=
+// nnz, a decreasing row_ptr, or a column outside [0, n)); *bad zeroed by the
+// caller.  Reads only inside row_ptr[n + 1] and col_ind[nnz].
+hipError_t launch_check_csr(int n, int nnz, const int32_t *rp, const int32_t *ci, int32_t *bad,
+                            hipStream_t stream);
+
 // *out = max over stored entries of |column - row| (the matrix bandwidth); *out
 // zeroed by the caller.
 hipError_t launch_bandwidth(int n, const int32_t *rp, const int32_t *ci, int32_t *out,
@@ -180,12 +186,16 @@ hipError_t launch_count_cols(int nnz, const int32_t *ci, int32_t *cnt, hipStream
 hipError_t launch_exclusive_scan(int n, const int32_t *in, int32_t *out, int32_t *tmp,
                                  hipStream_t stream);  // out[0..n], tmp >= scan_tmp_size(n)
 int64_t scan_tmp_size(int n);
+// scatter: entry k of A goes to row ci[k] of the transpose (slot order set by
+// atomics), with k recorded in src_t; sort_rows then orders each row by src,
+// i.e. by column and duplicates by their position in A (deterministic).
 template <typename T>
 hipError_t launch_scatter_transpose(int n, const int32_t *rp, const int32_t *ci, const T *va,
                                     const int32_t *rp_t, int32_t *cursor, int32_t *ci_t, T *va_t,
-                                    hipStream_t stream);
+                                    int32_t *src_t, hipStream_t stream);
 template <typename T>
-hipError_t launch_sort_rows(int n, const int32_t *rp, int32_t *ci, T *va, hipStream_t stream);
+hipError_t launch_sort_rows(int n, const int32_t *rp, int32_t *ci, T *va, int32_t *src,
+                            hipStream_t stream);
 hipError_t launch_csr_grad(int n, const int32_t *rp, const int32_t *ci, const double *lam,
                            const double *x, double *g, hipStream_t stream);
 
@@ -210,6 +220,11 @@ template <typename S, typename D>
 hipError_t launch_slice_fill_vals(int n, int ns, const int32_t *rp, const int32_t *ci, const S *va,
                                   const int32_t *sp, const int32_t *flag, D *sva,
                                   hipStream_t stream);
+
+// out[i] = the seeded U(-1, 1) vector: entry i is word i mod 4 of the
+// Philox4x64-10 block at counter floor(i/4) + 1 with key (seed, 0), mapped to
+// 2 (w >> 11) 2^-53 - 1.  n < 2^40.
+hipError_t launch_uniform_pm1(int64_t n, uint64_t seed, double *out, hipStream_t stream);
 
 // Left Jacobi scaling: va_out[k] = va[k] / a_ii and b_out[i] = b[i] / a_ii for the
 // row i of entry k (a_ii the sum of the row's diagonal entries); *bad is set to 1

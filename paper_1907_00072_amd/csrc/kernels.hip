@@ -751,11 +751,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(int n, int32_t *out,
   if (i < n) out[1 + i] += tmp[i / kScanPerBlock];
 }
 
+// Places entry k = (i, j) of A in row j of the transpose at a slot taken with an
+// atomic cursor (so in no fixed order), recording k in src_t.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter_transpose(
     int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const T *__restrict__ va, const int32_t *__restrict__ rp_t, int32_t *cursor,
-    int32_t *__restrict__ ci_t, T *__restrict__ va_t) {
+    int32_t *__restrict__ ci_t, T *__restrict__ va_t, int32_t *__restrict__ src_t) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   for (int k = rp[i]; k < rp[i + 1]; ++k) {
@@ -763,25 +765,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter_transpose(
     const int pos = rp_t[j] + atomicAdd(&cursor[j], 1);
     ci_t[pos] = i;
     va_t[pos] = va[k];
+    src_t[pos] = k;
   }
 }
 
+// Insertion sort of each row by A's entry index src (unique), which orders the
+// row by column and duplicate columns by their position in A: the same output
+// whatever order the scatter's atomics produced.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sort_rows(int n, const int32_t *__restrict__ rp,
-                                                      int32_t *ci, T *va) {
+                                                      int32_t *ci, T *va, int32_t *src) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int lo = rp[i], hi = rp[i + 1];
   for (int k = lo + 1; k < hi; ++k) {
-    const int key = ci[k];
+    const int key = src[k];
+    const int col = ci[k];
     const T val = va[k];
     int q = k - 1;
-    while (q >= lo && ci[q] > key) {
+    while (q >= lo && src[q] > key) {
+      src[q + 1] = src[q];
       ci[q + 1] = ci[q];
       va[q + 1] = va[q];
       --q;
     }
-    ci[q + 1] = key;
+    src[q + 1] = key;
+    ci[q + 1] = col;
     va[q + 1] = val;
   }
 }
@@ -1157,6 +1166,29 @@ hipError_t launch_spmv(const SpMat<T> &A, const T *g, const double *gscale, T *o
 }
 
 namespace {
+// bad[0] = 1 if the CSR structure is malformed: row_ptr not starting at 0, not
+// ending at nnz or decreasing, or a column index outside [0, n).  Only the rows
+// whose bounds are valid have their columns read, so every access stays inside
+// row_ptr[n + 1] and col_ind[nnz].
+__global__ __launch_bounds__(kBlock) void k_check_csr(int n, int nnz,
+                                                      const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci,
+                                                      int32_t *bad) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int lo = rp[i], hi = rp[i + 1];
+  bool ok = lo >= 0 && hi >= lo && hi <= nnz;
+  if (i == 0) ok = ok && lo == 0;
+  if (i == n - 1) ok = ok && hi == nnz;
+  if (ok) {
+    for (int p = lo; p < hi; ++p) {
+      const int c = ci[p];
+      ok = ok && c >= 0 && c < n;
+    }
+  }
+  if (!ok) atomicOr(bad, 1);
+}
+
 __global__ __launch_bounds__(kBlock) void k_bandwidth(int n, const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ ci,
                                                       int32_t *out) {
@@ -1167,6 +1199,12 @@ __global__ __launch_bounds__(kBlock) void k_bandwidth(int n, const int32_t *__re
   if (w > 0) atomicMax(out, w);
 }
 }  // namespace
+
+hipError_t launch_check_csr(int n, int nnz, const int32_t *rp, const int32_t *ci, int32_t *bad,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL(k_check_csr, dim3(tiles_of(n)), dim3(kBlock), 0, stream, n, nnz, rp, ci, bad);
+  return hipGetLastError();
+}
 
 hipError_t launch_bandwidth(int n, const int32_t *rp, const int32_t *ci, int32_t *out,
                             hipStream_t stream) {
@@ -1342,15 +1380,17 @@ hipError_t launch_exclusive_scan(int n, const int32_t *in, int32_t *out, int32_t
 template <typename T>
 hipError_t launch_scatter_transpose(int n, const int32_t *rp, const int32_t *ci, const T *va,
                                     const int32_t *rp_t, int32_t *cursor, int32_t *ci_t, T *va_t,
-                                    hipStream_t stream) {
+                                    int32_t *src_t, hipStream_t stream) {
   hipLaunchKernelGGL((k_scatter_transpose<T>), dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, rp,
-                     ci, va, rp_t, cursor, ci_t, va_t);
+                     ci, va, rp_t, cursor, ci_t, va_t, src_t);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sort_rows(int n, const int32_t *rp, int32_t *ci, T *va, hipStream_t stream) {
-  hipLaunchKernelGGL((k_sort_rows<T>), dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, rp, ci, va);
+hipError_t launch_sort_rows(int n, const int32_t *rp, int32_t *ci, T *va, int32_t *src,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL((k_sort_rows<T>), dim3(blocks_of(n)), dim3(kBlock), 0, stream, n, rp, ci, va,
+                     src);
   return hipGetLastError();
 }
 
@@ -1402,6 +1442,49 @@ template hipError_t launch_slice_fill_vals<float, float>(int, int, const int32_t
                                                          const int32_t *, const int32_t *, float *,
                                                          hipStream_t);
 
+// ------------------------------------------------- seeded start vector
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011): ten rounds over a 256-bit counter with a 128-bit
+// key; each round multiplies words 0 and 2 by fixed constants, swaps the
+// products' halves into place XORed with words 1, 3 and the key, and the key
+// advances by two Weyl increments between rounds.  Entry i of the vector is
+// word i mod 4 of the block at counter floor(i/4) + 1, key (seed, 0), mapped to
+// 2 (w >> 11) 2^-53 - 1 (exact in FP64, in [-1, 1)).  One thread per block.
+namespace {
+__global__ __launch_bounds__(kBlock) void k_uniform_pm1(int64_t n, uint64_t seed,
+                                                        double *__restrict__ out) {
+  const int64_t blk = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (blk * 4 >= n) return;
+  constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+  uint64_t x0 = (uint64_t)blk + 1, x1 = 0, x2 = 0, x3 = 0;
+  uint64_t k0 = seed, k1 = 0;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(kM0, x0), lo0 = kM0 * x0;
+    const uint64_t hi1 = __umul64hi(kM1, x2), lo1 = kM1 * x2;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+    k0 += kW0;
+    k1 += kW1;
+  }
+  const uint64_t w[4] = {x0, x1, x2, x3};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = blk * 4 + q;
+    if (i < n) out[i] = 2.0 * ((double)(w[q] >> 11) * 0x1.0p-53) - 1.0;
+  }
+}
+}  // namespace
+
+hipError_t launch_uniform_pm1(int64_t n, uint64_t seed, double *out, hipStream_t stream) {
+  const int64_t blocks = (n + 4 * kBlock - 1) / (4 * kBlock);
+  hipLaunchKernelGGL(k_uniform_pm1, dim3((unsigned)blocks), dim3(kBlock), 0, stream, n, seed, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, const double *va,
                                const double *b, double *va_out, double *b_out, int32_t *bad,
                                hipStream_t stream) {
@@ -1433,8 +1516,9 @@ hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, cons
   template hipError_t launch_copy_from_f64<T>(int, const double *, T *, hipStream_t);           \
   template hipError_t launch_scatter_transpose<T>(int, const int32_t *, const int32_t *,        \
                                                   const T *, const int32_t *, int32_t *,        \
-                                                  int32_t *, T *, hipStream_t);                 \
-  template hipError_t launch_sort_rows<T>(int, const int32_t *, int32_t *, T *, hipStream_t);
+                                                  int32_t *, T *, int32_t *, hipStream_t);      \
+  template hipError_t launch_sort_rows<T>(int, const int32_t *, int32_t *, T *, int32_t *,      \
+                                          hipStream_t);
 
 PP_INST(double)
 PP_INST(float)

@@ -61,6 +61,8 @@ constexpr double kCacheBudget = 216.0 * 1024 * 1024;
 constexpr int kSlabPerBandwidth = 8;
 // group size standing for "all of a step's launches"
 constexpr int kAllLaunches = 1 << 20;
+// seed of the start vector drawn when pp_build_poly / pp_build_poly_power get none
+constexpr uint64_t kDefaultSeed = 0;
 
 #define PP_TRY_HIP(expr)                              \
   do {                                                \
@@ -901,6 +903,23 @@ int check_csr(const pp_csr *A) {
   return PP_OK;
 }
 
+// The CSR structure checked on the device before any kernel indexes with it
+// (row_ptr from 0 to nnz and nondecreasing, every column in [0, n)): a
+// malformed matrix is PP_ERR_ARG, never an out-of-bounds access.  One pass over
+// row_ptr and col_ind and one synchronisation.  Uses the head of the arena.
+int validate_csr(const pp_csr *A, hipStream_t s) {
+  Arena *ar = nullptr;
+  PP_TRY(current_arena(&ar));
+  PP_TRY(ensure_arena(ar, 256, 64));
+  int32_t *bad = reinterpret_cast<int32_t *>(ar->dev);
+  PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, bad, s));
+  PP_TRY_HIP(ppk::launch_check_csr((int)A->n, (int)A->nnz, A->row_ptr, A->col_ind, bad, s));
+  int32_t *h = reinterpret_cast<int32_t *>(ar->host);
+  PP_TRY_HIP(hipMemcpyAsync(h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  return h[0] ? PP_ERR_ARG : PP_OK;
+}
+
 // The sliced copy of a call's matrix (see SpMat): built on the device from the
 // CSR arrays into the arena's matrix buffer.  `use` is false when the caller
 // asked for CSR, when the stored slots would not fit int32 offsets, or
@@ -1122,10 +1141,16 @@ int build_impl(const pp_csr *A, const double *v0, int d, hipStream_t s, pp_poly 
   Work<T> w;
   Carver meas(nullptr);
   w.carve(meas, n, d + 1);
+  double *v0gen = v0 ? nullptr : meas.take<double>(n);
   PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
   Carver c(ar->dev);
   w.carve(c, n, d + 1);
   w.host = ar->host;
+  if (!v0) {
+    v0gen = c.take<double>(n);
+    PP_TRY_HIP(ppk::launch_uniform_pm1(n, kDefaultSeed, v0gen, s));
+    v0 = v0gen;
+  }
   Counters cnt;
   Timers tm;
   pp_poly *p = new pp_poly();
@@ -1236,12 +1261,15 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
   double *xsave = meas.take<double>(n);
   double *prod = in.ilu ? meas.take<double>(n) : nullptr;
   int32_t *iscratch = meas.take<int32_t>(64);
+  const bool draw_v0 = !in.o.v0 && !in.o.poly && in.d > 0;
+  double *v0gen = draw_v0 ? meas.take<double>(n) : nullptr;
   PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
   Carver c(ar->dev);
   w.carve(c, n, L);
   xsave = c.take<double>(n);
   prod = in.ilu ? c.take<double>(n) : nullptr;
   iscratch = c.take<int32_t>(64);
+  v0gen = draw_v0 ? c.take<double>(n) : nullptr;
   w.host = ar->host;
   Opr<double> A(with_sell(view<double>(in.A, in.A->vals), sc));
   A.ilu = in.ilu;
@@ -1294,7 +1322,8 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
     steps = PolyRef::of(in.o.poly);
   } else if (in.d > 0) {
     const double t0 = now_s();
-    int rc = build_poly_impl<double>(A, in.o.v0 ? in.o.v0 : in.b, in.d, w, s, cnt, tm, &built);
+    if (draw_v0) PP_TRY_HIP(ppk::launch_uniform_pm1(n, in.o.v0_seed, v0gen, s));
+    int rc = build_poly_impl<double>(A, draw_v0 ? v0gen : in.o.v0, in.d, w, s, cnt, tm, &built);
     if (rc < 0) return rc;
     status = worst(status, rc);
     steps = PolyRef::of(&built);
@@ -1377,6 +1406,8 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
   float *vals32 = cast32 ? meas.take<float>(nnz > 0 ? nnz : 1) : nullptr;
   double *xsave = meas.take<double>(n);
   int32_t *iscratch = meas.take<int32_t>(64);
+  const bool draw_v0 = !in.o.v0 && !in.o.poly && in.d > 0;
+  double *v0gen = draw_v0 ? meas.take<double>(n) : nullptr;
   PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles() + 16));
   Carver c(ar->dev);
   w.carve(c, n, L);
@@ -1384,6 +1415,7 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
   vals32 = cast32 ? c.take<float>(nnz > 0 ? nnz : 1) : nullptr;
   xsave = c.take<double>(n);
   iscratch = c.take<int32_t>(64);
+  v0gen = draw_v0 ? c.take<double>(n) : nullptr;
   w.host = ar->host;
   w64.host = ar->host;
   hipStream_t s = in.s;
@@ -1439,7 +1471,8 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
     steps = PolyRef::of(in.o.poly);
   } else if (in.d > 0) {
     const double t0 = now_s();
-    int rc = build_poly_impl<float>(A32, in.o.v0 ? in.o.v0 : in.b, in.d, w, s, cnt, tm, &built);
+    if (draw_v0) PP_TRY_HIP(ppk::launch_uniform_pm1(n, in.o.v0_seed, v0gen, s));
+    int rc = build_poly_impl<float>(A32, draw_v0 ? v0gen : in.o.v0, in.d, w, s, cnt, tm, &built);
     if (rc < 0) return rc;
     status = worst(status, rc);
     steps = PolyRef::of(&built);
@@ -1513,12 +1546,13 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
 extern "C" {
 
 int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_poly **out) {
-  if (!out || !v0) return PP_ERR_ARG;
+  if (!out) return PP_ERR_ARG;
   *out = nullptr;
   PP_TRY(check_csr(A));
   if (d < 1 || d > kMaxD || d > A->n) return PP_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_lock);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  PP_TRY(validate_csr(A, s));
   return A->dtype == PP_F64 ? build_impl<double>(A, v0, d, s, out)
                             : build_impl<float>(A, v0, d, s, out);
 }
@@ -1528,6 +1562,7 @@ int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *st
   if (!p || !v || !y || v == y || p->n != A->n) return PP_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_lock);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  PP_TRY(validate_csr(A, s));
   return A->dtype == PP_F64 ? apply_impl<double>(A, p, v, y, s)
                             : apply_impl<float>(A, p, v, y, s);
 }
@@ -1550,6 +1585,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
     return PP_ERR_ARG;
   }
   std::lock_guard<std::mutex> lk(g_lock);
+  PP_TRY(validate_csr(A, in.s));
   Arena *ar = nullptr;
   std::unique_lock<std::mutex> ilu_lock;
   if (in.o.left_ilu) {
@@ -1619,13 +1655,14 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
 
 int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_degree,
                         void *stream, pp_poly **out, int *info_out) {
-  if (!out || !v0) return PP_ERR_ARG;
+  if (!out) return PP_ERR_ARG;
   *out = nullptr;
   if (info_out) *info_out = 0;
   PP_TRY(check_csr(A));
   if (deg < 0 || deg > ppk::kMaxCols - 2 || deg + 1 > A->n) return PP_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_lock);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  PP_TRY(validate_csr(A, s));
   Arena *ar = nullptr;
   PP_TRY(current_arena(&ar));
   const int n = (int)A->n, L = deg + 2;
@@ -1637,15 +1674,22 @@ int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_deg
     Carver meas(nullptr);
     w.carve(meas, n, L);
     meas.take<double>((size_t)L * L);
+    if (!v0) meas.take<double>(n);
     PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
     Carver c(ar->dev);
     w.carve(c, n, L);
     double *gram = c.take<double>((size_t)L * L);
     w.host = ar->host;
+    const double *start = v0;
+    if (!v0) {
+      double *v0gen = c.take<double>(n);
+      PP_TRY_HIP(ppk::launch_uniform_pm1(n, kDefaultSeed, v0gen, s));
+      start = v0gen;
+    }
     Counters cnt;
     pp_poly *p = new pp_poly();
     p->dtype = A->dtype;
-    int rc = build_power_impl<T>(with_sell(view<T>(A, A->vals), sc), v0, deg, auto_degree != 0,
+    int rc = build_power_impl<T>(with_sell(view<T>(A, A->vals), sc), start, deg, auto_degree != 0,
                                  w, gram, s, cnt, p, info_out);
     if (rc < 0) {
       delete p;
@@ -1719,15 +1763,18 @@ int pp_csr_transpose(const pp_csr *A, int32_t *rp_t, int32_t *ci_t, void *vals_t
   const int n = (int)A->n, nnz = (int)A->nnz;
   Arena *ar = nullptr;
   PP_TRY(current_arena(&ar));
+  PP_TRY(validate_csr(A, s));
   Carver meas(nullptr);
   meas.take<int32_t>(n);
   meas.take<int32_t>(n);
   meas.take<int32_t>(ppk::scan_tmp_size(n));
+  meas.take<int32_t>(nnz > 0 ? nnz : 1);
   PP_TRY(ensure_arena(ar, meas.off + 256, 64));
   Carver c(ar->dev);
   int32_t *cnt = c.take<int32_t>(n);
   int32_t *cursor = c.take<int32_t>(n);
   int32_t *tmp = c.take<int32_t>(ppk::scan_tmp_size(n));
+  int32_t *src = c.take<int32_t>(nnz > 0 ? nnz : 1);
   PP_TRY_HIP(ppk::launch_fill<int32_t>(n, 0, cnt, s));
   PP_TRY_HIP(ppk::launch_fill<int32_t>(n, 0, cursor, s));
   PP_TRY_HIP(ppk::launch_count_cols(nnz, A->col_ind, cnt, s));
@@ -1736,13 +1783,13 @@ int pp_csr_transpose(const pp_csr *A, int32_t *rp_t, int32_t *ci_t, void *vals_t
     if (A->dtype == PP_F64) {
       PP_TRY_HIP(ppk::launch_scatter_transpose<double>(n, A->row_ptr, A->col_ind,
                                                        (const double *)A->vals, rp_t, cursor,
-                                                       ci_t, (double *)vals_t, s));
-      PP_TRY_HIP(ppk::launch_sort_rows<double>(n, rp_t, ci_t, (double *)vals_t, s));
+                                                       ci_t, (double *)vals_t, src, s));
+      PP_TRY_HIP(ppk::launch_sort_rows<double>(n, rp_t, ci_t, (double *)vals_t, src, s));
     } else {
       PP_TRY_HIP(ppk::launch_scatter_transpose<float>(n, A->row_ptr, A->col_ind,
                                                       (const float *)A->vals, rp_t, cursor, ci_t,
-                                                      (float *)vals_t, s));
-      PP_TRY_HIP(ppk::launch_sort_rows<float>(n, rp_t, ci_t, (float *)vals_t, s));
+                                                      (float *)vals_t, src, s));
+      PP_TRY_HIP(ppk::launch_sort_rows<float>(n, rp_t, ci_t, (float *)vals_t, src, s));
     }
   }
   PP_TRY_HIP(hipStreamSynchronize(s));
@@ -1751,12 +1798,21 @@ int pp_csr_transpose(const pp_csr *A, int32_t *rp_t, int32_t *ci_t, void *vals_t
 
 int pp_csr_grad(const pp_csr *A, const double *lam, const double *x, double *g_vals,
                 void *stream) {
-  if (!A || A->n <= 0 || A->nnz < 0 || !A->row_ptr || !lam || !x ||
-      (A->nnz > 0 && (!A->col_ind || !g_vals)))
+  if (!A || A->n <= 0 || A->nnz < 0 || A->n >= (int64_t)1 << 31 || A->nnz >= (int64_t)1 << 31 ||
+      !A->row_ptr || !lam || !x || (A->nnz > 0 && (!A->col_ind || !g_vals)))
     return PP_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_lock);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  PP_TRY(validate_csr(A, s));
   PP_TRY_HIP(ppk::launch_csr_grad((int)A->n, A->row_ptr, A->col_ind, lam, x, g_vals, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  return PP_OK;
+}
+
+int pp_uniform_vector(int64_t n, uint64_t seed, double *out, void *stream) {
+  if (!out || n <= 0 || n >= ((int64_t)1 << 40)) return PP_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PP_TRY_HIP(ppk::launch_uniform_pm1(n, seed, out, s));
   PP_TRY_HIP(hipStreamSynchronize(s));
   return PP_OK;
 }
@@ -1796,6 +1852,6 @@ const char *pp_status_string(int code) {
   }
 }
 
-const char *pp_version(void) { return "libpp 0.2.0 gfx950"; }
+const char *pp_version(void) { return "libpp 0.3.0 gfx950"; }
 
 }  // extern "C"

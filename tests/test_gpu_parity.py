@@ -276,6 +276,60 @@ def test_transpose_and_grad(B, name):
     assert np.array_equal(g, -lam[rows] * x[Ah.col_ind])
 
 
+def test_transpose_with_duplicates_is_deterministic(B):
+    # duplicate (i, j) entries: the transpose keeps them in A's order, on every call
+    rng = np.random.default_rng(41)
+    n = 300
+    rows = np.sort(rng.integers(0, n, 4000))
+    cols = rng.integers(0, n, 4000)
+    cols[1::9] = cols[::9][: cols[1::9].size]  # plenty of repeats inside rows
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    rp = np.zeros(n + 1, np.int32)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    vals = rng.standard_normal(rows.size)
+    Ah = W.CSR(n, rp, cols.astype(np.int32), vals)
+    A = B.CSRMatrix.from_host(Ah)
+    # the reference: entries ordered by column, ties by their position in A
+    k = np.argsort(cols, kind="stable")
+    ref_rp = np.zeros(n + 1, np.int64)
+    np.add.at(ref_rp, cols + 1, 1)
+    ref_rp = np.cumsum(ref_rp)
+    for _ in range(3):
+        At = B.pp_csr_transpose(A)
+        assert np.array_equal(At.row_ptr.cpu().numpy(), ref_rp)
+        assert np.array_equal(At.col_ind.cpu().numpy(), rows[k])
+        assert np.array_equal(At.vals.cpu().numpy(), vals[k])
+
+
+def test_malformed_csr_is_rejected_before_any_product(B):
+    P = W.config(1, N=16)
+    n = P.A.n
+    b, v0 = _up(P.b), _up(P.v0)
+    bad_col = P.A.col_ind.copy()
+    bad_col[17] = n            # one column past the end
+    neg_col = P.A.col_ind.copy()
+    neg_col[3] = -1
+    bad_rp = P.A.row_ptr.copy()
+    bad_rp[40] = bad_rp[42]    # row_ptr decreasing at row 41
+    short_rp = P.A.row_ptr.copy()
+    short_rp[-1] -= 1          # row_ptr[n] != nnz
+    for rp, ci in ((P.A.row_ptr, bad_col), (P.A.row_ptr, neg_col), (bad_rp, P.A.col_ind),
+                   (short_rp, P.A.col_ind)):
+        A = B.CSRMatrix.from_host(W.CSR(n, rp, ci, P.A.vals), validate=False)
+        calls = (lambda: B.pp_gmres_solve(A, b, m=10, d=4, tol=1e-8, v0=v0),
+                 lambda: B.pp_build_poly(A, v0, 4),
+                 lambda: B.pp_apply(A, B.pp_poly_from_roots(n, [2.0, 3.0]), v0),
+                 lambda: B.pp_csr_transpose(A),
+                 lambda: B.pp_csr_grad(A, v0, b),
+                 lambda: B.pp_build_poly_power(A, v0, 3))
+        for call in calls:
+            with pytest.raises(B.PPError) as e:
+                call()
+            assert e.value.code == B.PP_ERR_ARG
+
+
 def test_adjoint_gradient_reduced_config4(B):
     from paper_1907_00072_amd.autograd import SolveConfig, pp_solve
     P = W.config(4, N=48)
