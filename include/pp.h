@@ -417,11 +417,21 @@ void pp_release_workspace(void);
 /* Human-readable name of a status code (static string). */
 const char *pp_status_string(int code);
 
-/* Library version string, e.g. "libpp 0.3.0 gfx950".  The minor version changes
- * whenever a struct of this header changes size or layout (0.2.0: pp_stats gained
- * chain_slab_rows and chain_cached; 0.3.0: pp_opts gained v0_seed, and a NULL v0
- * draws the seeded vector instead of using b), so a caller can check it matches
- * the header it was built with. */
+/* Where the calling thread's last PP_ERR_HIP came from: "file:line: call ->
+ * hipErrorName" of the first HIP call that failed inside the library since the
+ * thread's last entry into a device call ("" if none).  Static per-thread
+ * string, valid until the thread's next library call.  Every device entry point
+ * first clears any HIP error left pending by earlier runtime calls of the
+ * process (PP_LOG >= 1 reports one on stderr), so a PP_ERR_HIP always names a
+ * call of the library's own.  Passage: not in the paper (error reporting). */
+const char *pp_last_error(void);
+
+/* Library version string, e.g. "libpp 0.4.0 gfx950".  The minor version changes
+ * whenever a struct of this header changes size or layout or an entry point is
+ * added (0.2.0: pp_stats gained chain_slab_rows and chain_cached; 0.3.0: pp_opts
+ * gained v0_seed, and a NULL v0 draws the seeded vector instead of using b;
+ * 0.4.0: pp_last_error), so a caller can check it matches the header it was
+ * built with. */
 const char *pp_version(void);
 
 #ifdef __cplusplus

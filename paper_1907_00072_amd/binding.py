@@ -30,7 +30,7 @@ EXPORTS = ("pp_build_poly", "pp_apply", "pp_gmres_solve", "pp_poly_roots", "pp_p
            "pp_poly_free", "pp_roots_from_hessenberg", "pp_csr_transpose", "pp_csr_grad",
            "pp_release_workspace", "pp_status_string", "pp_version", "pp_build_poly_power",
            "pp_poly_coeffs", "pp_ilu0_factor", "pp_ilu0_apply", "pp_ilu0_values",
-           "pp_ilu0_levels", "pp_ilu0_free", "pp_uniform_vector")
+           "pp_ilu0_levels", "pp_ilu0_free", "pp_uniform_vector", "pp_last_error")
 
 
 class pp_csr(ctypes.Structure):
@@ -98,6 +98,8 @@ def lib():
     L.pp_status_string.restype = ctypes.c_char_p
     L.pp_version.argtypes = []
     L.pp_version.restype = ctypes.c_char_p
+    L.pp_last_error.argtypes = []
+    L.pp_last_error.restype = ctypes.c_char_p
     I32 = ctypes.c_int32
     L.pp_ilu0_factor.argtypes = [CSRP, VP, P(VP)]
     L.pp_ilu0_apply.argtypes = [VP, VP, VP, VP]
@@ -118,8 +120,11 @@ def lib():
 
 class PPError(RuntimeError):
     def __init__(self, code: int, where: str):
-        super().__init__(f"{where}: {pp_status_string(code)} (code {code})")
+        detail = lib().pp_last_error().decode() if code == PP_ERR_HIP else ""
+        super().__init__(f"{where}: {pp_status_string(code)} (code {code})"
+                         + (f" at {detail}" if detail else ""))
         self.code = code
+        self.detail = detail
 
 
 class PPWarning(UserWarning):

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/pp.h"
+#include "diag.h"
 #include "ilu.h"
 #include "kernels.h"
 
@@ -24,11 +25,7 @@ using ppk::Sweep;
 // Frontier passes launched between two reads of the level sizes.
 constexpr int kLevelBatch = 32;
 
-#define ILU_TRY_HIP(expr)                     \
-  do {                                        \
-    hipError_t e_ = (expr);                   \
-    if (e_ != hipSuccess) return PP_ERR_HIP;  \
-  } while (0)
+#define ILU_TRY_HIP(expr) PPD_TRY_HIP(expr, PP_ERR_HIP)
 #define ILU_TRY(expr)            \
   do {                           \
     int r_ = (expr);             \
@@ -264,6 +261,7 @@ double ilu_solve_bytes(const pp_ilu &M) {
 extern "C" {
 
 int pp_ilu0_factor(const pp_csr *A, void *stream, pp_ilu **out) {
+  ppd::enter("pp_ilu0_factor");
   if (!out) return PP_ERR_ARG;
   *out = nullptr;
   if (!A || A->n <= 0 || A->n >= ((int64_t)1 << 31) || A->nnz < A->n ||
@@ -290,6 +288,7 @@ int pp_ilu0_factor(const pp_csr *A, void *stream, pp_ilu **out) {
 }
 
 int pp_ilu0_apply(const pp_ilu *M, const double *r, double *z, void *stream) {
+  ppd::enter("pp_ilu0_apply");
   if (!M || !r || !z || !ppi::on_device(*M)) return PP_ERR_ARG;
   std::lock_guard<std::mutex> lk(M->lock);  // M->work, until the sweeps are done
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -299,6 +298,7 @@ int pp_ilu0_apply(const pp_ilu *M, const double *r, double *z, void *stream) {
 }
 
 int pp_ilu0_values(const pp_ilu *M, double *lu, void *stream) {
+  ppd::enter("pp_ilu0_values");
   if (!M || !lu || !ppi::on_device(*M)) return PP_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ILU_TRY_HIP(hipMemcpyAsync(lu, M->lu, M->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));

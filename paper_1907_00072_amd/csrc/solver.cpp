@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/pp.h"
+#include "diag.h"
 #include "host_numerics.h"
 #include "ilu.h"
 #include "kernels.h"
@@ -64,11 +65,7 @@ constexpr int kAllLaunches = 1 << 20;
 // seed of the start vector drawn when pp_build_poly / pp_build_poly_power get none
 constexpr uint64_t kDefaultSeed = 0;
 
-#define PP_TRY_HIP(expr)                              \
-  do {                                                \
-    hipError_t e_ = (expr);                           \
-    if (e_ != hipSuccess) return PP_ERR_HIP;          \
-  } while (0)
+#define PP_TRY_HIP(expr) PPD_TRY_HIP(expr, PP_ERR_HIP)
 #define PP_TRY(expr)                                  \
   do {                                                \
     int r_ = (expr);                                  \
@@ -80,13 +77,7 @@ std::mutex g_lock;
 // Tracing to stderr, from the environment variable PP_LOG (read once): 0 (default)
 // silent; 1 one line per restart cycle / refinement step; 2 also every Arnoldi
 // step's implicit residual.
-int log_level() {
-  static const int level = [] {
-    const char *v = std::getenv("PP_LOG");
-    return v ? std::atoi(v) : 0;
-  }();
-  return level;
-}
+int log_level() { return ppd::log_level(); }
 
 struct Arena {
   char *dev = nullptr;
@@ -1543,9 +1534,44 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
 }  // namespace
 
 // ====================================================================== C ABI
+namespace ppd {
+
+namespace {
+thread_local char t_detail[320] = "";
+}
+
+int log_level() {
+  static const int level = [] {
+    const char *v = std::getenv("PP_LOG");
+    return v ? std::atoi(v) : 0;
+  }();
+  return level;
+}
+
+hipError_t note(hipError_t e, const char *expr, const char *file, int line) {
+  const char *base = std::strrchr(file, '/');
+  std::snprintf(t_detail, sizeof(t_detail), "%s:%d: %s -> %s", base ? base + 1 : file, line,
+                expr, hipGetErrorName(e));
+  if (log_level() >= 1) std::fprintf(stderr, "[pp] HIP failure at %s\n", t_detail);
+  return e;
+}
+
+const char *last_detail() { return t_detail; }
+
+void enter(const char *entry) {
+  t_detail[0] = '\0';
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess && log_level() >= 1)
+    std::fprintf(stderr, "[pp] %s: cleared a HIP error pending from before the call (%s)\n",
+                 entry, hipGetErrorName(e));
+}
+
+}  // namespace ppd
+
 extern "C" {
 
 int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_poly **out) {
+  ppd::enter("pp_build_poly");
   if (!out) return PP_ERR_ARG;
   *out = nullptr;
   PP_TRY(check_csr(A));
@@ -1558,6 +1584,7 @@ int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_pol
 }
 
 int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *stream) {
+  ppd::enter("pp_apply");
   PP_TRY(check_csr(A));
   if (!p || !v || !y || v == y || p->n != A->n) return PP_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_lock);
@@ -1569,6 +1596,7 @@ int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *st
 
 int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, double tol,
                    const pp_opts *opt, void *stream, pp_stats *st) {
+  ppd::enter("pp_gmres_solve");
   if (st) std::memset(st, 0, sizeof(*st));
   PP_TRY(check_csr(A));
   if (!b || !x || m < 1 || m > kMaxM || !(tol > 0) || d < 0 || d > kMaxD || A->dtype != PP_F64)
@@ -1655,6 +1683,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
 
 int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_degree,
                         void *stream, pp_poly **out, int *info_out) {
+  ppd::enter("pp_build_poly_power");
   if (!out) return PP_ERR_ARG;
   *out = nullptr;
   if (info_out) *info_out = 0;
@@ -1756,6 +1785,7 @@ int pp_roots_from_hessenberg(const double *Hbar, int ldh, int s, double *re, dou
 }
 
 int pp_csr_transpose(const pp_csr *A, int32_t *rp_t, int32_t *ci_t, void *vals_t, void *stream) {
+  ppd::enter("pp_csr_transpose");
   PP_TRY(check_csr(A));
   if (!rp_t || (A->nnz > 0 && (!ci_t || !vals_t))) return PP_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_lock);
@@ -1798,6 +1828,7 @@ int pp_csr_transpose(const pp_csr *A, int32_t *rp_t, int32_t *ci_t, void *vals_t
 
 int pp_csr_grad(const pp_csr *A, const double *lam, const double *x, double *g_vals,
                 void *stream) {
+  ppd::enter("pp_csr_grad");
   if (!A || A->n <= 0 || A->nnz < 0 || A->n >= (int64_t)1 << 31 || A->nnz >= (int64_t)1 << 31 ||
       !A->row_ptr || !lam || !x || (A->nnz > 0 && (!A->col_ind || !g_vals)))
     return PP_ERR_ARG;
@@ -1810,6 +1841,7 @@ int pp_csr_grad(const pp_csr *A, const double *lam, const double *x, double *g_v
 }
 
 int pp_uniform_vector(int64_t n, uint64_t seed, double *out, void *stream) {
+  ppd::enter("pp_uniform_vector");
   if (!out || n <= 0 || n >= ((int64_t)1 << 40)) return PP_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   PP_TRY_HIP(ppk::launch_uniform_pm1(n, seed, out, s));
@@ -1844,7 +1876,8 @@ const char *pp_status_string(int code) {
     case PP_ERR_EIG: return "Hessenberg QR did not converge";
     case PP_ERR_SINGULAR: return "singular Hessenberg, zero start vector, or zero/non-finite root";
     case PP_WARN_DEGREE_REDUCED: return "warning: Arnoldi breakdown, polynomial has fewer roots";
-    case PP_WARN_NOT_CONVERGED: return "warning: iteration cap reached before tolerance";
+    case PP_WARN_NOT_CONVERGED:
+      return "warning: not converged (iteration cap, or stagnation at attainable accuracy)";
     case PP_WARN_NONFINITE: return "warning: non-finite value met, last finite iterate returned";
     case PP_WARN_CHOLESKY:
       return "warning: power-basis Gram matrix not positive definite (POTRF info > 0)";
@@ -1852,6 +1885,8 @@ const char *pp_status_string(int code) {
   }
 }
 
-const char *pp_version(void) { return "libpp 0.3.0 gfx950"; }
+const char *pp_last_error(void) { return ppd::last_detail(); }
+
+const char *pp_version(void) { return "libpp 0.4.0 gfx950"; }
 
 }  // extern "C"

@@ -21,6 +21,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
+from oracle import adjoint as oa  # noqa: E402
 from oracle import gmres as og  # noqa: E402
 from oracle import ilu as oi  # noqa: E402
 from oracle import poly as op  # noqa: E402
@@ -60,6 +61,8 @@ def run(names):
     jobs.append(("stencil27_96_f64_d25", 3, -25))
     jobs.append(("cd3d_256_pe100_d40", 5, 40))
     jobs.append(("recirc2d_257_eps200_ilu0_d13", "ilu", 13))
+    jobs.append(("cd2d_512_pe20_adjoint_d15", "adjoint", 15))
+    jobs.append(("cd3d_128_pe50_ir_d25", "ir128", 25))
     for name, cfg, d in jobs:
         if names and name not in names:
             continue
@@ -74,6 +77,39 @@ def run(names):
                                           max_iters=20000)
             refs[name] = record(name, P, d, x, st, time.time() - t0,
                                 {"relres_original": st.relres_original})
+            json.dump(refs, open(OUT, "w"), indent=1)
+            continue
+        if cfg == "adjoint":
+            # the backward solve of the 512^2 adjoint: PP-GMRES on A^T with its own
+            # polynomial (d = 15, v0 seed 204), right-hand side dL/dx = x - x_t for
+            # L = 0.5 ||x - x_t||^2 at the direct solution x = A^-1 b
+            P = W.config(4)
+            A = P.A.to_scipy()
+            xd = oa.DirectSolver(A).solve(P.b)
+            rhs = xd - P.extra["x_target"]
+            At = A.T.tocsr()
+            t0 = time.time()
+            lam, st = og.pp_gmres(At, rhs, P.m, P.tol, v0=P.extra["v0_adjoint"], d=d,
+                                  max_iters=5000)
+            stop = ("converged" if st.converged else
+                    "iteration cap" if st.iters >= 5000 else "stagnation")
+            rec = record(name, P, d, lam, st, time.time() - t0,
+                         {"stop": stop, "true_history": st.true_history,
+                          "relres_implicit": st.relres_implicit,
+                          "rhs": "x - x_t, x = A^-1 b by SuperLU"})
+            refs[name] = rec
+            json.dump(refs, open(OUT, "w"), indent=1)
+            continue
+        if cfg == "ir128":
+            # FP32 inner PP-GMRES inside FP64 refinement on the 128^3 problem
+            P = W.config(2)
+            A = P.A.to_scipy()
+            t0 = time.time()
+            x, st = og.pp_gmres_ir(A, P.b, P.m, d, P.tol, P.v0, inner_tol=1e-5, max_outer=50)
+            rec = record(name, P, d, x, st, time.time() - t0,
+                         {"outer": st.outer, "inner_tol": 1e-5,
+                          "true_history": st.true_history})
+            refs[name] = rec
             json.dump(refs, open(OUT, "w"), indent=1)
             continue
         P = W.config(cfg)

@@ -23,7 +23,7 @@ def _declared():
 
 def test_every_declared_symbol_is_exported():
     names = _declared()
-    assert len(names) == 20
+    assert len(names) == 21
     L = B.lib()
     for nm in names:
         assert hasattr(L, nm), nm
@@ -35,6 +35,8 @@ def test_version_and_status_strings():
     for code in (0, -1, -2, -3, -4, -5, 1, 2, 3):
         assert B.pp_status_string(code) != "unknown status"
     assert B.pp_status_string(99) == "unknown status"
+    # no device call has failed on this thread: the failure record is empty
+    assert B.lib().pp_last_error() == b""
 
 
 def _rand_hess(s, seed, sub_scale=1.0):

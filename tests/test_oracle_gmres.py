@@ -151,6 +151,32 @@ def test_iterative_refinement_fp32_inner():
     assert np.max(np.abs(np.sort(st.roots.real) - np.sort(r64.real)) / np.abs(np.sort(r64.real))) < 1e-3
 
 
+@pytest.mark.parametrize("cfg,N", [(1, None), (4, 128)])
+def test_iterative_refinement_inner_arithmetic_is_fp32(cfg, N):
+    """The refinement's inner cycle and its polynomial run in FP32, not FP64.
+
+    Pinned by attainable accuracy: a GMRES cycle computed in a precision with
+    unit roundoff u cannot leave a true residual much below u (times modest
+    growth), however small its implicit estimate gets.  With inner_tol = 1e-14
+    one refinement step therefore stops near FP32's u = 6e-8, while the same
+    cycle (same roots, same m) in FP64 goes below 1e-12: a float64 inner cycle
+    would fail the lower bound.  The FP32-built roots differ from the FP64-built
+    ones by FP32 rounding, far above FP64's: a float64 Arnoldi would fail it.
+    """
+    P = W.config(cfg, N=N) if N else W.config(cfg)
+    A = P.A.to_scipy()
+    x, st = gmres.pp_gmres_ir(A, P.b, P.m, P.d, 1e-30, P.v0, inner_tol=1e-14, max_outer=1)
+    assert st.outer == 1 and st.history[-1] < 1e-12      # the implicit estimate went low
+    rr = np.linalg.norm(P.b - A @ x) / np.linalg.norm(P.b)
+    assert 1e-8 < rr < 1e-4, rr
+    _, s64 = gmres.pp_gmres(A, P.b, P.m, 1e-14, roots=st.roots, max_iters=P.m)
+    assert s64.relres_true < 1e-12, s64.relres_true
+    r64, _ = poly.build_poly(A, P.v0, P.d)
+    a, b = np.sort_complex(st.roots), np.sort_complex(r64)
+    diff = np.max(np.abs(a - b) / np.abs(b))
+    assert 1e-9 < diff < 1e-3, diff
+
+
 def test_left_jacobi_composition():
     """Section II composition: the polynomial built for D^-1 A; solution equals A^-1 b."""
     import scipy.sparse as sp
