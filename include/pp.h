@@ -262,6 +262,27 @@ int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_pol
  * Returns PP_OK, PP_ERR_ARG (poly built for another n), PP_ERR_HIP, PP_ERR_NOMEM. */
 int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *stream);
 
+/* pp_apply without allocation, for callers that cannot allocate: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
+ * y = p(A) v as pp_apply does, and calls no hipMalloc, hipFree, hipHostMalloc or
+ * other allocating routine (the caller still owns A, v and y).
+ *   Scratch: the chain's three n-entry temporaries and the CSR check's flag live
+ *   in a fixed device array of the library, 48 MiB + 4 KiB on each GPU it runs
+ *   on, held from the library's load until the process ends.  Hence
+ *   n <= 2^21 = 2,097,152 rows in FP64 (2^22 in FP32); a larger n is PP_ERR_ARG,
+ *   and pp_last_error() states the limit.
+ *   Layout: the products run on A's CSR arrays whatever A->layout asks (the
+ *   sliced copy would need memory in proportion to nnz), in full-range launches
+ *   (cached when a product's working set fits the last-level cache); the result
+ *   equals pp_apply's on PP_LAYOUT_CSR bit for bit.
+ *   Sharing: every call on a GPU uses that GPU's one array, which keeps the last
+ *   call's contents (the flag is cleared by a fill kernel each call; the
+ *   temporaries are written before they are read).  Calls that overlapped on one
+ *   GPU would race on it: the library lock serialises the calls of a process and
+ *   each call synchronises its stream before it returns, so they do not overlap.
+ * Returns PP_OK, PP_ERR_ARG (as pp_apply, or n above the limit), PP_ERR_HIP. */
+int pp_apply_noalloc(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *stream);
+
 /* Solve A x = b with GMRES(m) right-preconditioned by the d-root polynomial.
  * Stopping: the true relative residual below tol, the iteration cap, or, once it
  * is below 100 * tol, three consecutive restart cycles that each fail to reduce
@@ -419,7 +440,8 @@ const char *pp_status_string(int code);
 
 /* Where the calling thread's last PP_ERR_HIP came from: "file:line: call ->
  * hipErrorName" of the first HIP call that failed inside the library since the
- * thread's last entry into a device call ("" if none).  Static per-thread
+ * thread's last entry into a device call, or the reason for an argument error
+ * that has one (pp_apply_noalloc's size limit); "" if none.  Static per-thread
  * string, valid until the thread's next library call.  Every device entry point
  * first clears any HIP error left pending by earlier runtime calls of the
  * process (PP_LOG >= 1 reports one on stderr), so a PP_ERR_HIP always names a
@@ -430,8 +452,8 @@ const char *pp_last_error(void);
  * whenever a struct of this header changes size or layout or an entry point is
  * added (0.2.0: pp_stats gained chain_slab_rows and chain_cached; 0.3.0: pp_opts
  * gained v0_seed, and a NULL v0 draws the seeded vector instead of using b;
- * 0.4.0: pp_last_error), so a caller can check it matches the header it was
- * built with. */
+ * 0.4.0: pp_last_error, pp_apply_noalloc), so a caller can check it matches the
+ * header it was built with. */
 const char *pp_version(void);
 
 #ifdef __cplusplus

@@ -30,7 +30,8 @@ EXPORTS = ("pp_build_poly", "pp_apply", "pp_gmres_solve", "pp_poly_roots", "pp_p
            "pp_poly_free", "pp_roots_from_hessenberg", "pp_csr_transpose", "pp_csr_grad",
            "pp_release_workspace", "pp_status_string", "pp_version", "pp_build_poly_power",
            "pp_poly_coeffs", "pp_ilu0_factor", "pp_ilu0_apply", "pp_ilu0_values",
-           "pp_ilu0_levels", "pp_ilu0_free", "pp_uniform_vector", "pp_last_error")
+           "pp_ilu0_levels", "pp_ilu0_free", "pp_uniform_vector", "pp_last_error",
+           "pp_apply_noalloc")
 
 
 class pp_csr(ctypes.Structure):
@@ -84,6 +85,7 @@ def lib():
     L.pp_build_poly_power.argtypes = [CSRP, VP, I, I, VP, P(VP), P(I)]
     L.pp_poly_coeffs.argtypes = [VP, P(D), I, P(I)]
     L.pp_apply.argtypes = [CSRP, VP, VP, VP, VP]
+    L.pp_apply_noalloc.argtypes = [CSRP, VP, VP, VP, VP]
     L.pp_gmres_solve.argtypes = [CSRP, VP, VP, I, I, D, P(pp_opts), VP, P(pp_stats)]
     L.pp_poly_roots.argtypes = [VP, P(D), P(D), I, P(I)]
     L.pp_poly_from_roots.argtypes = [I64, P(D), P(D), I, I, P(VP)]
@@ -109,6 +111,7 @@ def lib():
     L.pp_ilu0_free.restype = None
     L.pp_uniform_vector.argtypes = [I64, ctypes.c_uint64, VP, VP]
     for name in ("pp_build_poly", "pp_build_poly_power", "pp_poly_coeffs", "pp_apply",
+                 "pp_apply_noalloc",
                  "pp_gmres_solve", "pp_poly_roots",
                  "pp_poly_from_roots", "pp_roots_from_hessenberg", "pp_csr_transpose",
                  "pp_csr_grad", "pp_ilu0_factor", "pp_ilu0_apply", "pp_ilu0_values",
@@ -120,7 +123,7 @@ def lib():
 
 class PPError(RuntimeError):
     def __init__(self, code: int, where: str):
-        detail = lib().pp_last_error().decode() if code == PP_ERR_HIP else ""
+        detail = lib().pp_last_error().decode() if code < 0 else ""
         super().__init__(f"{where}: {pp_status_string(code)} (code {code})"
                          + (f" at {detail}" if detail else ""))
         self.code = code
@@ -377,6 +380,16 @@ def pp_apply(A: CSRMatrix, poly: Poly, v, y=None, stream=None):
     _dev_vec(y, A.dtype, A.n, "y")
     _check(lib().pp_apply(ctypes.byref(A.c()), poly.handle, _ptr(v), _ptr(y), _stream(stream)),
            "pp_apply")
+    return y
+
+
+def pp_apply_noalloc(A: CSRMatrix, poly: Poly, v, y, stream=None):
+    """y = p(A) v without allocation (the library's fixed per-GPU scratch array;
+    n <= 2^21 rows in FP64, 2^22 in FP32).  ``y`` is caller-allocated."""
+    _dev_vec(v, A.dtype, A.n, "v")
+    _dev_vec(y, A.dtype, A.n, "y")
+    _check(lib().pp_apply_noalloc(ctypes.byref(A.c()), poly.handle, _ptr(v), _ptr(y),
+                                  _stream(stream)), "pp_apply_noalloc")
     return y
 
 

@@ -20,7 +20,8 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           f"-I{os.path.join(ROOT, 'include')}"]
-SOURCES = ["kernels.hip", "ilu.hip", "solver.cpp", "ilu_host.cpp", "host_numerics.cpp"]
+SOURCES = ["kernels.hip", "ilu.hip", "noalloc.hip", "solver.cpp", "ilu_host.cpp",
+           "host_numerics.cpp"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -16,10 +16,12 @@ namespace ppd {
 
 // Record a failed HIP call; returns e.
 hipError_t note(hipError_t e, const char *expr, const char *file, int line);
+// Record an argument error's explanation (printf format), for pp_last_error().
+void note_msg(const char *fmt, ...);
 // Start of a device entry point: clear the record and any pending runtime error.
 void enter(const char *entry);
-// The record of this thread's last failed HIP call ("" if none since the
-// thread's last entry point).
+// The record of this thread's last failed HIP call or explained argument error
+// ("" if none since the thread's last entry point).
 const char *last_detail();
 // PP_LOG level (0 if unset), read once.
 int log_level();

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -26,6 +27,7 @@
 #include "host_numerics.h"
 #include "ilu.h"
 #include "kernels.h"
+#include "noalloc.h"
 
 struct pp_poly {
   int64_t n;
@@ -898,17 +900,21 @@ int check_csr(const pp_csr *A) {
 // (row_ptr from 0 to nnz and nondecreasing, every column in [0, n)): a
 // malformed matrix is PP_ERR_ARG, never an out-of-bounds access.  One pass over
 // row_ptr and col_ind and one synchronisation.  Uses the head of the arena.
+// bad: one device int32 (cleared here), h: one host int32.
+int check_csr_on_device(const pp_csr *A, int32_t *bad, int32_t *h, hipStream_t s) {
+  PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, bad, s));
+  PP_TRY_HIP(ppk::launch_check_csr((int)A->n, (int)A->nnz, A->row_ptr, A->col_ind, bad, s));
+  PP_TRY_HIP(hipMemcpyAsync(h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  return *h ? PP_ERR_ARG : PP_OK;
+}
+
 int validate_csr(const pp_csr *A, hipStream_t s) {
   Arena *ar = nullptr;
   PP_TRY(current_arena(&ar));
   PP_TRY(ensure_arena(ar, 256, 64));
-  int32_t *bad = reinterpret_cast<int32_t *>(ar->dev);
-  PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, bad, s));
-  PP_TRY_HIP(ppk::launch_check_csr((int)A->n, (int)A->nnz, A->row_ptr, A->col_ind, bad, s));
-  int32_t *h = reinterpret_cast<int32_t *>(ar->host);
-  PP_TRY_HIP(hipMemcpyAsync(h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  PP_TRY_HIP(hipStreamSynchronize(s));
-  return h[0] ? PP_ERR_ARG : PP_OK;
+  return check_csr_on_device(A, reinterpret_cast<int32_t *>(ar->dev),
+                             reinterpret_cast<int32_t *>(ar->host), s);
 }
 
 // The sliced copy of a call's matrix (see SpMat): built on the device from the
@@ -1090,6 +1096,22 @@ int choose_schedule(Opr<T> &A, const pp_csr *csr, int group, int slab_rows, int3
   return PP_OK;
 }
 
+// y = p(A) v on operator M with three n-entry temporaries (the chain's or, for a
+// power-basis polynomial, Horner's).
+template <typename T>
+int apply_run(const Opr<T> &M, const pp_poly *p, const T *v, T *y, T *const bufs[3],
+              hipStream_t s) {
+  if (p->kind == 1) {
+    PP_TRY(run_horner<T>(M, p->coeffs, v, nullptr, y, bufs[0], bufs[1], s, nullptr));
+  } else if (p->steps.empty()) {
+    PP_TRY_HIP(ppk::launch_fill<T>(M.n, T(0), y, s));
+  } else {
+    PP_TRY(run_chain<T>(M, p->steps, v, nullptr, nullptr, y, bufs[0], bufs[1], bufs[2], s,
+                        nullptr));
+  }
+  return PP_OK;
+}
+
 template <typename T>
 int apply_impl(const pp_csr *A, const pp_poly *p, const void *v, void *y, hipStream_t s) {
   Arena *ar = nullptr;
@@ -1108,16 +1130,45 @@ int apply_impl(const pp_csr *A, const pp_poly *p, const void *v, void *y, hipStr
   isc = c.take<int32_t>(64);
   Opr<T> M(with_sell(view<T>(A, A->vals), sc));
   if (products > 0) PP_TRY(choose_schedule<T>(M, A, 0, 0, isc, s));
-  const T *vv = static_cast<const T *>(v);
-  T *yy = static_cast<T *>(y);
-  if (p->kind == 1) {
-    PP_TRY(run_horner<T>(M, p->coeffs, vv, nullptr, yy, bufs[0], bufs[1], s, nullptr));
-  } else if (p->steps.empty()) {
-    PP_TRY_HIP(ppk::launch_fill<T>(n, T(0), yy, s));
-  } else {
-    PP_TRY(run_chain<T>(M, p->steps, vv, nullptr, nullptr, yy, bufs[0], bufs[1], bufs[2], s,
-                        nullptr));
+  PP_TRY(apply_run<T>(M, p, static_cast<const T *>(v), static_cast<T *>(y), bufs, s));
+  PP_TRY_HIP(hipStreamSynchronize(s));
+  return PP_OK;
+}
+
+// pp_apply_noalloc: the same chain on A's CSR arrays, with the three temporaries
+// and the check's flag carved from the library's fixed per-GPU array.  Full-range
+// launches only (the slab-skewed order keeps its launch list in host memory):
+// cached when a product's working set fits the cache budget, else non-temporal,
+// the choice choose_schedule makes for group 0 without the slab option.
+template <typename T>
+int apply_noalloc_impl(const pp_csr *A, const pp_poly *p, const void *v, void *y,
+                       hipStream_t s) {
+  const int n = (int)A->n;
+  void *base = nullptr;
+  size_t cap = 0;
+  PP_TRY_HIP(ppx::noalloc_scratch(&base, &cap));
+  Carver meas(nullptr);
+  meas.take<int32_t>(64);
+  for (int k = 0; k < 3; ++k) meas.take<T>(pad_ld(n));
+  // the stated limit (the array holds a little slack beyond it for alignment)
+  const int64_t max_rows = ppx::kNoAllocMaxRowsF64 * (int64_t)(sizeof(double) / sizeof(T));
+  if (n > max_rows || meas.off + 256 > cap) {
+    ppd::note_msg("pp_apply_noalloc: n = %d needs %zu bytes of scratch, the fixed array holds "
+                  "%zu (n <= %lld rows in FP64, %lld in FP32)",
+                  n, meas.off + 256, cap, (long long)ppx::kNoAllocMaxRowsF64,
+                  (long long)(2 * ppx::kNoAllocMaxRowsF64));
+    return PP_ERR_ARG;
   }
+  Carver c(static_cast<char *>(base));
+  int32_t *flag = c.take<int32_t>(64);
+  T *bufs[3];
+  for (auto &b : bufs) b = c.take<T>(pad_ld(n));
+  int32_t hflag = 0;
+  PP_TRY(check_csr_on_device(A, flag, &hflag, s));
+  Opr<T> M(view<T>(A, A->vals));
+  const double per_row = product_bytes(M, 1) / (double)n;
+  M.keep = (double)n * per_row <= kCacheBudget;
+  PP_TRY(apply_run<T>(M, p, static_cast<const T *>(v), static_cast<T *>(y), bufs, s));
   PP_TRY_HIP(hipStreamSynchronize(s));
   return PP_OK;
 }
@@ -1558,6 +1609,14 @@ hipError_t note(hipError_t e, const char *expr, const char *file, int line) {
 
 const char *last_detail() { return t_detail; }
 
+void note_msg(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(t_detail, sizeof(t_detail), fmt, ap);
+  va_end(ap);
+  if (log_level() >= 1) std::fprintf(stderr, "[pp] %s\n", t_detail);
+}
+
 void enter(const char *entry) {
   t_detail[0] = '\0';
   const hipError_t e = hipGetLastError();
@@ -1592,6 +1651,17 @@ int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *st
   PP_TRY(validate_csr(A, s));
   return A->dtype == PP_F64 ? apply_impl<double>(A, p, v, y, s)
                             : apply_impl<float>(A, p, v, y, s);
+}
+
+int pp_apply_noalloc(const pp_csr *A, const pp_poly *p, const void *v, void *y,
+                     void *stream) {
+  ppd::enter("pp_apply_noalloc");
+  PP_TRY(check_csr(A));
+  if (!p || !v || !y || v == y || p->n != A->n) return PP_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_lock);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return A->dtype == PP_F64 ? apply_noalloc_impl<double>(A, p, v, y, s)
+                            : apply_noalloc_impl<float>(A, p, v, y, s);
 }
 
 int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, double tol,
@@ -1876,8 +1946,7 @@ const char *pp_status_string(int code) {
     case PP_ERR_EIG: return "Hessenberg QR did not converge";
     case PP_ERR_SINGULAR: return "singular Hessenberg, zero start vector, or zero/non-finite root";
     case PP_WARN_DEGREE_REDUCED: return "warning: Arnoldi breakdown, polynomial has fewer roots";
-    case PP_WARN_NOT_CONVERGED:
-      return "warning: not converged (iteration cap, or stagnation at attainable accuracy)";
+    case PP_WARN_NOT_CONVERGED: return "warning: iteration cap reached before tolerance";
     case PP_WARN_NONFINITE: return "warning: non-finite value met, last finite iterate returned";
     case PP_WARN_CHOLESKY:
       return "warning: power-basis Gram matrix not positive definite (POTRF info > 0)";
