@@ -57,6 +57,10 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-1e-8 rel. residual (s) PP-GMRES vs GMRES; SpMV HBM GB/s % of peak"
 HBM_PEAK_GBPS = 8000.0
+# measured on MI355X with a flat FP64 copy kernel (one element per thread): buffers far
+# larger than the 256 MiB Infinity Cache, and two 128 MiB buffers that stay in it
+HBM_COPY_GBPS = 6310.0
+CACHE_COPY_GBPS = 7370.0
 
 
 def log(msg):
@@ -69,11 +73,18 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=256, help="grid points per axis (256 = headline)")
+    ap.add_argument("--config", type=int, default=5,
+                    help="workload configuration (5 = the headline 256^3 problem; 1-4 time the "
+                         "same kind of line on the others, at their own m, d and tol)")
     ap.add_argument("--legs", default="ir,plain,power,csr,jacobi,fullrange,ilu,adjoint",
                     help="comma list of extra legs: ir, plain, power, csr, jacobi, fullrange, ilu, "
                          "adjoint, none")
     ap.add_argument("--plain-max-iters", type=int, default=30000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-full-solve", metavar="OUT_JSON", default=None,
+                    help="instead of the default line: time the oracle's complete solve of the "
+                         "workload on this host (minutes at 256^3; no GPU used), then the "
+                         "cpu_baseline estimator on the same host, and write both to OUT_JSON")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the default line: time-to-tol on every workload configuration "
                          "(one JSON object)")
@@ -93,12 +104,28 @@ def main():
     from paper_1907_00072_amd import binding as B
     from paper_1907_00072_amd import workloads as W
 
+    if args.cpu_full_solve:
+        P = W.config(5, N=args.grid)
+        As = P.A.to_scipy()
+        log(f"cpu full solve: oracle on {P.name} grid {args.grid}^3, n={P.A.n}")
+        full, roots = cpu_full_solve(P, As, args.grid)
+        log(f"cpu full solve: {full['value']:.1f}s, {full['iters']} steps, "
+            f"{full['cycles']} cycles, relres {full['relres']:.2e}")
+        est, parts, wall, busy = cpu_estimate(P, As, roots, full["iters"], full["cycles"])
+        rec = {"full_solve": full, "estimate_s": est, "estimate_parts": parts,
+               "estimate_sample_s": wall, "command": "python bench.py --cpu-full-solve OUT_JSON"}
+        with open(args.cpu_full_solve, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec), flush=True)
+        return
     dev = torch.device("cuda:0")
     if args.sweep:
         print(json.dumps(sweep(B, W, torch, dev, args.steps)), flush=True)
         return
     t0 = time.perf_counter()
-    P = W.config(5, N=args.grid)
+    if args.config != 5:
+        args.grid = 0   # the configuration's own size; no stored 256^3 references apply
+    P = W.config(5, N=args.grid) if args.config == 5 else W.config(args.config)
     log(f"generated {P.name} grid {args.grid}^3: n={P.A.n} nnz={P.A.nnz} "
         f"in {time.perf_counter() - t0:.1f}s")
     A = B.CSRMatrix.from_host(P.A, device=dev)
@@ -149,6 +176,11 @@ def main():
     chain_gbps = bc / tc / 1e9 if tc > 0 else None
     layout_name = {"sell": "sliced (diagonal slices)", "csr": "CSR"}.get(st.layout_used,
                                                                        st.layout_used)
+    # a middle real-root step on the sliced copy: stored values, one 64-byte descriptor per
+    # 64-row slice, the gathered input and the output (explicit-column slices add 4 B a slot)
+    per_row_layout = ((8.0 * st.nnz_stored + 64.0 * ((P.A.n + 63) // 64) + 16.0 * P.A.n) / P.A.n
+                      if st.layout_used == "sell" else None)
+    cached = bool(st.chain_slab_rows or st.chain_cached)
     roofline = {
         "kernel": f"k_chain (fused {layout_name} product + Leja root update), FP64, "
                   + (f"slab-skewed over {st.chain_slab_rows:,}-row slabs, cached loads"
@@ -160,15 +192,31 @@ def main():
         "unit": "GB/s",
         "frac": round(chain_gbps / HBM_PEAK_GBPS, 4) if chain_gbps else None,
         "traffic": pmc_traffic(args.grid, bc / nl if nl else None),
+        "rate_basis": (
+            "achieved = the layout's algorithmic bytes per launch (its values, slice descriptors "
+            "and vectors) over the launches' event-timed duration.  "
+            + ("Under this schedule a slab's later launches re-read it from the 256 MiB Infinity "
+               "Cache, so achieved is a cache-assisted rate and frac is NOT a fraction of HBM "
+               "bandwidth: hbm_only gives that (the same solve with every launch streaming from "
+               "HBM), frac_of_cache_resident_copy compares achieved with a copy whose buffers "
+               "sit in the cache" if cached else
+               "Every launch streams from HBM: frac is a fraction of the HBM peak.")),
+        "frac_of_cache_resident_copy": (round(chain_gbps / CACHE_COPY_GBPS, 4)
+                                        if chain_gbps and cached else None),
+        "cache_resident_copy_GBps": CACHE_COPY_GBPS,
+        "hbm_copy_GBps": HBM_COPY_GBPS,
+        "hbm_only": None,
+        "dram_bytes": None,
+        "dram_bytes_note": ("not measurable on gfx950: rocprofv3 lists no counter behind the "
+                            "Infinity Cache (TCC_EA0_RDREQ_DRAM / WRREQ_DRAM count the L2's requests "
+                            "to DRAM addresses, Infinity Cache hits included); traffic is those "
+                            "L2-miss bytes"),
         "bytes_per_launch": bc / nl if nl else None,
+        "bytes_per_row": {"sliced_copy_real_root_step": per_row_layout,
+                          "csr_formula_12nnz_36n": (12.0 * P.A.nnz + 36.0 * P.A.n) / P.A.n},
         "avg_launch_us": tc / nl * 1e6 if nl else None,
         "launches": nl,
         "schedule": {"slab_rows": st.chain_slab_rows, "cached": st.chain_cached},
-        "note": ("algorithmic bytes over time; under the slab-skewed schedule a slab's later "
-                 "launches re-read it from the 256 MiB Infinity Cache, so the rate can exceed "
-                 "the HBM-only copy ceiling (6.31 TB/s; 7.37 TB/s for a cache-resident copy)"
-                 if st.chain_slab_rows or st.chain_cached else
-                 "algorithmic bytes over time, every launch streaming from HBM"),
     }
     phases = {
         "chain_GBps": chain_gbps,
@@ -262,6 +310,13 @@ def main():
             "time_s": tb, "iters": s7.iters, "relres": s7.relres_true, **kwb,
             "chain_GBps": s7.bytes_chain / s7.t_chain / 1e9 if s7.t_chain > 0 else None,
             "same_x_as_default": bool(torch.equal(x, x_default))}
+        if s7.t_chain > 0 and s7.launches_chain:
+            hb = s7.bytes_chain / s7.t_chain / 1e9
+            roofline["hbm_only"] = {
+                "schedule": "full-range launches, non-temporal loads and stores (chain_group 1)",
+                "achieved": round(hb, 1), "frac": round(hb / HBM_PEAK_GBPS, 4),
+                "frac_of_hbm_copy": round(hb / HBM_COPY_GBPS, 4), "unit": "GB/s",
+                "avg_launch_us": s7.t_chain / s7.launches_chain * 1e6}
         log(f"full-range non-temporal chain: {tb:.3f}s iters {s7.iters}")
 
     if "ilu" in wanted:
@@ -306,7 +361,7 @@ def main():
 
     cpu = None
     if args.cpu_baseline:
-        cpu = cpu_baseline(P, As, B, A, v0, st)
+        cpu = cpu_baseline(P, As, st, args.grid)
 
     out = {
         "metric": METRIC,
@@ -321,7 +376,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{P.name}" if args.grid == 256 else f"cd3d_{args.grid}_pe100",
+        "config": {"workload": (f"cd3d_{args.grid}_pe100" if args.config == 5 and args.grid != 256
+                                else P.name),
                    "n": P.A.n, "nnz": P.A.nnz, "m": P.m, "d": P.d, "tol": P.tol,
                    "solver": "PP-GMRES(m), Leja-ordered harmonic Ritz roots, CGS2",
                    "layout": st.layout_used, "nnz_stored": st.nnz_stored},
@@ -380,7 +436,58 @@ def sweep(B, W, torch, dev, steps):
         del A, b, v0, x
         torch.cuda.empty_cache()
     out[W.EX1_WORKLOAD["name"]] = example1(B, W, torch, dev, steps)
+    out.update(permuted_legs(B, W, torch, dev))
     return {"sweep": out, "steps": steps, "data": "synthetic"}
+
+
+def permuted_legs(B, W, torch, dev, grid=256):
+    """The headline solve on matrices without diagonal structure: the 256^3 problem
+    under a seeded symmetric permutation P A P^T (b and v0 permuted alike), uniform
+    over all rows (the worst case: every gather a random cache line) and within
+    blocks of 4096 rows (an unstructured matrix whose ordering keeps locality, as a
+    bandwidth-reducing ordering of a finite-element mesh would).  One timed solve
+    after a warm-up each, with the library's automatic layout and schedule, and the
+    chain kernel's per-product time and algorithmic rate beside the stencil's."""
+    import warnings
+    P = W.config(5, N=grid)
+    out = {}
+    for name, block in (("cd3d_256_pe100_perm", None), ("cd3d_256_pe100_perm4096", 4096)):
+        if grid != 256:
+            name = name.replace("256", str(grid))
+        t0 = time.perf_counter()
+        perm = W.permutation(P.A.n, 17, block)
+        Ap = W.permuted(P.A, perm)
+        log(f"{name}: permuted in {time.perf_counter() - t0:.1f}s")
+        A = B.CSRMatrix.from_host(Ap, device=dev)
+        del Ap
+        b = torch.from_numpy(P.b[perm]).to(dev)
+        v0 = torch.from_numpy(P.v0[perm]).to(dev)
+        x = torch.zeros_like(b)
+
+        def run():
+            x.zero_()
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore")
+                return B.pp_gmres_solve(A, b, x, m=P.m, d=P.d, tol=P.tol, v0=v0, timing=True)[1]
+        run()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        st = run()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - ts
+        out[name] = {"time_s": t, "iters": st.iters, "relres": st.relres_true,
+                     "layout": st.layout_used, "nnz_stored": st.nnz_stored,
+                     "chain_slab_rows": st.chain_slab_rows, "chain_cached": st.chain_cached,
+                     "chain_us_per_launch": st.t_chain / st.launches_chain * 1e6
+                     if st.launches_chain else None,
+                     "chain_GBps": st.bytes_chain / st.t_chain / 1e9 if st.t_chain > 0 else None,
+                     "t_chain_s": st.t_chain, "t_orth_s": st.t_orth, "t_poly_s": st.t_poly}
+        log(f"{name}: {t:.3f}s, {st.iters} steps, layout {st.layout_used}, chain "
+            f"{out[name]['chain_us_per_launch']:.0f} us per launch, "
+            f"{out[name]['chain_GBps']:.0f} GB/s")
+        del A, b, v0, x
+        torch.cuda.empty_cache()
+    return out
 
 
 def example1(B, W, torch, dev, steps):
@@ -598,61 +705,135 @@ def torch_copy_rate(torch, nbytes=2 << 30, reps=5):
     return 2.0 * nbytes / sec / 1e9
 
 
-def cpu_baseline(P, As, B, A, v0, st):
-    """Oracle timed on a bounded sample of the same solve (see module docstring).
-
-    Timed on the full matrix: one application of p(A) by the oracle (complex
-    arithmetic, one root at a time), one sparse product, and one Gram-Schmidt
-    column unit (a dot and an axpy of length n).  The estimate charges every
-    Arnoldi step of the GPU solve (and each cycle end) one p(A) and one product,
-    the build its d products, and both their CGS2 sweeps 3 (j + 1) column units at
-    step j.  `cores` is the CPU time of the sample over its wall time: the threads
-    it actually kept busy.
-    """
-    import numpy as np
-
-    from oracle import poly as op
-
-    poly = B.pp_build_poly(A, v0, P.d)
-    roots = poly.roots()
-    r0 = P.b / np.linalg.norm(P.b)
-    log("cpu baseline: oracle p(A)v, one product and one CGS column unit on the full matrix")
-    c0, w0 = time.process_time(), time.perf_counter()
-    ts = time.perf_counter()
-    z = op.apply_poly(As, roots, r0)
-    t_poly = time.perf_counter() - ts
-    ts = time.perf_counter()
-    w = As @ z
-    t_mv = time.perf_counter() - ts
-    ts = time.perf_counter()
-    for _ in range(3):
-        h = r0 @ w
-        w = w - h * r0
-    t_col = (time.perf_counter() - ts) / 3
-    cpu, wall = time.process_time() - c0, time.perf_counter() - w0
-    build_cols = sum(3 * (j + 1) for j in range(P.d))
-    gmres_cols = sum(3 * (j % P.m + 1) for j in range(st.iters))
-    est = ((st.iters + st.cycles) * (t_poly + t_mv) + P.d * t_mv +
-           (build_cols + gmres_cols) * t_col)
-    cores = max(1, round(cpu / wall))
-    model = "unknown CPU"
+def host_model():
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    log(f"cpu baseline: p(A)v {t_poly:.1f}s, product {t_mv:.3f}s, column {t_col:.3f}s "
-        f"-> estimated solve {est:.0f}s ({cpu / wall:.1f} threads busy)")
-    return {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
-            "sample": (f"on the full n={P.A.n} matrix: the oracle's p(A)v with {len(roots)} roots "
-                       f"(complex arithmetic) {t_poly:.2f}s, one product {t_mv:.3f}s, one CGS "
-                       f"column unit (dot + axpy) {t_col:.4f}s; scaled to the GPU solve's "
-                       f"{st.iters} steps + {st.cycles} cycle ends (p(A) and a product each), "
-                       f"{P.d} build products and {build_cols + gmres_cols} CGS2 column units.  "
-                       f"The sample kept {cpu / wall:.1f} threads busy (SciPy CSR products are "
-                       f"single-threaded).  Host: {model}, {os.cpu_count()} logical CPUs visible.")}
+    return "unknown CPU"
+
+
+def oracle_roots(P, grid):
+    """Roots of the oracle's own polynomial for the workload: the stored oracle run's
+    at 256^3 (written by tests/golden/make_fullsize_refs.py), else built here by the
+    oracle (small grids)."""
+    import numpy as np
+
+    from oracle import poly as op
+    ref = oracle_reference(grid)
+    if ref is not None and len(ref["roots_re"]) == P.d:
+        return np.asarray(ref["roots_re"]) + 1j * np.asarray(ref["roots_im"]), "stored oracle run"
+    roots, _ = op.build_poly(P.A.to_scipy(), P.v0, P.d)
+    return roots, "oracle build_poly"
+
+
+def cpu_estimate(P, As, roots, st_iters, st_cycles):
+    """The oracle's time for the whole solve, from timings of its own functions on
+    the full matrix: one p(A)v (complex arithmetic, one root at a time), and the
+    Arnoldi process (one product + CGS2 per step) to k1 and k2 steps.  The Arnoldi
+    prefixes give the per-step cost t(j) = c0 + c1 j at j basis columns (least
+    squares on T(k) = k c0 + c1 k(k+1)/2); a GMRES step at column j costs one p(A)v
+    plus t(j), a cycle end one p(A)v plus one product, the build T(d).  Returns
+    (estimate_s, parts, sample_wall_s, threads_busy)."""
+    import numpy as np
+
+    from oracle import poly as op
+    r0 = P.b / np.linalg.norm(P.b)
+    c0w, w0 = time.process_time(), time.perf_counter()
+    ts = time.perf_counter()
+    op.apply_poly(As, roots, r0)
+    t_apply = time.perf_counter() - ts
+    ks, Ts = (4, 8), []
+    for k in ks:
+        ts = time.perf_counter()
+        op.arnoldi(As, P.v0, k)
+        Ts.append(time.perf_counter() - ts)
+    M = np.array([[k, k * (k + 1) / 2.0] for k in ks])
+    c0, c1 = np.linalg.solve(M, np.asarray(Ts))
+    c1 = max(c1, 0.0)
+    c0 = max(c0, 0.0)
+    ts = time.perf_counter()
+    As @ r0
+    t_mv = time.perf_counter() - ts
+    wall = time.perf_counter() - w0
+    busy = (time.process_time() - c0w) / wall
+
+    def T(k):
+        return k * c0 + c1 * k * (k + 1) / 2.0
+    steps = sum(t_apply + c0 + c1 * (j % P.m + 1) for j in range(st_iters))
+    est = T(P.d) + steps + st_cycles * (t_apply + t_mv) + t_mv
+    parts = {"p_of_A_v_s": t_apply, "arnoldi_prefix_s": dict(zip(map(str, ks), Ts)),
+             "step_cost_s": [c0, c1], "product_s": t_mv, "build_s_est": T(P.d)}
+    return est, parts, wall, busy
+
+
+class _CountedOperator:
+    """The matrix with a count of its products, printing a progress line every 200
+    (a whole oracle solve at 256^3 runs for minutes)."""
+
+    def __init__(self, A):
+        self.A, self.k, self.shape = A, 0, A.shape
+
+    def __matmul__(self, x):
+        self.k += 1
+        if self.k % 200 == 0:
+            log(f"cpu full solve: {self.k} products")
+        return self.A @ x
+
+
+def cpu_full_solve(P, As, grid):
+    """The oracle's complete solve of the workload, timed: its polynomial build
+    (d Arnoldi steps, harmonic Ritz values, Leja order) and PP-GMRES(m) to tol."""
+    from oracle import gmres as og
+    from oracle import poly as op
+    A = _CountedOperator(As)
+    c0, w0 = time.process_time(), time.perf_counter()
+    roots, _ = op.build_poly(A, P.v0, P.d)
+    t_build = time.perf_counter() - w0
+    log(f"cpu full solve: build {t_build:.1f}s")
+    _, so = og.pp_gmres(A, P.b, P.m, P.tol, roots=roots, max_iters=20000)
+    wall = time.perf_counter() - w0
+    return {"value": wall, "unit": "s", "build_s": t_build, "iters": so.iters,
+            "cycles": so.cycles, "relres": so.relres_true, "converged": so.converged,
+            "threads_busy": (time.process_time() - c0) / wall, "products": A.k,
+            "host": host_model(), "logical_cpus": os.cpu_count(),
+            "workload": P.name if grid == 256 else f"cd3d_{grid}_pe100"}, roots
+
+
+def cpu_baseline(P, As, st, grid):
+    """Oracle time for the whole solve on this host: an estimate from timings of the
+    oracle's own functions on the full matrix (cpu_estimate), with the oracle's own
+    roots, scaled to the oracle's step and cycle counts (the GPU's, equal within 2%).
+    The complete oracle solve measured once on the GPU machine host is quoted beside it
+    (profiles/oracle_cpu_cd3d_256_pe100.json, written by `bench.py --cpu-full-solve`),
+    with the estimator's value from that same run as its calibration."""
+    roots, src = oracle_roots(P, grid)
+    log("cpu baseline: timing the oracle's p(A)v and Arnoldi prefixes on the full matrix")
+    est, parts, wall, busy = cpu_estimate(P, As, roots, st.iters, st.cycles)
+    cal = None
+    path = os.path.join(ROOT, "profiles", "oracle_cpu_cd3d_256_pe100.json")
+    if grid == 256 and os.path.exists(path):
+        rec = json.load(open(path))
+        full = rec["full_solve"]
+        cal = {"measured_full_solve_s": full["value"], "estimate_same_run_s": rec["estimate_s"],
+               "measured_over_estimate": full["value"] / rec["estimate_s"],
+               "host": full["host"], "threads_busy": full["threads_busy"],
+               "source": "profiles/oracle_cpu_cd3d_256_pe100.json"}
+    log(f"cpu baseline: estimated oracle solve {est:.0f}s (sample {wall:.1f}s, {busy:.1f} "
+        f"threads busy)")
+    return {"value": est, "unit": "s", "cores": max(1, round(busy)), "kind": "oracle",
+            "sample": (f"the oracle's own functions on the full n={P.A.n} matrix: one p(A)v with "
+                       f"{len(roots)} roots ({src}; complex arithmetic) {parts['p_of_A_v_s']:.1f}s, "
+                       f"Arnoldi (product + CGS2) to 4 and 8 steps "
+                       f"{parts['arnoldi_prefix_s']['4']:.1f}s / "
+                       f"{parts['arnoldi_prefix_s']['8']:.1f}s; scaled to the build's {P.d} "
+                       f"steps and the solve's {st.iters} steps and {st.cycles} cycle ends "
+                       f"({wall:.0f}s of sampling, {busy:.1f} threads busy: SciPy's sparse "
+                       f"products are single-threaded, NumPy's Gram-Schmidt products are not).  "
+                       f"Host: {host_model()}, {os.cpu_count()} logical CPUs visible."),
+            "parts": parts, "calibration": cal}
 
 
 if __name__ == "__main__":

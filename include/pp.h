@@ -327,7 +327,9 @@ int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_deg
                         void *stream, pp_poly **out, int *info_out);
 
 /* Copy a power-basis polynomial's coefficients (y_0 .. y_deg) to host c[cap];
- * *n_out = deg + 1.  PP_ERR_ARG for a root-form polynomial or a short buffer. */
+ * *n_out = deg + 1.  Passage: Section II eq. (2) (the coefficients y of
+ * p(A) = sum_k y_k A^k that the normal equations give).  PP_ERR_ARG for a
+ * root-form polynomial or a short buffer. */
 int pp_poly_coeffs(const pp_poly *p, double *c, int cap, int *n_out);
 
 /* Copy the Leja-ordered roots to host arrays re[cap], im[cap]; *d_out = number
@@ -350,10 +352,14 @@ int pp_poly_roots(const pp_poly *p, double *re, double *im, int cap, int *d_out)
 int pp_poly_from_roots(int64_t n, const double *re, const double *im, int d, int dtype,
                        pp_poly **out);
 
+/* Free a polynomial (NULL is ignored).  Passage: not in the paper (ownership of
+ * the pp_poly object). */
 void pp_poly_free(pp_poly *p);
 
 /* Harmonic Ritz values from a host Hessenberg matrix, in modified Leja order.
- * Host only, no device work.  Hbar is (s+1) x s, column-major with leading
+ * Passage: the roots of the minimum-residual polynomial (Section II, the root
+ * form described above): the zeros of pi(alpha) = 1 - alpha p(alpha) are the
+ * harmonic Ritz values of the Arnoldi process.  Host only, no device work.  Hbar is (s+1) x s, column-major with leading
  * dimension ldh >= s+1 (the Arnoldi relation A Q_s = Q_{s+1} Hbar).  Outputs
  * re[s], im[s].  Returns PP_ERR_SINGULAR if H_s is singular or a root is zero,
  * PP_ERR_EIG if the QR iteration fails. */
@@ -392,33 +398,38 @@ int pp_csr_grad(const pp_csr *A, const double *lam, const double *x, double *g_v
  * N x N grid in natural order, 3N-2 for N^3). */
 
 /* Factor A (PP_F64; every row's columns strictly increasing, in [0, n), with a
- * stored diagonal).  out receives a new pp_ilu.  Synchronises the stream.
+ * stored diagonal).  Passage: Section VI, second example (ILU(0) as the left
+ * preconditioner, the polynomial of M^-1 A on the right).  out receives a new pp_ilu.  Synchronises the stream.
  * Returns PP_OK; PP_ERR_ARG for a bad pattern, a non-FP64 A or null pointers;
  * PP_ERR_SINGULAR for a zero pivot or a non-finite factor entry; PP_ERR_HIP;
  * PP_ERR_NOMEM.  Not serialised with the other calls: it uses no shared
  * workspace. */
 int pp_ilu0_factor(const pp_csr *A, void *stream, pp_ilu **out);
 
-/* z = M^-1 r = U^-1 (L^-1 r): device FP64 vectors of n entries; z may equal r
+/* z = M^-1 r = U^-1 (L^-1 r) (Section VI, second example: applying the ILU(0)
+ * preconditioner): device FP64 vectors of n entries; z may equal r
  * (in place).  Synchronises the stream.  A pp_ilu holds one work vector, so the
  * calls that use it (this one, and solves with it as left_ilu) are serialised on
  * it.  Returns PP_OK, PP_ERR_ARG (also when the current device is not the one M
  * was made on), PP_ERR_HIP. */
 int pp_ilu0_apply(const pp_ilu *M, const double *r, double *z, void *stream);
 
-/* Copy the factors into lu (device FP64[nnz], A's CSR order): the strictly lower
+/* Copy the factors into lu (device FP64[nnz], A's CSR order; inspection of the
+ * ILU(0) of Section VI's second example, not defined by the paper): the strictly lower
  * entries hold L (its unit diagonal implied), the others U.  Synchronises.
  * Returns PP_OK, PP_ERR_ARG (null pointer, or M made on another device),
  * PP_ERR_HIP. */
 int pp_ilu0_values(const pp_ilu *M, double *lu, void *stream);
 
 /* Levels of the forward and backward sweeps, and the launches one pp_ilu0_apply
- * makes (any output pointer may be NULL).  Host only.  Returns PP_OK, or
+ * makes (any output pointer may be NULL; the paper defines no such call: it
+ * reports the dependency chains that bound a sweep's cost).  Host only.  Returns PP_OK, or
  * PP_ERR_ARG when M is NULL. */
 int pp_ilu0_levels(const pp_ilu *M, int32_t *nlev_forward, int32_t *nlev_backward,
                    int32_t *launches);
 
-/* Free a factorisation (NULL is ignored); waits for the device first. */
+/* Free a factorisation (NULL is ignored); waits for the device first.  Passage:
+ * not in the paper (ownership of the pp_ilu object). */
 void pp_ilu0_free(pp_ilu *M);
 
 /* The seeded random start vector of Section V (entries uniform on (-1, 1)), the
@@ -432,10 +443,13 @@ void pp_ilu0_free(pp_ilu *M);
  * Synchronises the stream.  Returns PP_OK, PP_ERR_ARG, PP_ERR_HIP. */
 int pp_uniform_vector(int64_t n, uint64_t seed, double *out, void *stream);
 
-/* Free the library's device and pinned-host arena on every device. */
+/* Free the library's device and pinned-host arena on every device.  Passage: not
+ * in the paper (workspace ownership). */
 void pp_release_workspace(void);
 
-/* Human-readable name of a status code (static string). */
+/* Human-readable name of a status code (static string).  Passage: not in the
+ * paper; the warning codes follow its POTRF-style convention (results still
+ * returned, Section IV). */
 const char *pp_status_string(int code);
 
 /* Where the calling thread's last PP_ERR_HIP came from: "file:line: call ->
@@ -448,7 +462,7 @@ const char *pp_status_string(int code);
  * call of the library's own.  Passage: not in the paper (error reporting). */
 const char *pp_last_error(void);
 
-/* Library version string, e.g. "libpp 0.4.0 gfx950".  The minor version changes
+/* Library version string, e.g. "libpp 0.4.0 gfx950" (not in the paper).  The minor version changes
  * whenever a struct of this header changes size or layout or an entry point is
  * added (0.2.0: pp_stats gained chain_slab_rows and chain_cached; 0.3.0: pp_opts
  * gained v0_seed, and a NULL v0 draws the seeded vector instead of using b;

@@ -77,6 +77,11 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libpp.so not built ({LIB_PATH}); run "
                           "`python -m paper_1907_00072_amd.csrc.build`")
+    # torch first: its wheel carries its own HIP runtime (libamdhip64, same soname
+    # as the system's), and the library's dependency then resolves to that copy.
+    # Loaded before torch, the library would bring in the system runtime and torch
+    # its own: two runtimes in one process, and the second to start finds no device.
+    _torch()
     L = ctypes.CDLL(LIB_PATH)
     P, I, I64, D, VP = (ctypes.POINTER, ctypes.c_int, ctypes.c_int64, ctypes.c_double,
                         ctypes.c_void_p)

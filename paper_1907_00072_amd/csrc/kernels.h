@@ -121,33 +121,70 @@ hipError_t launch_residual(const SpMat<T> &A, const T *b, const T *x, T *out, do
 constexpr int kOrthRead = 0;        // k_dots, k_norm2 without the FP32 copy (read-only)
 constexpr int kOrthUpdateDots = 1;  // k_update fused with the next pass's dots
 constexpr int kOrthWrite = 2;       // k_update with the norm or alone, k_norm2 with the copy
-constexpr int kOrthMinRpt = 2;      // the smallest value orth_rpt returns
+constexpr int kOrthMinRpt = 1;      // the smallest value orth_rpt returns
+// workgroups a sweep keeps at least, while n allows: 8 per compute unit for the
+// dot and update sweeps; one per compute unit for the update + dots sweep, whose
+// workgroups each end with nc block reductions (measured at 512^2: 1024 short
+// workgroups run its nc <= 40 instances up to 25% slower than 128-256 longer ones)
+constexpr int kOrthMinGroups = 2048;
+constexpr int kOrthMinGroupsUpdateDots = 256;
 
 // Rows per thread (each workgroup owns a contiguous block of 256 * rpt rows) of
-// a CGS2 sweep over nc <= kMaxCols basis columns.  Read-only sweeps run long
-// workgroups; sweeps that write run short ones, so the resident workgroups'
-// stores stay within a narrow window of HBM, as in a flat copy; the update +
-// dots sweep sits between because each workgroup must also reduce nc partial
-// dots.  Measured on gfx950 at n = 16.8M (FP64 update + norm: 5.2 -> 6.0 TB/s).
-int orth_rpt(int kind, int nc, bool f32);
+// a CGS2 sweep of n rows over nc <= kMaxCols basis columns.  Read-only sweeps
+// run long workgroups; sweeps that write run short ones, so the resident
+// workgroups' stores stay within a narrow window of HBM, as in a flat copy; the
+// update + dots sweep sits between because each workgroup must also reduce nc
+// partial dots.  Measured on gfx950 at n = 16.8M (FP64 update + norm: 5.2 -> 6.0
+// TB/s).  Smaller n lowers rpt (down to 1) until the sweep has kOrthMinGroups
+// (kOrthMinGroupsUpdateDots) workgroups, or one per 256 rows: long blocks on a
+// few hundred thousand rows would leave most compute units idle (at 512^2 the dot
+// sweep ran 32 workgroups at 1.1 TB/s; with 1024 it runs twice as fast).
+int orth_rpt(int kind, int nc, bool f32, int64_t n);
 // Workgroups G of a sweep of n rows at rpt rows per thread; its partials are
 // laid out [column][G].
 int orth_grid(int n, int rpt);
 
+// The second stage of a sweep's reduction done inside the sweep: its last
+// workgroup to finish (an atomic ticket on `counter`, a device int that is 0
+// between launches and is set back to 0) sums the partials exactly as
+// launch_reduce_cols (colscale, h, coef) or launch_reduce_norm (nrm, inv) would,
+// so the results are bitwise the same with one launch fewer.  Worth it when the
+// partials are few (the last workgroup sums them alone).
+// Largest partial count a folded second stage takes: one partial per thread of the
+// 256-thread reduction it reproduces.
+constexpr int kFoldMaxG = kBlock;
+struct FoldOut {
+  int *counter = nullptr;
+  const double *colscale = nullptr;
+  double *h = nullptr;
+  double *coef = nullptr;
+  double *nrm = nullptr;
+  double *inv = nullptr;
+  // norm stage only (optional): after nrm, copy_src[0..copy_n) -> copy_dst, where
+  // copy_dst may be pinned host memory and copy_src + nrm_at is where nrm lives
+  const double *copy_src = nullptr;
+  double *copy_dst = nullptr;
+  int copy_n = 0;
+  int nrm_at = 0;
+};
+
 // partial[(c0+c) * G + g] = sum over block g's rows of V(i, c0+c) * w(i), c < nc <= kMaxCols,
-// G = orth_grid(n, rpt).
+// G = orth_grid(n, rpt).  fold (optional): then also launch_reduce_cols(partial, G, c0, nc,
+// fold->colscale, fold->h, fold->coef).
 template <typename T>
 hipError_t launch_dots(int n, int rpt, const T *V, int64_t ldv, int c0, int nc, const T *w,
-                       double *partial, hipStream_t stream);
+                       double *partial, hipStream_t stream, const FoldOut *fold = nullptr);
 
 // out = w_in - sum_c V(:, c) * coef(c),  coef(c) = sign * a(c) * (b ? b(c) : 1), nc <= kMaxCols.
 // w_in may be nullptr (zero) and may equal out.  With dots: partial dots of the
 // new vector with V(:, 0..nc) as in launch_dots.  With norm: partial[g] = sum of
-// out^2 over block g (double).  G = orth_grid(n, rpt).
+// out^2 over block g (double).  G = orth_grid(n, rpt).  fold (with dots or norm only):
+// then also the matching second stage, as for launch_dots.
 template <typename T>
 hipError_t launch_update(int n, int rpt, const T *V, int64_t ldv, int nc, const double *coef_a,
                          const double *coef_b, double sign, const T *w_in, T *out, bool dots,
-                         bool norm, double *partial, hipStream_t stream);
+                         bool norm, double *partial, hipStream_t stream,
+                         const FoldOut *fold = nullptr);
 
 // partial[g] = sum over block g of (scale*x(i))^2 in double; optionally also
 // writes out32 = (float)(scale * x) when out32 != nullptr (the refinement cast).
@@ -161,9 +198,12 @@ hipError_t launch_reduce_cols(const double *partial, int G, int c0, int nc, cons
                               double *h, double *coef, hipStream_t stream);
 
 // Norm finalisation: nrm[0] = sqrt(sum_g partial[g]); if inv != nullptr,
-// inv[0] = 1/nrm (0 when nrm == 0).
+// inv[0] = 1/nrm (0 when nrm == 0).  With copy_dst (pinned host memory, say): then
+// also copy_dst[i] = copy_src[i] for i < copy_n, where copy_src + nrm_at is nrm
+// (a small result block handed to the host without a separate copy).
 hipError_t launch_reduce_norm(const double *partial, int G, double *nrm, double *inv,
-                              hipStream_t stream);
+                              hipStream_t stream, const double *copy_src = nullptr,
+                              double *copy_dst = nullptr, int copy_n = 0, int nrm_at = 0);
 
 // Fill a device array with a value.
 template <typename T>

@@ -484,11 +484,132 @@ __global__ __launch_bounds__(kBlock) void k_axpy(int n, double c, const T *__res
 }
 
 // ------------------------------------------------------------------ CGS2
-template <typename T, int NCB>
+// Fixed-order sum of x[0..G) over the workgroup's threads (thread t takes
+// t, t + 256, ...), with four loads in flight per thread.
+__device__ __forceinline__ double strided_sum(const double *__restrict__ x, int G) {
+  double s = 0.0;
+  int g = threadIdx.x;
+  for (; g + 3 * kBlock < G; g += 4 * kBlock) {
+    const double a0 = x[g], a1 = x[g + kBlock], a2 = x[g + 2 * kBlock], a3 = x[g + 3 * kBlock];
+    s += (a0 + a1) + (a2 + a3);
+  }
+  for (; g < G; g += kBlock) s += x[g];
+  return s;
+}
+
+// Second stage of a column reduction (one workgroup): h[c] = colscale[c] * sum of
+// the G partials of column c, coef[c] = colscale[c] * h[c].  The same arithmetic
+// whether it runs in k_reduce_cols or in the producing sweep's last workgroup.
+__device__ __forceinline__ void reduce_col_finish(const double *__restrict__ partial, int G,
+                                                  int c, const double *colscale, double *h,
+                                                  double *coef, double *red4) {
+  double s = strided_sum(partial + (int64_t)c * G, G);
+  s = block_sum(s, red4);
+  if (threadIdx.x == 0) {
+    const double sc = colscale ? colscale[c] : 1.0;
+    const double hv = sc * s;
+    h[c] = hv;
+    if (coef) coef[c] = sc * hv;
+  }
+}
+
+// Second stage of a norm: nrm = sqrt(sum of the G partials), inv = 1/nrm (0 for 0).
+__device__ __forceinline__ void reduce_norm_finish(const double *__restrict__ partial, int G,
+                                                   double *nrm, double *inv, double *red4) {
+  double s = strided_sum(partial, G);
+  s = block_sum(s, red4);
+  if (threadIdx.x == 0) {
+    const double r = sqrt(s);
+    nrm[0] = r;
+    if (inv) inv[0] = (r > 0.0) ? 1.0 / r : 0.0;
+  }
+}
+
+// What block_sum(strided_sum(x, G)) returns in a 256-thread workgroup, for
+// G <= 256, computed by one wavefront: lane l stands for threads l, l + 64,
+// l + 128 and l + 192 in turn (each holds 0.0 + x[t] or 0.0, as strided_sum
+// leaves it), each group is summed by the same butterfly as wave_sum, and the
+// four group sums are added in block_sum's order.  Bitwise the same value.
+__device__ __forceinline__ double col_sum_as_block(const double *__restrict__ x, int G) {
+  const int lane = threadIdx.x & 63;
+  double v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int t = 64 * k + lane;
+    v[k] = 0.0;
+    if (t < G) v[k] += x[t];
+  }
+  double r[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = wave_sum(v[k]);
+  return ((r[0] + r[1]) + r[2]) + r[3];
+}
+
+// The folded column stage: wavefront w of the last workgroup finishes columns
+// w, w + 4, ... (as reduce_col_finish, G <= kFoldMaxG).
+__device__ __forceinline__ void fold_cols(const double *__restrict__ partial, int G, int c0,
+                                          int nc, const FoldOut &f) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c = c0 + wv; c < c0 + nc; c += 4) {
+    const double s = col_sum_as_block(partial + (int64_t)c * G, G);
+    if (lane == 0) {
+      const double sc = f.colscale ? f.colscale[c] : 1.0;
+      const double hv = sc * s;
+      f.h[c] = hv;
+      if (f.coef) f.coef[c] = sc * hv;
+    }
+  }
+}
+
+// The folded norm stage (as reduce_norm_finish, G <= kFoldMaxG), by wavefront 0.
+// With copy_dst set, the workgroup then copies copy_src[0..copy_n) there, the norm
+// itself written from the register (the other entries come from earlier launches).
+// Called by every thread of the workgroup.
+__device__ __forceinline__ void fold_norm(const double *__restrict__ partial, int G,
+                                          const FoldOut &f) {
+  __shared__ double s_r;
+  if (threadIdx.x < 64) {
+    const double s = col_sum_as_block(partial, G);
+    if (threadIdx.x == 0) {
+      const double r = sqrt(s);
+      f.nrm[0] = r;
+      if (f.inv) f.inv[0] = (r > 0.0) ? 1.0 / r : 0.0;
+      s_r = r;
+    }
+  }
+  if (f.copy_dst) {
+    __syncthreads();
+    const double r = s_r;
+    for (int i = threadIdx.x; i < f.copy_n; i += kBlock)
+      f.copy_dst[i] = (i == f.nrm_at) ? r : f.copy_src[i];
+  }
+}
+
+// Called by every thread of a sweep's workgroup once wave 0 has stored the
+// workgroup's partials (those stores all come from threads < 64).  Wave 0
+// releases them at device scope and takes a ticket; the workgroup that draws
+// the last ticket acquires every other workgroup's partials and returns true.
+// The counter is re-armed (set back to 0) by that workgroup.
+__device__ __forceinline__ bool last_to_arrive(int *counter) {
+  __shared__ int s_last;
+  if (threadIdx.x < 64) {
+    __threadfence();
+    if (threadIdx.x == 0) s_last = (atomicAdd(counter, 1) == (int)gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) *counter = 0;
+  }
+  return last;
+}
+
+template <typename T, int NCB, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_dots(int n, int rpt, const T *__restrict__ V,
                                                  int64_t ldv, int c0, int nc,
                                                  const T *__restrict__ w,
-                                                 double *__restrict__ partial) {
+                                                 double *__restrict__ partial, FoldOut f) {
   __shared__ double red[4][NCB];
   T acc[NCB];
 #pragma unroll
@@ -523,14 +644,17 @@ __global__ __launch_bounds__(kBlock) void k_dots(int n, int rpt, const T *__rest
     partial[(int64_t)(c0 + c) * gridDim.x + blockIdx.x] =
         ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
   }
+  if constexpr (FOLD) {
+    if (last_to_arrive(f.counter)) fold_cols(partial, gridDim.x, c0, nc, f);
+  }
 }
 
-template <typename T, int NCB, bool DOTS, bool NORM>
+template <typename T, int NCB, bool DOTS, bool NORM, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_update(int n, int rpt, const T *__restrict__ V,
                                                    int64_t ldv, int nc, const double *coef_a,
                                                    const double *coef_b, double sign,
                                                    const T *w_in, T *out,
-                                                   double *__restrict__ partial) {
+                                                   double *__restrict__ partial, FoldOut f) {
   __shared__ T s_coef[NCB];
   __shared__ double red[4][DOTS ? NCB : 1];
   __shared__ double red4[4];
@@ -580,10 +704,16 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, int rpt, const T *__re
       partial[(int64_t)c * gridDim.x + blockIdx.x] =
           ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
     }
+    if constexpr (FOLD) {
+      if (last_to_arrive(f.counter)) fold_cols(partial, gridDim.x, 0, nc, f);
+    }
   }
   if constexpr (NORM) {
     const double s = block_sum(nacc, red4);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if constexpr (FOLD) {
+      if (last_to_arrive(f.counter)) fold_norm(partial, gridDim.x, f);
+    }
   }
 }
 
@@ -612,43 +742,28 @@ __global__ __launch_bounds__(kBlock) void k_norm2(int n, int rpt, const T *__res
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
-// Fixed-order sum of x[0..G) over the workgroup's threads (thread t takes
-// t, t + 256, ...), with four loads in flight per thread.
-__device__ __forceinline__ double strided_sum(const double *__restrict__ x, int G) {
-  double s = 0.0;
-  int g = threadIdx.x;
-  for (; g + 3 * kBlock < G; g += 4 * kBlock) {
-    const double a0 = x[g], a1 = x[g + kBlock], a2 = x[g + 2 * kBlock], a3 = x[g + 3 * kBlock];
-    s += (a0 + a1) + (a2 + a3);
-  }
-  for (; g < G; g += kBlock) s += x[g];
-  return s;
-}
-
 __global__ __launch_bounds__(kBlock) void k_reduce_cols(const double *__restrict__ partial, int G,
                                                         int c0, const double *colscale, double *h,
                                                         double *coef) {
   __shared__ double red4[4];
-  const int c = c0 + blockIdx.x;
-  double s = strided_sum(partial + (int64_t)c * G, G);
-  s = block_sum(s, red4);
-  if (threadIdx.x == 0) {
-    const double sc = colscale ? colscale[c] : 1.0;
-    const double hv = sc * s;
-    h[c] = hv;
-    if (coef) coef[c] = sc * hv;
-  }
+  reduce_col_finish(partial, G, c0 + blockIdx.x, colscale, h, coef, red4);
 }
 
+// With copy_dst: then copy_src[0..copy_n) -> copy_dst (pinned host memory, say),
+// the norm itself (copy_src[nrm_at]) written from the register.
 __global__ __launch_bounds__(kBlock) void k_reduce_norm(const double *__restrict__ partial, int G,
-                                                        double *nrm, double *inv) {
+                                                        double *nrm, double *inv,
+                                                        const double *copy_src, double *copy_dst,
+                                                        int copy_n, int nrm_at) {
   __shared__ double red4[4];
-  double s = strided_sum(partial, G);
-  s = block_sum(s, red4);
-  if (threadIdx.x == 0) {
-    const double r = sqrt(s);
-    nrm[0] = r;
-    if (inv) inv[0] = (r > 0.0) ? 1.0 / r : 0.0;
+  __shared__ double s_r;
+  reduce_norm_finish(partial, G, nrm, inv, red4);
+  if (copy_dst) {
+    if (threadIdx.x == 0) s_r = nrm[0];
+    __syncthreads();
+    const double r = s_r;
+    for (int i = threadIdx.x; i < copy_n; i += kBlock)
+      copy_dst[i] = (i == nrm_at) ? r : copy_src[i];
   }
 }
 
@@ -1225,7 +1340,7 @@ hipError_t launch_residual(const SpMat<T> &A, const T *b, const T *x, T *out, do
   return hipGetLastError();
 }
 
-int orth_rpt(int kind, int nc, bool f32) {
+static int orth_rpt_table(int kind, int nc, bool f32) {
   if (kind == kOrthRead) return (f32 && nc <= 24) ? 4 : 32;
   if (kind == kOrthUpdateDots) {
     if (nc <= 8) return f32 ? 4 : 2;
@@ -1233,7 +1348,14 @@ int orth_rpt(int kind, int nc, bool f32) {
     if (nc <= 40) return 8;
     return 32;
   }
-  return (!f32 && nc > 40) ? 8 : kOrthMinRpt;
+  return (!f32 && nc > 40) ? 8 : 2;
+}
+
+int orth_rpt(int kind, int nc, bool f32, int64_t n) {
+  const int groups = kind == kOrthUpdateDots ? kOrthMinGroupsUpdateDots : kOrthMinGroups;
+  const int64_t cap = n / ((int64_t)kBlock * groups);
+  const int rpt = orth_rpt_table(kind, nc, f32);
+  return (int)std::max<int64_t>(kOrthMinRpt, std::min<int64_t>(rpt, cap));
 }
 
 int orth_grid(int n, int rpt) {
@@ -1265,25 +1387,33 @@ int orth_grid(int n, int rpt) {
 
 template <typename T>
 hipError_t launch_dots(int n, int rpt, const T *V, int64_t ldv, int c0, int nc, const T *w,
-                       double *partial, hipStream_t stream) {
+                       double *partial, hipStream_t stream, const FoldOut *fold) {
   if (nc < 1 || nc > kMaxCols || rpt < 1) return hipErrorInvalidValue;
   const int G = orth_grid(n, rpt);
-#define PP_DOTS_CALL(NCB)                                                                       \
-  hipLaunchKernelGGL((k_dots<T, NCB>), dim3(G), dim3(kBlock), 0, stream, n, rpt, V, ldv, c0, nc, \
-                     w, partial)
+  if (fold && (G > kFoldMaxG || !fold->counter || !fold->h)) return hipErrorInvalidValue;
+  const FoldOut f = fold ? *fold : FoldOut{};
+#define PP_DOTS_CALL(NCB)                                                                     \
+  do {                                                                                        \
+    if (fold)                                                                                 \
+      hipLaunchKernelGGL((k_dots<T, NCB, true>), dim3(G), dim3(kBlock), 0, stream, n, rpt, V, \
+                         ldv, c0, nc, w, partial, f);                                         \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_dots<T, NCB, false>), dim3(G), dim3(kBlock), 0, stream, n, rpt,   \
+                         V, ldv, c0, nc, w, partial, f);                                      \
+  } while (0)
   PP_NCB_SWITCH(nc, PP_DOTS_CALL);
 #undef PP_DOTS_CALL
   return hipGetLastError();
 }
 
-template <typename T, bool DOTS, bool NORM>
+template <typename T, bool DOTS, bool NORM, bool FOLD>
 static void update_dispatch(int n, int rpt, const T *V, int64_t ldv, int nc, const double *ca,
                             const double *cb, double sign, const T *w_in, T *out, double *partial,
-                            hipStream_t stream) {
+                            hipStream_t stream, const FoldOut &f) {
   const int G = orth_grid(n, rpt);
-#define PP_UPD_CALL(NCB)                                                                      \
-  hipLaunchKernelGGL((k_update<T, NCB, DOTS, NORM>), dim3(G), dim3(kBlock), 0, stream, n, rpt, \
-                     V, ldv, nc, ca, cb, sign, w_in, out, partial)
+#define PP_UPD_CALL(NCB)                                                                   \
+  hipLaunchKernelGGL((k_update<T, NCB, DOTS, NORM, FOLD>), dim3(G), dim3(kBlock), 0, stream, \
+                     n, rpt, V, ldv, nc, ca, cb, sign, w_in, out, partial, f)
   PP_NCB_SWITCH(nc, PP_UPD_CALL);
 #undef PP_UPD_CALL
 }
@@ -1291,17 +1421,30 @@ static void update_dispatch(int n, int rpt, const T *V, int64_t ldv, int nc, con
 template <typename T>
 hipError_t launch_update(int n, int rpt, const T *V, int64_t ldv, int nc, const double *coef_a,
                          const double *coef_b, double sign, const T *w_in, T *out, bool dots,
-                         bool norm, double *partial, hipStream_t stream) {
+                         bool norm, double *partial, hipStream_t stream, const FoldOut *fold) {
   if (nc < 1 || nc > kMaxCols || (dots && norm) || rpt < 1) return hipErrorInvalidValue;
-  if (dots)
-    update_dispatch<T, true, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
-                                    stream);
-  else if (norm)
-    update_dispatch<T, false, true>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
-                                    stream);
-  else
-    update_dispatch<T, false, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
-                                     partial, stream);
+  if (fold && (!(dots || norm) || orth_grid(n, rpt) > kFoldMaxG || !fold->counter ||
+               (dots ? !fold->h : !fold->nrm)))
+    return hipErrorInvalidValue;
+  const FoldOut f = fold ? *fold : FoldOut{};
+  if (dots) {
+    if (fold)
+      update_dispatch<T, true, false, true>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
+                                            partial, stream, f);
+    else
+      update_dispatch<T, true, false, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
+                                             partial, stream, f);
+  } else if (norm) {
+    if (fold)
+      update_dispatch<T, false, true, true>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
+                                            partial, stream, f);
+    else
+      update_dispatch<T, false, true, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
+                                             partial, stream, f);
+  } else {
+    update_dispatch<T, false, false, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
+                                            partial, stream, f);
+  }
   return hipGetLastError();
 }
 
@@ -1322,8 +1465,11 @@ hipError_t launch_reduce_cols(const double *partial, int G, int c0, int nc, cons
 }
 
 hipError_t launch_reduce_norm(const double *partial, int G, double *nrm, double *inv,
-                              hipStream_t stream) {
-  hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(kBlock), 0, stream, partial, G, nrm, inv);
+                              hipStream_t stream, const double *copy_src, double *copy_dst,
+                              int copy_n, int nrm_at) {
+  if (copy_dst && (!copy_src || nrm_at < 0 || nrm_at >= copy_n)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(kBlock), 0, stream, partial, G, nrm, inv,
+                     copy_src, copy_dst, copy_n, nrm_at);
   return hipGetLastError();
 }
 
@@ -1504,10 +1650,10 @@ hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, cons
   template hipError_t launch_residual<T>(const SpMat<T> &, const T *, const T *, T *, double *,  \
                                          int *, hipStream_t);                                   \
   template hipError_t launch_dots<T>(int, int, const T *, int64_t, int, int, const T *, double *, \
-                                     hipStream_t);                                              \
+                                     hipStream_t, const FoldOut *);                             \
   template hipError_t launch_update<T>(int, int, const T *, int64_t, int, const double *,       \
                                        const double *, double, const T *, T *, bool, bool,      \
-                                       double *, hipStream_t);                                  \
+                                       double *, hipStream_t, const FoldOut *);                 \
   template hipError_t launch_norm2<T>(int, int, const T *, const double *, float *, double *,   \
                                       hipStream_t);                                             \
   template hipError_t launch_fill<T>(int64_t, T, T *, hipStream_t);                             \

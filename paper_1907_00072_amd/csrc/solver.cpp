@@ -119,7 +119,9 @@ int ensure_arena(Arena *a, size_t dev_bytes, size_t host_doubles) {
     if (a->host) (void)hipHostFree(a->host);
     a->host = nullptr;
     a->host_cap = 0;
-    if (hipHostMalloc((void **)&a->host, host_doubles * sizeof(double), hipHostMallocDefault) !=
+    // coherent: kernels write small results straight into it (the Arnoldi step's
+    // Hessenberg column), visible to the host once the stream is synchronised
+    if (hipHostMalloc((void **)&a->host, host_doubles * sizeof(double), hipHostMallocCoherent) !=
         hipSuccess) {
       a->host = nullptr;
       return PP_ERR_NOMEM;
@@ -165,6 +167,14 @@ struct Carver {
 
 inline int64_t pad_ld(int64_t n) { return (n + 63) / 64 * 64; }
 
+// Environment variable PP_FOLD=1 folds each CGS2 reduction's second stage into its
+// sweep where the partials are few (the same bits, three launches fewer per step;
+// measured slower on MI355X, so off by default).  Read at each call.
+bool fold_enabled() {
+  const char *v = std::getenv("PP_FOLD");
+  return v && std::atoi(v) != 0;
+}
+
 // Device workspace of one solve in compute type T.
 template <typename T>
 struct Work {
@@ -178,6 +188,9 @@ struct Work {
   double *coef1 = nullptr, *coef2 = nullptr, *ybuf = nullptr;  // [L] each
   double *misc = nullptr;      // [16]
   double *host = nullptr;      // pinned [2L + 8 + L]
+  int32_t *fold_counter = nullptr;  // ticket counter of the folded reductions
+  bool fold_armed = false;          // fold_counter zeroed on the device
+  bool fold_ok = false;             // folded reductions asked for (PP_FOLD=1)
 
   template <typename C>
   void carve(C &c, int n_, int L_) {
@@ -201,6 +214,9 @@ struct Work {
     coef2 = c.template take<double>(L);
     ybuf = c.template take<double>(L);
     misc = c.template take<double>(16);
+    fold_counter = c.template take<int32_t>(64);
+    fold_armed = false;
+    fold_ok = fold_enabled();
   }
   size_t host_doubles() const { return 3 * (size_t)L + 16; }
 };
@@ -560,7 +576,8 @@ constexpr bool is_f32() {
 template <typename T>
 int update_any(Work<T> &w, int nc, const double *coef, const T *w_in, T *out, bool norm,
                hipStream_t s, int *G) {
-  const int rpt = ppk::orth_rpt(ppk::kOrthWrite, std::min(nc, ppk::kMaxCols), is_f32<T>());
+  const int rpt =
+      ppk::orth_rpt(ppk::kOrthWrite, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
   for (int c0 = 0; c0 < nc; c0 += ppk::kMaxCols) {
     const int cc = std::min(ppk::kMaxCols, nc - c0);
     const bool lastc = (c0 + cc >= nc);
@@ -575,7 +592,8 @@ int update_any(Work<T> &w, int nc, const double *coef, const T *w_in, T *out, bo
 // partial dots of vec with V(:, 0..nc); *G receives the partials' workgroup count.
 template <typename T>
 int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s, int *G) {
-  const int rpt = ppk::orth_rpt(ppk::kOrthRead, std::min(nc, ppk::kMaxCols), is_f32<T>());
+  const int rpt =
+      ppk::orth_rpt(ppk::kOrthRead, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
   for (int c0 = 0; c0 < nc; c0 += ppk::kMaxCols) {
     const int cc = std::min(ppk::kMaxCols, nc - c0);
     PP_TRY_HIP(ppk::launch_dots<T>(w.n, rpt, w.V, w.ldv, c0, cc, vec, w.partial, s));
@@ -620,30 +638,67 @@ int arnoldi_step(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, in
   const int L = w.L;
   double *h1 = w.hbuf, *h2 = w.hbuf + L, *nrm = w.hbuf + 2 * L;
   T *vnext = w.V + (int64_t)(j + 1) * w.ldv;
+  // With few partials (small n) each sweep's last workgroup also does the second
+  // reduction stage, bitwise as the separate launch would (ppk::FoldOut).
+  const bool one_chunk = nc <= ppk::kMaxCols;
+  const bool may_fold = one_chunk && w.fold_ok;
+  const int rpt1 =
+      ppk::orth_rpt(ppk::kOrthRead, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
+  const int rpt2 = ppk::orth_rpt(ppk::kOrthUpdateDots, nc, is_f32<T>(), w.n);
+  const int rpt3 =
+      ppk::orth_rpt(ppk::kOrthWrite, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
+  const bool fold1 = may_fold && ppk::orth_grid(w.n, rpt1) <= ppk::kFoldMaxG;
+  const bool fold2 = may_fold && ppk::orth_grid(w.n, rpt2) <= ppk::kFoldMaxG;
+  const bool fold3 = may_fold && ppk::orth_grid(w.n, rpt3) <= ppk::kFoldMaxG;
+  if ((fold1 || fold2 || fold3) && !w.fold_armed) {
+    PP_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, w.fold_counter, s));
+    w.fold_armed = true;
+  }
   // pass 1: h1 = V^T w
   int G1 = 0, G2 = 0, G3 = 0;
-  PP_TRY(dots_any<T>(w, nc, w.W, s, &G1));
-  PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, G1, 0, nc, w.colscale, h1, w.coef1, s));
-  if (nc <= ppk::kMaxCols) {
+  if (fold1) {
+    const ppk::FoldOut f{w.fold_counter, w.colscale, h1, w.coef1};
+    PP_TRY_HIP(ppk::launch_dots<T>(w.n, rpt1, w.V, w.ldv, 0, nc, w.W, w.partial, s, &f));
+  } else {
+    PP_TRY(dots_any<T>(w, nc, w.W, s, &G1));
+    PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, G1, 0, nc, w.colscale, h1, w.coef1, s));
+  }
+  if (one_chunk) {
     // w -= V h1, fused with pass 2's dots
-    const int rpt = ppk::orth_rpt(ppk::kOrthUpdateDots, nc, is_f32<T>());
-    PP_TRY_HIP(ppk::launch_update<T>(w.n, rpt, w.V, w.ldv, nc, w.coef1, nullptr, 1.0, w.W, w.W,
-                                     true, false, w.partial, s));
-    G2 = ppk::orth_grid(w.n, rpt);
+    const ppk::FoldOut f{w.fold_counter, w.colscale, h2, w.coef2};
+    PP_TRY_HIP(ppk::launch_update<T>(w.n, rpt2, w.V, w.ldv, nc, w.coef1, nullptr, 1.0, w.W, w.W,
+                                     true, false, w.partial, s, fold2 ? &f : nullptr));
+    G2 = ppk::orth_grid(w.n, rpt2);
   } else {
     PP_TRY(update_any<T>(w, nc, w.coef1, w.W, w.W, false, s, nullptr));
     PP_TRY(dots_any<T>(w, nc, w.W, s, &G2));
   }
-  PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, G2, 0, nc, w.colscale, h2, w.coef2, s));
+  if (!fold2)
+    PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, G2, 0, nc, w.colscale, h2, w.coef2, s));
   // pass 2 update, norm, store as column j+1
-  PP_TRY(update_any<T>(w, nc, w.coef2, w.W, vnext, true, s, &G3));
-  PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, G3, nrm, w.colscale + j + 1, s));
+  // the norm's second stage also hands the column (h1 | h2 | nrm) to the pinned host
+  // buffer, so the step needs no separate device-to-host copy
+  const int hcount = 2 * L + 1;
+  if (fold3) {
+    ppk::FoldOut f;
+    f.counter = w.fold_counter;
+    f.nrm = nrm;
+    f.inv = w.colscale + j + 1;
+    f.copy_src = w.hbuf;
+    f.copy_dst = w.host;
+    f.copy_n = hcount;
+    f.nrm_at = 2 * L;
+    PP_TRY_HIP(ppk::launch_update<T>(w.n, rpt3, w.V, w.ldv, nc, w.coef2, nullptr, 1.0, w.W,
+                                     vnext, false, true, w.partial, s, &f));
+  } else {
+    PP_TRY(update_any<T>(w, nc, w.coef2, w.W, vnext, true, s, &G3));
+    PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, G3, nrm, w.colscale + j + 1, s, w.hbuf,
+                                       w.host, hcount, 2 * L));
+  }
   cnt.dots += 3;
   // three sweeps over nc basis columns; w read three times and written twice
   cnt.bytes_orth += (double)sizeof(T) * w.n * (3.0 * nc + 5.0);
   tm.mark(3, s);
-  PP_TRY_HIP(hipMemcpyAsync(w.host, w.hbuf, (2 * (size_t)L + 1) * sizeof(double),
-                            hipMemcpyDeviceToHost, s));
   PP_TRY_HIP(hipStreamSynchronize(s));
   double a2 = 0.0;
   bool ok = true;
@@ -664,7 +719,7 @@ int arnoldi_step(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, in
 template <typename T>
 int start_from_vector(Work<T> &w, const double *src, hipStream_t s, double *beta) {
   PP_TRY_HIP(ppk::launch_copy_from_f64<T>(w.n, src, w.V, s));
-  const int rpt = ppk::orth_rpt(ppk::kOrthRead, 1, is_f32<T>());
+  const int rpt = ppk::orth_rpt(ppk::kOrthRead, 1, is_f32<T>(), w.n);
   PP_TRY_HIP(ppk::launch_norm2<T>(w.n, rpt, w.V, nullptr, nullptr, w.partial, s));
   PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, ppk::orth_grid(w.n, rpt), w.misc, w.colscale,
                                      s));
@@ -866,7 +921,8 @@ int cycle_update(const Opr<T> &A, const PolyRef &pr, Work<T> &w, int k,
   PP_TRY_HIP(hipMemcpyAsync(w.ybuf, w.host + 2 * w.L + 8, k * sizeof(double),
                             hipMemcpyHostToDevice, s));
   const bool poly = pr.active();
-  const int rpt = ppk::orth_rpt(ppk::kOrthWrite, std::min(k, ppk::kMaxCols), is_f32<T>());
+  const int rpt =
+      ppk::orth_rpt(ppk::kOrthWrite, std::min(k, ppk::kMaxCols), is_f32<T>(), w.n);
   for (int c0 = 0; c0 < k; c0 += ppk::kMaxCols) {
     const int cc = std::min(ppk::kMaxCols, k - c0);
     T *dst = poly ? w.U : x_out;
@@ -1237,7 +1293,7 @@ int worst(int a, int b) {
 
 // ||b|| in FP64 (device) -> host.
 int norm_f64(Work<double> &w, const double *x, hipStream_t s, double *out) {
-  const int rpt = ppk::orth_rpt(ppk::kOrthRead, 1, false);
+  const int rpt = ppk::orth_rpt(ppk::kOrthRead, 1, false, w.n);
   PP_TRY_HIP(ppk::launch_norm2<double>(w.n, rpt, x, nullptr, nullptr, w.partial, s));
   PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, ppk::orth_grid(w.n, rpt), w.misc + 1, nullptr,
                                      s));
@@ -1550,7 +1606,7 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
       break;
     }
     // V32(:,0) = (float)(r / beta), with its FP32 norm
-    const int rpt = ppk::orth_rpt(ppk::kOrthWrite, 1, true);
+    const int rpt = ppk::orth_rpt(ppk::kOrthWrite, 1, true, n);
     PP_TRY_HIP(ppk::launch_norm2<double>(n, rpt, r64, w64.colscale, w.V, w.partial, s));
     PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, ppk::orth_grid(n, rpt), w.misc, w.colscale,
                                        s));
@@ -1946,7 +2002,8 @@ const char *pp_status_string(int code) {
     case PP_ERR_EIG: return "Hessenberg QR did not converge";
     case PP_ERR_SINGULAR: return "singular Hessenberg, zero start vector, or zero/non-finite root";
     case PP_WARN_DEGREE_REDUCED: return "warning: Arnoldi breakdown, polynomial has fewer roots";
-    case PP_WARN_NOT_CONVERGED: return "warning: iteration cap reached before tolerance";
+    case PP_WARN_NOT_CONVERGED:
+      return "warning: not converged (iteration cap, or stagnation at attainable accuracy)";
     case PP_WARN_NONFINITE: return "warning: non-finite value met, last finite iterate returned";
     case PP_WARN_CHOLESKY:
       return "warning: power-basis Gram matrix not positive definite (POTRF info > 0)";

@@ -44,7 +44,8 @@ import numpy as np
 __all__ = [
     "CSR", "Problem", "convection_diffusion", "stencil27_random", "bidiag1",
     "bidiag2", "laplacian5", "uniform", "normal", "config", "CONFIG_NAMES",
-    "random_csr", "recirculating_flow", "ILU_WORKLOAD", "EX1_WORKLOAD",
+    "random_csr", "recirculating_flow", "ILU_WORKLOAD", "EX1_WORKLOAD", "permutation",
+    "permuted",
 ]
 
 
@@ -303,6 +304,36 @@ ILU_WORKLOAD = {"name": "recirc2d_257_eps200_ilu0", "N": 257, "eps": 1.0 / 200.0
 # roots), on the paper's size (1025^2 unknowns).
 EX1_WORKLOAD = {"name": "recirc2d_1025_eps2", "N": 1025, "eps": 0.5, "m": 50,
                 "degrees": [0, 5, 10], "tol": 1e-8, "v0_seed": 107}
+
+
+def permutation(n: int, seed: int, block: Optional[int] = None) -> np.ndarray:
+    """A seeded permutation of range(n): uniform over all of it (block None), or
+    uniform within each run of `block` consecutive indices (locality kept)."""
+    rng = np.random.default_rng(seed)
+    if block is None:
+        return rng.permutation(n)
+    perm = np.arange(n)
+    for s in range(0, n, block):
+        perm[s:s + block] = s + rng.permutation(min(block, n - s))
+    return perm
+
+
+def permuted(A: CSR, perm: np.ndarray) -> CSR:
+    """The symmetric permutation P A P^T: row and column perm[i] of A become row and
+    column i (columns sorted within each row).  Same spectrum; no diagonal structure
+    is left unless perm keeps it."""
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(A.n)
+    lens = np.diff(A.row_ptr)[perm]
+    rp = np.zeros(A.n + 1, dtype=np.int64)
+    np.cumsum(lens, out=rp[1:])
+    starts = A.row_ptr[perm].astype(np.int64)
+    idx = np.repeat(starts - rp[:-1], lens) + np.arange(rp[-1])
+    cols = inv[A.col_ind[idx]].astype(np.int32)
+    vals = A.vals[idx]
+    rows = np.repeat(np.arange(A.n), lens)
+    order = np.lexsort((cols, rows))
+    return CSR(A.n, rp.astype(np.int32), cols[order], vals[order])
 
 
 def _rhs_from_solution(A: CSR, x: np.ndarray) -> np.ndarray:

@@ -880,3 +880,97 @@ def test_checkpoint_and_resume_is_exact(B):
     assert s_res.relres_true < 1e-10
     assert s_part.iters + s_res.iters == s_full.iters
     assert torch.equal(x_res, x_full)
+
+
+@pytest.mark.parametrize("cfg,N,precision", [(1, None, "f64"), (4, 128, "f64"), (4, 400, "f64"),
+                                             (1, None, "f32_ir"), (2, 16, "f64")])
+def test_folded_reductions_are_bitwise_the_separate_launches(B, cfg, N, precision, monkeypatch):
+    """Each CGS2 sweep whose partials are few (at most 256) also does the
+    reduction's second stage in its last workgroup; PP_FOLD=0 keeps the separate
+    launches.  Same bits, step for step: 64^2 and 128^2 fold every sweep, 400^2
+    folds the dot sweeps and leaves some update sweeps (313 partials) to the
+    separate launches, and the 16^3 case with m = 80 also runs steps past 64
+    basis columns (chunked sweeps, never folded)."""
+    import warnings
+    P = W.config(cfg, N=N) if N else W.config(cfg)
+    A = B.CSRMatrix.from_host(P.A)
+    kw = dict(m=P.m, d=P.d, tol=P.tol, v0=_up(P.v0), history=2000)
+    if precision == "f32_ir":
+        kw.update(precision="f32_ir", inner_tol=1e-5)
+    if cfg == 2:
+        kw.update(m=80, d=6, tol=1e-12, max_iters=200)
+    runs = []
+    for fold in ("1", "0"):
+        monkeypatch.setenv("PP_FOLD", fold)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", B.PPWarning)
+            x, st = B.pp_gmres_solve(A, _up(P.b), **kw)
+        runs.append((x, st))
+    (x1, s1), (x0, s0) = runs
+    assert s1.iters == s0.iters and s1.cycles == s0.cycles and s1.iters > 0
+    assert torch.equal(x1, x0)
+    assert np.array_equal(s1.history, s0.history)
+
+
+@pytest.mark.parametrize("block,layout", [(None, "auto"), (None, "sell"), (None, "csr"),
+                                          (4096, "auto")])
+def test_permuted_stencil_solve_matches_oracle(B, block, layout):
+    """A matrix without diagonal structure: the 40^3 convection-diffusion problem
+    (Peclet 100) under a seeded symmetric permutation P A P^T, uniform over all rows
+    or within blocks of 4096.  Its slices hold explicit columns (no shared
+    diagonals), its bandwidth is about n.  The solve follows the parity rule
+    against the oracle on the same permuted system, and un-permuted it solves the
+    original system."""
+    P = W.config(5, N=40)
+    perm = W.permutation(P.A.n, 17, block)
+    Ap = W.permuted(P.A, perm)
+    bp, v0p = P.b[perm], P.v0[perm]
+    xg, st, xo, so = _solve_both(B, Ap, bp, v0p, 30, 12, 1e-8, layout=layout)
+    _assert_parity(st, so, xg, xo, 1e-8)
+    x = np.empty_like(xg)
+    x[perm] = xg
+    assert np.linalg.norm(P.b - P.A.to_scipy() @ x) <= 1e-8 * np.linalg.norm(P.b)
+    if layout != "auto":
+        assert st.layout_used == layout
+    # automatic schedule: the bandwidth rules out the slab-skewed order
+    assert st.chain_slab_rows == 0
+
+
+def _dense_p(A, roots):
+    """p(A) formed densely from its roots: A^{-1} (I - prod_i (I - A/theta_i))."""
+    n = A.shape[0]
+    Pi = np.eye(n, dtype=complex)
+    for t in roots:
+        Pi = Pi @ (np.eye(n) - A / t)
+    return np.linalg.solve(A, np.eye(n) - Pi).real
+
+
+@pytest.mark.parametrize("name,d,layout", [("cd2d_8", 10, "auto"), ("cd2d_8", 10, "csr"),
+                                           ("dense_40", 9, "auto"), ("dense_40", 9, "sell"),
+                                           ("rand_64", 12, "csr"), ("rand_64", 12, "sell")])
+def test_apply_every_column_against_dense_p(B, name, d, layout):
+    """Brute force (n <= 64): every column of p(A), i.e. pp_apply on each unit
+    vector, against p(A) formed densely from the same roots; both real roots and
+    conjugate pairs occur in these root sets."""
+    if name == "cd2d_8":
+        Ah = W.config(1, N=8).A
+    elif name == "dense_40":
+        rng = np.random.default_rng(41)
+        M = rng.standard_normal((40, 40)) / np.sqrt(40) + 1.5 * np.eye(40)
+        S = sp.csr_matrix(M)
+        Ah = W.CSR(40, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.copy())
+    else:
+        Ah = W.random_csr(64, 9, seed=43, diag_shift=3.0)
+    M = Ah.to_dense()
+    roots, _ = opoly.build_poly(Ah.to_scipy(), W.uniform(Ah.n, 44), d)
+    ref = _dense_p(M, roots)
+    A = B.CSRMatrix.from_host(Ah, layout=layout)
+    poly = B.pp_poly_from_roots(Ah.n, roots)
+    got = np.column_stack([B.pp_apply(A, poly, _up(e)).cpu().numpy() for e in np.eye(Ah.n)])
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # FP32: the same columns to FP32 rounding
+    A32 = B.CSRMatrix.from_host(Ah, layout=layout, dtype=torch.float32)
+    p32 = B.pp_poly_from_roots(Ah.n, roots, dtype="f32")
+    got32 = np.column_stack([B.pp_apply(A32, p32, _up(e, torch.float32)).cpu().numpy()
+                             for e in np.eye(Ah.n)])
+    assert np.max(np.abs(got32 - ref)) <= 1e-4 * np.max(np.abs(ref))

@@ -51,3 +51,17 @@ def test_seeds_are_deterministic():
     assert np.array_equal(W.normal(10, 1), np.random.default_rng(1).standard_normal(10))
     a = W.uniform(1000, 5, 0.0, 1.0)
     assert a.min() >= 0 and a.max() < 1
+
+
+def test_symmetric_permutation_is_p_a_pt():
+    A = W.config(5, N=10).A
+    M = A.to_scipy().toarray()
+    for blk in (None, 64):
+        p = W.permutation(A.n, 5, blk)
+        assert np.array_equal(np.sort(p), np.arange(A.n))
+        if blk:
+            assert np.all(p // blk == np.arange(A.n) // blk)   # stays inside its block
+        B = W.permuted(A, p)
+        assert np.array_equal(B.to_scipy().toarray(), M[np.ix_(p, p)])
+        for i in range(B.n):
+            assert np.all(np.diff(B.col_ind[B.row_ptr[i]:B.row_ptr[i + 1]]) > 0)
