@@ -165,7 +165,13 @@ struct Carver {
   }
 };
 
-inline int64_t pad_ld(int64_t n) { return (n + 63) / 64 * 64; }
+// Leading dimension of the Krylov basis: n rounded up to 64 elements (512 B), plus 64
+// more when that is a multiple of 2048 elements, so columns are not a power-of-two
+// number of bytes apart (the CGS2 sweeps read one row of every column together).
+inline int64_t pad_ld(int64_t n) {
+  const int64_t ld = (n + 63) / 64 * 64;
+  return ld % 2048 == 0 ? ld + 64 : ld;
+}
 
 // Environment variable PP_FOLD=1 folds each CGS2 reduction's second stage into its
 // sweep where the partials are few (the same bits, three launches fewer per step;
