@@ -117,29 +117,6 @@ template <typename T>
 hipError_t launch_residual(const SpMat<T> &A, const T *b, const T *x, T *out, double *partial,
                            int *ntiles, hipStream_t stream);
 
-// Sweep kinds of the Gram-Schmidt kernels, for the choice of rows per thread.
-constexpr int kOrthRead = 0;        // k_dots, k_norm2 without the FP32 copy (read-only)
-constexpr int kOrthUpdateDots = 1;  // k_update fused with the next pass's dots
-constexpr int kOrthWrite = 2;       // k_update with the norm or alone, k_norm2 with the copy
-constexpr int kOrthMinRpt = 1;      // the smallest value orth_rpt returns
-// workgroups a sweep keeps at least, while n allows: 8 per compute unit for the
-// dot and update sweeps; one per compute unit for the update + dots sweep, whose
-// workgroups each end with nc block reductions (measured at 512^2: 1024 short
-// workgroups run its nc <= 40 instances up to 25% slower than 128-256 longer ones)
-constexpr int kOrthMinGroups = 2048;
-constexpr int kOrthMinGroupsUpdateDots = 256;
-
-// Rows per thread (each workgroup owns a contiguous block of 256 * rpt rows) of
-// a CGS2 sweep of n rows over nc <= kMaxCols basis columns.  Read-only sweeps
-// run long workgroups; sweeps that write run short ones, so the resident
-// workgroups' stores stay within a narrow window of HBM, as in a flat copy; the
-// update + dots sweep sits between because each workgroup must also reduce nc
-// partial dots.  Measured on gfx950 at n = 16.8M (FP64 update + norm: 5.2 -> 6.0
-// TB/s).  Smaller n lowers rpt (down to 1) until the sweep has kOrthMinGroups
-// (kOrthMinGroupsUpdateDots) workgroups, or one per 256 rows: long blocks on a
-// few hundred thousand rows would leave most compute units idle (at 512^2 the dot
-// sweep ran 32 workgroups at 1.1 TB/s; with 1024 it runs twice as fast).
-int orth_rpt(int kind, int nc, bool f32, int64_t n);
 // Workgroups G of a sweep of n rows at rpt rows per thread; its partials are
 // laid out [column][G].
 int orth_grid(int n, int rpt);
@@ -171,9 +148,12 @@ struct FoldOut {
 // partial[(c0+c) * G + g] = sum over block g's rows of V(i, c0+c) * w(i), c < nc <= kMaxCols,
 // G = orth_grid(n, rpt).  fold (optional): then also launch_reduce_cols(partial, G, c0, nc,
 // fold->colscale, fold->h, fold->coef).
+// cached: ordinary loads of V and w (a basis whose sweeps' working set fits the
+// caches, re-read by the next sweep), else non-temporal ones.
 template <typename T>
 hipError_t launch_dots(int n, int rpt, const T *V, int64_t ldv, int c0, int nc, const T *w,
-                       double *partial, hipStream_t stream, const FoldOut *fold = nullptr);
+                       double *partial, hipStream_t stream, const FoldOut *fold = nullptr,
+                       bool cached = false);
 
 // out = w_in - sum_c V(:, c) * coef(c),  coef(c) = sign * a(c) * (b ? b(c) : 1), nc <= kMaxCols.
 // w_in may be nullptr (zero) and may equal out.  With dots: partial dots of the
@@ -184,7 +164,7 @@ template <typename T>
 hipError_t launch_update(int n, int rpt, const T *V, int64_t ldv, int nc, const double *coef_a,
                          const double *coef_b, double sign, const T *w_in, T *out, bool dots,
                          bool norm, double *partial, hipStream_t stream,
-                         const FoldOut *fold = nullptr);
+                         const FoldOut *fold = nullptr, bool cached = false);
 
 // partial[g] = sum over block g of (scale*x(i))^2 in double; optionally also
 // writes out32 = (float)(scale * x) when out32 != nullptr (the refinement cast).

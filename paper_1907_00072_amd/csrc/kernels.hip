@@ -605,7 +605,9 @@ __device__ __forceinline__ bool last_to_arrive(int *counter) {
   return last;
 }
 
-template <typename T, int NCB, bool FOLD>
+// KEEP: ordinary loads (the basis re-read from the caches by the next sweep, for a
+// working set that fits them); otherwise non-temporal.
+template <typename T, int NCB, bool FOLD, bool KEEP>
 __global__ __launch_bounds__(kBlock) void k_dots(int n, int rpt, const T *__restrict__ V,
                                                  int64_t ldv, int c0, int nc,
                                                  const T *__restrict__ w,
@@ -621,8 +623,8 @@ __global__ __launch_bounds__(kBlock) void k_dots(int n, int rpt, const T *__rest
     if (i < n) {
       T v[NCB];
 #pragma unroll
-      for (int c = 0; c < NCB; ++c) v[c] = ldnt(Vc + (int64_t)min(c, nc - 1) * ldv + i);
-      const T wi = ldnt(w + i);
+      for (int c = 0; c < NCB; ++c) v[c] = ld_pass<KEEP>(Vc + (int64_t)min(c, nc - 1) * ldv + i);
+      const T wi = ld_pass<KEEP>(w + i);
       // keep every load of the row ahead of the arithmetic (the scheduler would
       // otherwise interleave load/wait/fma to save registers)
       __builtin_amdgcn_sched_barrier(0);
@@ -649,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(int n, int rpt, const T *__rest
   }
 }
 
-template <typename T, int NCB, bool DOTS, bool NORM, bool FOLD>
+template <typename T, int NCB, bool DOTS, bool NORM, bool FOLD, bool KEEP>
 __global__ __launch_bounds__(kBlock) void k_update(int n, int rpt, const T *__restrict__ V,
                                                    int64_t ldv, int nc, const double *coef_a,
                                                    const double *coef_b, double sign,
@@ -676,12 +678,12 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, int rpt, const T *__re
     if (i < n) {
       T v[NCB];
 #pragma unroll
-      for (int c = 0; c < NCB; ++c) v[c] = ldnt(V + (int64_t)min(c, nc - 1) * ldv + i);
-      T wi = w_in ? ldnt(w_in + i) : T(0);
+      for (int c = 0; c < NCB; ++c) v[c] = ld_pass<KEEP>(V + (int64_t)min(c, nc - 1) * ldv + i);
+      T wi = w_in ? ld_pass<KEEP>(w_in + i) : T(0);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int c = 0; c < NCB; ++c) wi -= v[c] * coef[c];
-      stnt(wi, out + i);
+      st_pass<KEEP>(wi, out + i);
       if constexpr (DOTS) {
 #pragma unroll
         for (int c = 0; c < NCB; ++c) acc[c] += v[c] * wi;
@@ -1340,24 +1342,6 @@ hipError_t launch_residual(const SpMat<T> &A, const T *b, const T *x, T *out, do
   return hipGetLastError();
 }
 
-static int orth_rpt_table(int kind, int nc, bool f32) {
-  if (kind == kOrthRead) return (f32 && nc <= 24) ? 4 : 32;
-  if (kind == kOrthUpdateDots) {
-    if (nc <= 8) return f32 ? 4 : 2;
-    if (nc <= 24) return 4;
-    if (nc <= 40) return 8;
-    return 32;
-  }
-  return (!f32 && nc > 40) ? 8 : 2;
-}
-
-int orth_rpt(int kind, int nc, bool f32, int64_t n) {
-  const int groups = kind == kOrthUpdateDots ? kOrthMinGroupsUpdateDots : kOrthMinGroups;
-  const int64_t cap = n / ((int64_t)kBlock * groups);
-  const int rpt = orth_rpt_table(kind, nc, f32);
-  return (int)std::max<int64_t>(kOrthMinRpt, std::min<int64_t>(rpt, cap));
-}
-
 int orth_grid(int n, int rpt) {
   const int64_t per = (int64_t)kBlock * rpt;
   return (int)((n + per - 1) / per);
@@ -1387,64 +1371,81 @@ int orth_grid(int n, int rpt) {
 
 template <typename T>
 hipError_t launch_dots(int n, int rpt, const T *V, int64_t ldv, int c0, int nc, const T *w,
-                       double *partial, hipStream_t stream, const FoldOut *fold) {
+                       double *partial, hipStream_t stream, const FoldOut *fold, bool cached) {
   if (nc < 1 || nc > kMaxCols || rpt < 1) return hipErrorInvalidValue;
   const int G = orth_grid(n, rpt);
   if (fold && (G > kFoldMaxG || !fold->counter || !fold->h)) return hipErrorInvalidValue;
   const FoldOut f = fold ? *fold : FoldOut{};
-#define PP_DOTS_CALL(NCB)                                                                     \
-  do {                                                                                        \
-    if (fold)                                                                                 \
-      hipLaunchKernelGGL((k_dots<T, NCB, true>), dim3(G), dim3(kBlock), 0, stream, n, rpt, V, \
-                         ldv, c0, nc, w, partial, f);                                         \
-    else                                                                                      \
-      hipLaunchKernelGGL((k_dots<T, NCB, false>), dim3(G), dim3(kBlock), 0, stream, n, rpt,   \
-                         V, ldv, c0, nc, w, partial, f);                                      \
+  // a folded sweep always runs with ordinary loads (it only serves small sweeps)
+#define PP_DOTS_CALL(NCB)                                                                      \
+  do {                                                                                         \
+    if (fold)                                                                                  \
+      hipLaunchKernelGGL((k_dots<T, NCB, true, true>), dim3(G), dim3(kBlock), 0, stream, n,    \
+                         rpt, V, ldv, c0, nc, w, partial, f);                                  \
+    else if (cached)                                                                           \
+      hipLaunchKernelGGL((k_dots<T, NCB, false, true>), dim3(G), dim3(kBlock), 0, stream, n,   \
+                         rpt, V, ldv, c0, nc, w, partial, f);                                  \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_dots<T, NCB, false, false>), dim3(G), dim3(kBlock), 0, stream, n,  \
+                         rpt, V, ldv, c0, nc, w, partial, f);                                  \
   } while (0)
   PP_NCB_SWITCH(nc, PP_DOTS_CALL);
 #undef PP_DOTS_CALL
   return hipGetLastError();
 }
 
-template <typename T, bool DOTS, bool NORM, bool FOLD>
+template <typename T, bool DOTS, bool NORM, bool FOLD, bool KEEP>
 static void update_dispatch(int n, int rpt, const T *V, int64_t ldv, int nc, const double *ca,
                             const double *cb, double sign, const T *w_in, T *out, double *partial,
                             hipStream_t stream, const FoldOut &f) {
   const int G = orth_grid(n, rpt);
-#define PP_UPD_CALL(NCB)                                                                   \
-  hipLaunchKernelGGL((k_update<T, NCB, DOTS, NORM, FOLD>), dim3(G), dim3(kBlock), 0, stream, \
-                     n, rpt, V, ldv, nc, ca, cb, sign, w_in, out, partial, f)
+#define PP_UPD_CALL(NCB)                                                                        \
+  hipLaunchKernelGGL((k_update<T, NCB, DOTS, NORM, FOLD, KEEP>), dim3(G), dim3(kBlock), 0,        \
+                     stream, n, rpt, V, ldv, nc, ca, cb, sign, w_in, out, partial, f)
   PP_NCB_SWITCH(nc, PP_UPD_CALL);
 #undef PP_UPD_CALL
+}
+
+// The sweep kind's instance: folded (always with ordinary loads and stores), or
+// separate with ordinary (cached) or non-temporal ones.
+template <typename T, bool DOTS, bool NORM>
+static void update_mode(int n, int rpt, const T *V, int64_t ldv, int nc, const double *ca,
+                        const double *cb, double sign, const T *w_in, T *out, double *partial,
+                        hipStream_t stream, const FoldOut *fold, bool cached) {
+  const FoldOut f = fold ? *fold : FoldOut{};
+  if constexpr (DOTS || NORM) {
+    if (fold) {
+      update_dispatch<T, DOTS, NORM, true, true>(n, rpt, V, ldv, nc, ca, cb, sign, w_in, out,
+                                                 partial, stream, f);
+      return;
+    }
+  }
+  if (cached)
+    update_dispatch<T, DOTS, NORM, false, true>(n, rpt, V, ldv, nc, ca, cb, sign, w_in, out,
+                                                partial, stream, f);
+  else
+    update_dispatch<T, DOTS, NORM, false, false>(n, rpt, V, ldv, nc, ca, cb, sign, w_in, out,
+                                                 partial, stream, f);
 }
 
 template <typename T>
 hipError_t launch_update(int n, int rpt, const T *V, int64_t ldv, int nc, const double *coef_a,
                          const double *coef_b, double sign, const T *w_in, T *out, bool dots,
-                         bool norm, double *partial, hipStream_t stream, const FoldOut *fold) {
+                         bool norm, double *partial, hipStream_t stream, const FoldOut *fold,
+                         bool cached) {
   if (nc < 1 || nc > kMaxCols || (dots && norm) || rpt < 1) return hipErrorInvalidValue;
   if (fold && (!(dots || norm) || orth_grid(n, rpt) > kFoldMaxG || !fold->counter ||
                (dots ? !fold->h : !fold->nrm)))
     return hipErrorInvalidValue;
-  const FoldOut f = fold ? *fold : FoldOut{};
-  if (dots) {
-    if (fold)
-      update_dispatch<T, true, false, true>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
-                                            partial, stream, f);
-    else
-      update_dispatch<T, true, false, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
-                                             partial, stream, f);
-  } else if (norm) {
-    if (fold)
-      update_dispatch<T, false, true, true>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
-                                            partial, stream, f);
-    else
-      update_dispatch<T, false, true, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
-                                             partial, stream, f);
-  } else {
-    update_dispatch<T, false, false, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out,
-                                            partial, stream, f);
-  }
+  if (dots)
+    update_mode<T, true, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
+                                stream, fold, cached);
+  else if (norm)
+    update_mode<T, false, true>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
+                                stream, fold, cached);
+  else
+    update_mode<T, false, false>(n, rpt, V, ldv, nc, coef_a, coef_b, sign, w_in, out, partial,
+                                 stream, fold, cached);
   return hipGetLastError();
 }
 
@@ -1650,10 +1651,10 @@ hipError_t launch_jacobi_scale(int n, const int32_t *rp, const int32_t *ci, cons
   template hipError_t launch_residual<T>(const SpMat<T> &, const T *, const T *, T *, double *,  \
                                          int *, hipStream_t);                                   \
   template hipError_t launch_dots<T>(int, int, const T *, int64_t, int, int, const T *, double *, \
-                                     hipStream_t, const FoldOut *);                             \
+                                     hipStream_t, const FoldOut *, bool);                       \
   template hipError_t launch_update<T>(int, int, const T *, int64_t, int, const double *,       \
                                        const double *, double, const T *, T *, bool, bool,      \
-                                       double *, hipStream_t, const FoldOut *);                 \
+                                       double *, hipStream_t, const FoldOut *, bool);           \
   template hipError_t launch_norm2<T>(int, int, const T *, const double *, float *, double *,   \
                                       hipStream_t);                                             \
   template hipError_t launch_fill<T>(int64_t, T, T *, hipStream_t);                             \

@@ -173,6 +173,43 @@ inline int64_t pad_ld(int64_t n) {
   return ld % 2048 == 0 ? ld + 64 : ld;
 }
 
+// ------------------------------------------------------- CGS2 sweep sizing
+// Sweep kinds, for the choice of rows per thread.
+constexpr int kOrthRead = 0;        // k_dots, k_norm2 without the FP32 copy (read-only)
+constexpr int kOrthUpdateDots = 1;  // k_update fused with the next pass's dots
+constexpr int kOrthWrite = 2;       // k_update with the norm or alone, k_norm2 with the copy
+constexpr int kOrthMinRpt = 1;      // the smallest value orth_rpt returns
+
+// Rows per thread of a CGS2 sweep of n rows over nc <= kMaxCols basis columns (each
+// workgroup owns a contiguous block of 256 * rpt rows).  The table was measured on
+// gfx950 at n = 16.8M: read-only sweeps run long workgroups; sweeps that write run
+// short ones, so the resident workgroups' stores stay within a narrow window of
+// HBM, as in a flat copy (FP64 update + norm: 5.2 -> 6.0 TB/s); the update + dots
+// sweep sits between.  Smaller n lowers rpt (down to 1) until the sweep keeps a
+// floor of workgroups, or one per 256 rows: long blocks on a few hundred thousand
+// rows leave most compute units idle (at 512^2 the dot sweep ran 32 workgroups at
+// 1.1 TB/s).  Each workgroup of a sweep with dots ends with nc block reductions,
+// so that floor falls with nc (2048 workgroups for a few columns, 256 from 32
+// columns on); the update and norm sweeps keep 2048.
+int orth_rpt_table(int kind, int nc, bool f32) {
+  if (kind == kOrthRead) return (f32 && nc <= 24) ? 4 : 32;
+  if (kind == kOrthUpdateDots) {
+    if (nc <= 8) return f32 ? 4 : 2;
+    if (nc <= 24) return 4;
+    if (nc <= 40) return 8;
+    return 32;
+  }
+  return (!f32 && nc > 40) ? 8 : 2;
+}
+
+int orth_rpt(int kind, int nc, bool f32, int64_t n) {
+  const int64_t groups =
+      kind == kOrthWrite ? 2048 : std::min<int64_t>(2048, std::max<int64_t>(256, 8192 / nc));
+  const int64_t cap = n / ((int64_t)ppk::kBlock * groups);
+  const int rpt = orth_rpt_table(kind, nc, f32);
+  return (int)std::max<int64_t>(kOrthMinRpt, std::min<int64_t>(rpt, cap));
+}
+
 // Environment variable PP_FOLD=1 folds each CGS2 reduction's second stage into its
 // sweep where the partials are few (the same bits, three launches fewer per step;
 // measured slower on MI355X, so off by default).  Read at each call.
@@ -212,7 +249,7 @@ struct Work {
     U = c.template take<T>(ldv);
     const size_t tiles = (size_t)(n_ + ppk::kBlock - 1) / ppk::kBlock;
     // CGS2 partials: up to L columns at the largest workgroup count of any sweep
-    const size_t gmax = (size_t)ppk::orth_grid(n_, ppk::kOrthMinRpt);
+    const size_t gmax = (size_t)ppk::orth_grid(n_, kOrthMinRpt);
     partial = c.template take<double>(std::max((size_t)L * gmax, tiles) + 64);
     colscale = c.template take<double>(L);
     hbuf = c.template take<double>(2 * (size_t)L + 8);
@@ -581,15 +618,15 @@ constexpr bool is_f32() {
 // whose partials' workgroup count is returned in *G.
 template <typename T>
 int update_any(Work<T> &w, int nc, const double *coef, const T *w_in, T *out, bool norm,
-               hipStream_t s, int *G) {
+               hipStream_t s, int *G, bool cached = false) {
   const int rpt =
-      ppk::orth_rpt(ppk::kOrthWrite, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
+      orth_rpt(kOrthWrite, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
   for (int c0 = 0; c0 < nc; c0 += ppk::kMaxCols) {
     const int cc = std::min(ppk::kMaxCols, nc - c0);
     const bool lastc = (c0 + cc >= nc);
     PP_TRY_HIP(ppk::launch_update<T>(w.n, rpt, w.V + (int64_t)c0 * w.ldv, w.ldv, cc, coef + c0,
                                      nullptr, 1.0, c0 == 0 ? w_in : out, out, false,
-                                     norm && lastc, w.partial, s));
+                                     norm && lastc, w.partial, s, nullptr, cached));
   }
   if (G) *G = ppk::orth_grid(w.n, rpt);
   return PP_OK;
@@ -597,12 +634,13 @@ int update_any(Work<T> &w, int nc, const double *coef, const T *w_in, T *out, bo
 
 // partial dots of vec with V(:, 0..nc); *G receives the partials' workgroup count.
 template <typename T>
-int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s, int *G) {
+int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s, int *G, bool cached = false) {
   const int rpt =
-      ppk::orth_rpt(ppk::kOrthRead, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
+      orth_rpt(kOrthRead, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
   for (int c0 = 0; c0 < nc; c0 += ppk::kMaxCols) {
     const int cc = std::min(ppk::kMaxCols, nc - c0);
-    PP_TRY_HIP(ppk::launch_dots<T>(w.n, rpt, w.V, w.ldv, c0, cc, vec, w.partial, s));
+    PP_TRY_HIP(ppk::launch_dots<T>(w.n, rpt, w.V, w.ldv, c0, cc, vec, w.partial, s, nullptr,
+                                   cached));
   }
   *G = ppk::orth_grid(w.n, rpt);
   return PP_OK;
@@ -648,11 +686,14 @@ int arnoldi_step(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, in
   // reduction stage, bitwise as the separate launch would (ppk::FoldOut).
   const bool one_chunk = nc <= ppk::kMaxCols;
   const bool may_fold = one_chunk && w.fold_ok;
+  // the step's three sweeps re-read the same nc basis columns: ordinary loads when
+  // they (and w) fit the cache budget, so the second and third sweeps find them there
+  const bool keep = (double)(nc + 2) * (double)w.ldv * sizeof(T) <= kCacheBudget;
   const int rpt1 =
-      ppk::orth_rpt(ppk::kOrthRead, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
-  const int rpt2 = ppk::orth_rpt(ppk::kOrthUpdateDots, nc, is_f32<T>(), w.n);
+      orth_rpt(kOrthRead, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
+  const int rpt2 = orth_rpt(kOrthUpdateDots, nc, is_f32<T>(), w.n);
   const int rpt3 =
-      ppk::orth_rpt(ppk::kOrthWrite, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
+      orth_rpt(kOrthWrite, std::min(nc, ppk::kMaxCols), is_f32<T>(), w.n);
   const bool fold1 = may_fold && ppk::orth_grid(w.n, rpt1) <= ppk::kFoldMaxG;
   const bool fold2 = may_fold && ppk::orth_grid(w.n, rpt2) <= ppk::kFoldMaxG;
   const bool fold3 = may_fold && ppk::orth_grid(w.n, rpt3) <= ppk::kFoldMaxG;
@@ -666,14 +707,14 @@ int arnoldi_step(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, in
     const ppk::FoldOut f{w.fold_counter, w.colscale, h1, w.coef1};
     PP_TRY_HIP(ppk::launch_dots<T>(w.n, rpt1, w.V, w.ldv, 0, nc, w.W, w.partial, s, &f));
   } else {
-    PP_TRY(dots_any<T>(w, nc, w.W, s, &G1));
+    PP_TRY(dots_any<T>(w, nc, w.W, s, &G1, keep));
     PP_TRY_HIP(ppk::launch_reduce_cols(w.partial, G1, 0, nc, w.colscale, h1, w.coef1, s));
   }
   if (one_chunk) {
     // w -= V h1, fused with pass 2's dots
     const ppk::FoldOut f{w.fold_counter, w.colscale, h2, w.coef2};
     PP_TRY_HIP(ppk::launch_update<T>(w.n, rpt2, w.V, w.ldv, nc, w.coef1, nullptr, 1.0, w.W, w.W,
-                                     true, false, w.partial, s, fold2 ? &f : nullptr));
+                                     true, false, w.partial, s, fold2 ? &f : nullptr, keep));
     G2 = ppk::orth_grid(w.n, rpt2);
   } else {
     PP_TRY(update_any<T>(w, nc, w.coef1, w.W, w.W, false, s, nullptr));
@@ -697,7 +738,7 @@ int arnoldi_step(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, in
     PP_TRY_HIP(ppk::launch_update<T>(w.n, rpt3, w.V, w.ldv, nc, w.coef2, nullptr, 1.0, w.W,
                                      vnext, false, true, w.partial, s, &f));
   } else {
-    PP_TRY(update_any<T>(w, nc, w.coef2, w.W, vnext, true, s, &G3));
+    PP_TRY(update_any<T>(w, nc, w.coef2, w.W, vnext, true, s, &G3, keep));
     PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, G3, nrm, w.colscale + j + 1, s, w.hbuf,
                                        w.host, hcount, 2 * L));
   }
@@ -725,7 +766,7 @@ int arnoldi_step(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, in
 template <typename T>
 int start_from_vector(Work<T> &w, const double *src, hipStream_t s, double *beta) {
   PP_TRY_HIP(ppk::launch_copy_from_f64<T>(w.n, src, w.V, s));
-  const int rpt = ppk::orth_rpt(ppk::kOrthRead, 1, is_f32<T>(), w.n);
+  const int rpt = orth_rpt(kOrthRead, 1, is_f32<T>(), w.n);
   PP_TRY_HIP(ppk::launch_norm2<T>(w.n, rpt, w.V, nullptr, nullptr, w.partial, s));
   PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, ppk::orth_grid(w.n, rpt), w.misc, w.colscale,
                                      s));
@@ -928,7 +969,7 @@ int cycle_update(const Opr<T> &A, const PolyRef &pr, Work<T> &w, int k,
                             hipMemcpyHostToDevice, s));
   const bool poly = pr.active();
   const int rpt =
-      ppk::orth_rpt(ppk::kOrthWrite, std::min(k, ppk::kMaxCols), is_f32<T>(), w.n);
+      orth_rpt(kOrthWrite, std::min(k, ppk::kMaxCols), is_f32<T>(), w.n);
   for (int c0 = 0; c0 < k; c0 += ppk::kMaxCols) {
     const int cc = std::min(ppk::kMaxCols, k - c0);
     T *dst = poly ? w.U : x_out;
@@ -1299,7 +1340,7 @@ int worst(int a, int b) {
 
 // ||b|| in FP64 (device) -> host.
 int norm_f64(Work<double> &w, const double *x, hipStream_t s, double *out) {
-  const int rpt = ppk::orth_rpt(ppk::kOrthRead, 1, false, w.n);
+  const int rpt = orth_rpt(kOrthRead, 1, false, w.n);
   PP_TRY_HIP(ppk::launch_norm2<double>(w.n, rpt, x, nullptr, nullptr, w.partial, s));
   PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, ppk::orth_grid(w.n, rpt), w.misc + 1, nullptr,
                                      s));
@@ -1612,7 +1653,7 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
       break;
     }
     // V32(:,0) = (float)(r / beta), with its FP32 norm
-    const int rpt = ppk::orth_rpt(ppk::kOrthWrite, 1, true, n);
+    const int rpt = orth_rpt(kOrthWrite, 1, true, n);
     PP_TRY_HIP(ppk::launch_norm2<double>(n, rpt, r64, w64.colscale, w.V, w.partial, s));
     PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, ppk::orth_grid(n, rpt), w.misc, w.colscale,
                                        s));
