@@ -10,8 +10,8 @@
 // for (k < i stored in row i for the forward solve and the factorisation,
 // k > i for the backward solve), so the rows of one level are independent.
 // Levels are found on the device by frontier expansion over the transposed
-// pattern.  A run of consecutive narrow levels (at most kRunRows rows each) goes
-// to one workgroup that steps through them with a barrier between levels; a
+// pattern.  A run of consecutive narrow levels (at most kRunRows rows each, at
+// most kRunLevels levels) goes to one workgroup that steps through them with a barrier between levels; a
 // wide level gets a launch of its own.  Inside a run the solved values of the
 // last kRing levels travel through LDS when every dependency allows it.
 #pragma once
@@ -31,13 +31,22 @@ constexpr int kRunRows = 1024;     // widest level handled inside a run
 constexpr int kPipeSlots = 8;      // most waited-for entries per row of the pipelined run
 constexpr int kRing = 4;           // levels of solved values a run keeps in LDS
 constexpr int kRingSlots = 4;      // most entries per row of the LDS-ring run kernel
+constexpr int kRunLevels = 4096;   // most levels in one run (a longer chain of narrow levels
+                                   // is split into several runs)
+
+// Per-position layout of the LDS-ring run data (see Sweep): doubles of entries and
+// 32-bit words of packed slots for rows of w <= kRingSlots entries.
+constexpr int ring_vstride(int w) { return w == 1 ? 1 : w == 2 ? 2 : 4; }
+constexpr int ring_swords(int w) { return w <= 2 ? 1 : 2; }
+static_assert(kRing * kRunRows < 32768, "ring slots are 16-bit integers");
 
 // A span of consecutive levels [l0, l1): a run (narrow levels, one workgroup) or
 // a single wide level.
 struct LevelSpan {
   int l0, l1;
   bool run;
-  int width;  // rows of the span's widest level
+  int width;          // rows of the span's widest level
+  bool glob = false;  // a run some of whose rows wait for values solved by earlier launches
 };
 
 // Level schedule of one triangular sweep and its level-ordered copy of the factor.
@@ -65,8 +74,13 @@ struct Sweep {
   // was solved by an earlier launch; nullptr when some entry is neither (then the
   // run kernel reads every solved value from global memory)
   int32_t *esrc = nullptr;
-  int32_t *lglob = nullptr;  // [nlev] 1 when a level of a run has an entry read from global
-  const double *zero = nullptr;  // a 0.0 nothing writes: the target of unneeded loads
+  // LDS-ring run data (nullptr unless esrc is set and width <= kRingSlots), per
+  // position q: ring_swords(width) 32-bit words of ring slots at rslot[q * words],
+  // each slot a 16-bit integer (-1: the value is not in the ring), and the entries at
+  // rval[q * ring_vstride(width) + s] (zero past width), divided by the pivot in the
+  // backward sweep
+  uint32_t *rslot = nullptr;
+  double *rval = nullptr;
   std::vector<int32_t> lbeg_host;
   std::vector<LevelSpan> spans;
 };
@@ -133,6 +147,13 @@ hipError_t launch_sweep_sources(int n, int width, int nlev, const int32_t *lbeg,
                                 const int32_t *ecol, const int32_t *qpos,
                                 const int32_t *runstart, int32_t *esrc, int32_t *lglob,
                                 int32_t *flag, hipStream_t stream);
+
+// LDS-ring run data (Sweep::rslot, Sweep::rval) from the slot-major copy and esrc
+// (width 1..kRingSlots); diag: the backward sweep's pivots (entries divided by
+// them), nullptr for the forward sweep.
+hipError_t launch_ring_pack(int n, int width, const int32_t *esrc, const double *eval,
+                            const double *diag, uint32_t *rslot, double *rval,
+                            hipStream_t stream);
 
 // Elementwise chain step with the operator's product given (prod = Op g, unscaled):
 // the kinds of ChainArgs with (A g)(i) replaced by prod(i).

@@ -8,8 +8,8 @@
 // back to back inside one workgroup (a barrier between levels, no launch between
 // them); a level wider than kRunRows gets its own launch with one thread per row.
 // Three run kernels, fastest first: k_sweep_ring (solved values passed through an
-// LDS ring, LDS-only barriers, all loads of a level issued two levels ahead),
-// k_sweep_pipe (the same prefetching on global memory), and k_forward_run /
+// LDS ring, LDS-only barriers, a level's loads issued 4 to 10 levels ahead),
+// k_sweep_pipe (two levels ahead, on global memory), and k_forward_run /
 // k_backward_run (level-ordered CSR, any row length).
 #include <hip/hip_runtime.h>
 
@@ -422,107 +422,196 @@ __global__ __launch_bounds__(kB) void k_sweep_sources(int n, int width, int nlev
 // Registers of one row of a run level (see k_sweep_ring).
 template <int W>
 struct RingRow {
-  bool ok;         // this thread has a row at the level
-  int i;           // the row
-  int c[W], x[W];  // entries: column and ring slot (-1: not in the ring)
-  double v[W], d, r;
+  bool ok;                          // this thread has a row at the level
+  int q;                            // its position
+  uint32_t xs[ring_swords(W)];    // packed ring slots
+  double v[ring_vstride(W)];      // entries (the last ones padding when W = 3)
+  double r;                         // right-hand side in level order
 };
 
+template <int W>
+__device__ __forceinline__ int ring_slot(const RingRow<W> &R, int s) {
+  return (int)(int16_t)(R.xs[s >> 1] >> (16 * (s & 1)));
+}
+
+// Values solved by earlier launches, taken out of a run's right-hand side before
+// the run starts: rq[q] -= sum of v * out[c] over the entries of position q in
+// [q0, q1) whose column was solved before the run (esrc -1 on a real column); v
+// is the run's stored entry (divided by the pivot in the backward sweep, like
+// rq).  The run kernel then reads solved values from its LDS ring alone.
+template <int W>
+__global__ __launch_bounds__(kB) void k_ring_glob(int q0, int q1, int n,
+                                                  const int32_t *__restrict__ ecol,
+                                                  const int32_t *__restrict__ esrc,
+                                                  const double *__restrict__ rval,
+                                                  const double *__restrict__ out,
+                                                  double *__restrict__ rq) {
+  const int q = q0 + (int)(blockIdx.x * kB + threadIdx.x);
+  if (q >= q1) return;
+  double acc = rq[q];
+#pragma unroll
+  for (int s = 0; s < W; ++s) {
+    const int64_t e = (int64_t)s * n + q;
+    const int c = ecol[e];
+    if (c >= 0 && esrc[e] < 0) acc -= rval[(int64_t)q * ring_vstride(W) + s] * out[c];
+  }
+  rq[q] = acc;
+}
+
 // The pipelined run with the solved values of the last kRing levels in an LDS ring
-// (each entry's esrc says where its value is).  Only LDS is exchanged between the
-// run's waves, so the barrier between levels fences LDS alone and the global
-// loads issued ahead stay in flight across it.  The level loop is unrolled by
-// three over three register sets (the level being solved, the next one, the one
-// after), so a prefetched value lands in the register that later uses it and no
-// copy waits for it; every load is unconditional (clamped indices, results
-// selected at use).  Global gathers, of values solved by earlier launches, are
-// issued only on the levels that have them (lglob, uniform per level).
-template <int W, bool BACK>
+// (each entry's slot says where its value is; values solved by earlier launches
+// are already in the right-hand side, see k_ring_glob).  Everything runs in level
+// order: position q's right-hand side rq[q] is replaced by its solution (the
+// caller scatters the run's positions to rows afterwards), so every load and
+// store of a level is contiguous.  The backward sweep comes here with its rows
+// divided by the pivots (entries at set-up, the right-hand side at its gather),
+// so both sweeps run the same unit-diagonal step.
+// Only LDS is exchanged between the run's waves, so the barrier between levels
+// fences LDS alone and the global loads issued ahead stay in flight across it.
+// Everything a level needs is loaded D levels ahead into one of D + 1 register
+// sets (the loop is unrolled by D + 1, so a prefetched value lands in the register
+// that later uses it); no load in the loop is conditional (clamped indices,
+// results selected at use), so the wait before a level's arithmetic covers that
+// level's loads and no later ones.  The level offsets a load needs are read from
+// LDS one level early, in the shadow of the barrier.
+template <int W, int D>
 __global__ __launch_bounds__(kRunThreads) void k_sweep_ring(
-    int l0, int l1, int n, const int32_t *__restrict__ lbeg, const int32_t *__restrict__ lglob,
-    const int32_t *__restrict__ row, const int32_t *__restrict__ ecol,
-    const int32_t *__restrict__ esrc, const double *__restrict__ eval,
-    const double *__restrict__ diag, const double *__restrict__ zero,
-    const double *__restrict__ rq, double *out) {
+    int l0, int l1, const int32_t *__restrict__ lbeg, const uint32_t *__restrict__ rslot,
+    const double *__restrict__ rval, double *rq) {
+  constexpr int VS = ring_vstride(W), SW = ring_swords(W);
   // the last slot is never written: the target of ring loads a row does not need
   __shared__ double ring[kRing * kRunRows + 1];
   constexpr int kNoSlot = kRing * kRunRows;
-  __shared__ int32_t s_lb[kLbegChunk + 8];
-  __shared__ int32_t s_gf[kLbegChunk + 8];
+  constexpr int kLbExtra = 2 * D + 4;  // offsets read past the run's last level
+  // the run's level offsets, lbeg[l0 + k] (clamped to lbeg[l1]); l1 - l0 <= kRunLevels
+  __shared__ int32_t s_lb[kRunLevels + kLbExtra];
   const int t = threadIdx.x;
-  int base = l0;
-  auto stage = [&]() {
-    for (int k = t; k < kLbegChunk + 8; k += (int)blockDim.x) {
-      const int l = base + k;
-      s_lb[k] = lbeg[min(l, l1)];
-      s_gf[k] = l < l1 ? lglob[l] : 0;
-    }
-    __syncthreads();
+  // position of this thread at level l from the level's first and next offsets
+  auto pos = [&](int l, int b0, int b1) -> int {
+    const int q = b0 + t;
+    return (l < l1 && q < b1) ? q : -1;
   };
-  auto pos = [&](int l) -> int {
-    if (l >= l1) return -1;
-    const int q = s_lb[l - base] + t;
-    return q < s_lb[l - base + 1] ? q : -1;
-  };
-  auto load = [&](int l, RingRow<W> &R) {
-    const int q = pos(l);
+  auto load = [&](int q, RingRow<W> &R) {
     R.ok = q >= 0;
-    const int qc = R.ok ? q : 0;
-    R.i = row[qc];
-    R.r = rq[qc];
+    R.q = R.ok ? q : 0;
+    R.r = rq[R.q];
+    if constexpr (SW == 1) {
+      R.xs[0] = rslot[R.q];
+    } else {
+      const uint2 w = reinterpret_cast<const uint2 *>(rslot)[R.q];
+      R.xs[0] = w.x;
+      R.xs[1] = w.y;
+    }
+    const double *vp = rval + (int64_t)R.q * VS;
+    if constexpr (VS == 1) {
+      R.v[0] = vp[0];
+    } else {
+#pragma unroll
+      for (int k = 0; k < VS; k += 2) {
+        const double2 w = reinterpret_cast<const double2 *>(vp)[k / 2];
+        R.v[k] = w.x;
+        R.v[k + 1] = w.y;
+      }
+    }
+  };
+  // offsets of the level whose loads the next step issues: lbeg[l + D], lbeg[l + D + 1]
+  int nb0, nb1;
+  // level l: solve S0, fetch level l + D into SD
+  auto step = [&](int l, RingRow<W> &S0, RingRow<W> &SD) {
+    double g[W];
 #pragma unroll
     for (int s = 0; s < W; ++s) {
-      R.c[s] = ecol[(int64_t)s * n + qc];
-      R.x[s] = esrc[(int64_t)s * n + qc];
-      R.v[s] = eval[(int64_t)s * n + qc];
+      const int x = ring_slot(S0, s);
+      g[s] = ring[x >= 0 ? x : kNoSlot];
     }
-    if constexpr (BACK) R.d = diag[qc];
-  };
-  // level l: solve S0 and fetch everything of level l + 2 into S2 (the right-hand
-  // side comes in level order, so no load waits for another)
-  auto step = [&](int l, RingRow<W> &S0, RingRow<W> &S1, RingRow<W> &S2) {
-    const bool glob = __builtin_amdgcn_readfirstlane(s_gf[l - base]) != 0;
-    double gg[W], gi[W];
-    if (glob) {
+    load(pos(l + D, nb0, nb1), SD);
+    double acc = S0.r;
 #pragma unroll
-      for (int s = 0; s < W; ++s)
-        gg[s] = *((S0.ok && S0.x[s] < 0 && S0.c[s] >= 0) ? out + S0.c[s] : zero);
-    }
-#pragma unroll
-    for (int s = 0; s < W; ++s) gi[s] = ring[S0.x[s] >= 0 ? S0.x[s] : kNoSlot];
-    (void)S1;
-    load(l + 2, S2);
-    if (S0.ok) {
-      double acc = S0.r;
-#pragma unroll
-      for (int s = 0; s < W; ++s) {
-        const double g = S0.x[s] >= 0 ? gi[s] : ((glob && S0.c[s] >= 0) ? gg[s] : 0.0);
-        acc -= S0.v[s] * g;
-      }
-      const double val = BACK ? acc / S0.d : acc;
-      ring[(l % kRing) * kRunRows + t] = val;
-      out[S0.i] = val;
-    }
+    for (int s = 0; s < W; ++s) acc -= S0.v[s] * (ring_slot(S0, s) >= 0 ? g[s] : 0.0);
+    // a thread with no row at level l owns no reader of this slot
+    ring[(l % kRing) * kRunRows + t] = acc;
+    if (S0.ok) rq[S0.q] = acc;
+    nb0 = nb1;
+    nb1 = s_lb[l + D + 2 - l0];
     // level l's ring slots are written before level l + 1 reads them
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
   };
-  stage();
-  RingRow<W> A, Bv, C;
-  load(l0, A);
-  load(l0 + 1, Bv);
-  // levels past l1 are empty (no row), so the loop may run up to two of them
-  for (int l = l0; l < l1; l += 3) {
-    if (l - base >= kLbegChunk) {  // uniform: every thread restages
-      base = l;
-      stage();
-    }
-    step(l, A, Bv, C);
-    step(l + 1, Bv, C, A);
-    step(l + 2, C, A, Bv);
+  // staged once: no global load in the level loop but the prefetches, whose
+  // waits then stay D levels behind
+  for (int k = t; k < l1 - l0 + kLbExtra; k += (int)blockDim.x) s_lb[k] = lbeg[min(l0 + k, l1)];
+  __syncthreads();
+  RingRow<W> R[D + 1];
+  // the first D levels' loads are issued level after level, in the loop's order,
+  // so the loop's waits (fixed in the code, shared with later iterations) count
+  // the loads of D - 1 levels as still in flight
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    load(pos(l0 + k, s_lb[k], s_lb[k + 1]), R[k]);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  nb0 = s_lb[D];
+  nb1 = s_lb[D + 1];
+  // levels past l1 are empty (no row), so the loop may run up to D of them; a run
+  // has a level (l0 < l1), and the loop is entered without a test, which keeps the
+  // loads above in the order written
+  int l = l0;
+  do {
+#pragma unroll
+    for (int k = 0; k <= D; ++k) step(l + k, R[k], R[(k + D) % (D + 1)]);
+    l += D + 1;
+  } while (l < l1);
 }
+
+// Ring-run data from the slot-major copy: slots packed as 16-bit integers, entries
+// per position (divided by the pivot when diag is given: the backward sweep).
+template <int W>
+__global__ __launch_bounds__(kB) void k_ring_pack(int n, const int32_t *__restrict__ esrc,
+                                                  const double *__restrict__ eval,
+                                                  const double *__restrict__ diag,
+                                                  uint32_t *__restrict__ rslot,
+                                                  double *__restrict__ rval) {
+  const int q = blockIdx.x * kB + threadIdx.x;
+  if (q >= n) return;
+  constexpr int VS = ring_vstride(W), SW = ring_swords(W);
+  uint32_t w[2] = {0u, 0u};
+  const double d = diag ? diag[q] : 1.0;
+#pragma unroll
+  for (int s = 0; s < VS; ++s) {
+    int x = -1;
+    double v = 0.0;
+    if (s < W) {
+      x = esrc[(int64_t)s * n + q];
+      v = eval[(int64_t)s * n + q];
+      if (x < 0) x = -1;
+    }
+    if (s < 2 * SW) w[s >> 1] |= (uint32_t)(uint16_t)(int16_t)x << (16 * (s & 1));
+    rval[(int64_t)q * VS + s] = diag ? v / d : v;
+  }
+#pragma unroll
+  for (int k = 0; k < SW; ++k) rslot[(int64_t)q * SW + k] = w[k];
+}
+
+// Right-hand side of a ring sweep in level order: dst[q] = src[row[q]] (divided by
+// the pivot when diag is given).
+__global__ __launch_bounds__(kB) void k_gather_ring(int n, const int32_t *__restrict__ row,
+                                                    const double *__restrict__ diag,
+                                                    const double *__restrict__ src,
+                                                    double *__restrict__ dst) {
+  const int q = blockIdx.x * kB + threadIdx.x;
+  if (q < n) dst[q] = diag ? src[row[q]] / diag[q] : src[row[q]];
+}
+
+// A finished run's solutions to their rows: dst[row[q]] = src[q], q in [q0, q1).
+__global__ __launch_bounds__(kB) void k_scatter_run(int q0, int q1,
+                                                    const int32_t *__restrict__ row,
+                                                    const double *__restrict__ src,
+                                                    double *__restrict__ dst) {
+  const int q = q0 + (int)(blockIdx.x * kB + threadIdx.x);
+  if (q < q1) dst[row[q]] = src[q];
+}
+
 
 // ------------------------------------------------------------- composed operator
 // The chain step kinds of ChainArgs with (A g)(i) replaced by the given prod(i).
@@ -686,38 +775,48 @@ hipError_t launch_sweep_sources(int n, int width, int nlev, const int32_t *lbeg,
   return hipGetLastError();
 }
 
-namespace {
-__global__ __launch_bounds__(kB) void k_gather_level(int n, const int32_t *__restrict__ row,
-                                                     const double *__restrict__ src,
-                                                     double *__restrict__ dst) {
-  const int q = blockIdx.x * kB + threadIdx.x;
-  if (q < n) dst[q] = src[row[q]];
+// Levels a ring run loads ahead of the one it solves: a level takes a fraction of
+// the latency of a load that misses the L2, so as many as the registers allow
+// (D + 1 register sets, 4 wavefronts a SIMD at 1024 threads: 128 VGPRs).
+template <int W>
+constexpr int ring_ahead() {
+  return W <= 1 ? 10 : W == 2 ? 7 : W == 3 ? 5 : 4;
 }
-}  // namespace
 
-// Whether a sweep runs LDS-ring kernels (they read the right-hand side in level order).
-static bool uses_ring(const Sweep &S) { return S.esrc && S.width <= kRingSlots; }
+// One LDS-ring run: the values it waits for from earlier launches out of its
+// right-hand side, the run in level order on work, its solutions to their rows.
+template <int W>
+static void launch_ring(const Sweep &S, const LevelSpan &sp, int n, double *work, double *out,
+                        hipStream_t stream) {
+  const int q0 = S.lbeg_host[sp.l0], q1 = S.lbeg_host[sp.l1];
+  if (sp.glob)
+    hipLaunchKernelGGL((k_ring_glob<W>), dim3(blocks(q1 - q0)), dim3(kB), 0, stream, q0, q1, n,
+                       S.ecol, S.esrc, S.rval, out, work);
+  hipLaunchKernelGGL((k_sweep_ring<W, ring_ahead<W>()>), dim3(1),
+                     dim3((sp.width + 63) / 64 * 64), 0, stream, sp.l0, sp.l1, S.lbeg, S.rslot,
+                     S.rval, work);
+  hipLaunchKernelGGL(k_scatter_run, dim3(blocks(q1 - q0)), dim3(kB), 0, stream, q0, q1, S.row,
+                     work, out);
+}
 
-// The pipelined run for the sweep's slot count (1..kPipeSlots): with the LDS ring
-// when every in-run dependency is recent enough (rq: the right-hand side in level
-// order), else on global memory.
+// A run of a sweep with a slot-major copy: LDS-ring runs when the sweep has their
+// data (work: the right-hand side in level order), else the pipelined run on
+// global memory for the sweep's slot count (1..kPipeSlots).
 template <bool BACK>
-static void launch_pipe(const Sweep &S, const LevelSpan &sp, int n, const double *rhs,
-                        const double *rq, double *out, hipStream_t stream) {
-#define PP_PIPE(W)                                                                            \
-  do {                                                                                        \
-    if constexpr (W <= kRingSlots) {                                                          \
-      if (S.esrc) {                                                                           \
-        hipLaunchKernelGGL((k_sweep_ring<(W <= kRingSlots ? W : 1), BACK>), dim3(1),          \
-                           dim3((sp.width + 63) / 64 * 64), 0, stream, sp.l0, sp.l1, n,       \
-                           S.lbeg, S.lglob,                                                   \
-                           S.row, S.ecol, S.esrc, S.eval, S.diag, S.zero, rq, out);           \
-        break;                                                                                \
-      }                                                                                       \
-    }                                                                                         \
-    hipLaunchKernelGGL((k_sweep_pipe<W, BACK>), dim3(1), dim3(kRunThreads), 0, stream, sp.l0, \
-                       sp.l1, n, S.lbeg, S.row, S.ecol, S.eval, S.diag, rhs, out);            \
-  } while (0)
+static void launch_slot_run(const Sweep &S, const LevelSpan &sp, int n, const double *rhs,
+                            double *work, double *out, hipStream_t stream) {
+  if (S.rslot) {
+    switch (S.width) {
+      case 1: launch_ring<1>(S, sp, n, work, out, stream); break;
+      case 2: launch_ring<2>(S, sp, n, work, out, stream); break;
+      case 3: launch_ring<3>(S, sp, n, work, out, stream); break;
+      default: launch_ring<4>(S, sp, n, work, out, stream); break;
+    }
+    return;
+  }
+#define PP_PIPE(W)                                                                               \
+  hipLaunchKernelGGL((k_sweep_pipe<W, BACK>), dim3(1), dim3(kRunThreads), 0, stream, sp.l0,      \
+                     sp.l1, n, S.lbeg, S.row, S.ecol, S.eval, S.diag, rhs, out)
   switch (S.width) {
     case 1: PP_PIPE(1); break;
     case 2: PP_PIPE(2); break;
@@ -731,6 +830,23 @@ static void launch_pipe(const Sweep &S, const LevelSpan &sp, int n, const double
 #undef PP_PIPE
 }
 
+hipError_t launch_ring_pack(int n, int width, const int32_t *esrc, const double *eval,
+                            const double *diag, uint32_t *rslot, double *rval,
+                            hipStream_t stream) {
+#define PP_PACK(W)                                                                           \
+  hipLaunchKernelGGL((k_ring_pack<W>), dim3(blocks(n)), dim3(kB), 0, stream, n, esrc, eval, \
+                     diag, rslot, rval)
+  switch (width) {
+    case 1: PP_PACK(1); break;
+    case 2: PP_PACK(2); break;
+    case 3: PP_PACK(3); break;
+    case 4: PP_PACK(4); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PP_PACK
+  return hipGetLastError();
+}
+
 hipError_t launch_sweep_fill(int n, const int32_t *row, const int32_t *rp, const int32_t *ci,
                              const int32_t *dpos, const double *lu, bool upper,
                              const int32_t *ptr, int32_t *col, double *val, double *diag,
@@ -742,11 +858,12 @@ hipError_t launch_sweep_fill(int n, const int32_t *row, const int32_t *rp, const
 
 hipError_t launch_ilu_forward(int n, const Sweep &L, const double *r, double *z, double *work,
                               hipStream_t stream) {
-  if (uses_ring(L))
-    hipLaunchKernelGGL(k_gather_level, dim3(blocks(n)), dim3(kB), 0, stream, n, L.row, r, work);
+  if (L.rslot)
+    hipLaunchKernelGGL(k_gather_ring, dim3(blocks(n)), dim3(kB), 0, stream, n, L.row, nullptr, r,
+                       work);
   for (const LevelSpan &sp : L.spans) {
     if (sp.run && L.ecol) {
-      launch_pipe<false>(L, sp, n, r, work, z, stream);
+      launch_slot_run<false>(L, sp, n, r, work, z, stream);
     } else if (sp.run) {
       hipLaunchKernelGGL(k_forward_run, dim3(1), dim3(kRunThreads), 0, stream, sp.l0, sp.l1,
                          L.lbeg, L.row, L.ptr, L.col, L.val, r, z);
@@ -761,11 +878,12 @@ hipError_t launch_ilu_forward(int n, const Sweep &L, const double *r, double *z,
 
 hipError_t launch_ilu_backward(int n, const Sweep &U, const double *z, double *x, double *work,
                                hipStream_t stream) {
-  if (uses_ring(U))
-    hipLaunchKernelGGL(k_gather_level, dim3(blocks(n)), dim3(kB), 0, stream, n, U.row, z, work);
+  if (U.rslot)  // the right-hand side in level order, divided by the pivots
+    hipLaunchKernelGGL(k_gather_ring, dim3(blocks(n)), dim3(kB), 0, stream, n, U.row, U.diag, z,
+                       work);
   for (const LevelSpan &sp : U.spans) {
     if (sp.run && U.ecol) {
-      launch_pipe<true>(U, sp, n, z, work, x, stream);
+      launch_slot_run<true>(U, sp, n, z, work, x, stream);
     } else if (sp.run) {
       hipLaunchKernelGGL(k_backward_run, dim3(1), dim3(kRunThreads), 0, stream, sp.l0, sp.l1,
                          U.lbeg, U.row, U.ptr, U.col, U.val, U.diag, z, x);

@@ -58,14 +58,15 @@ void free_ilu(pp_ilu *M) {
 }
 
 // Launch spans of a level schedule: consecutive levels of at most kRunRows rows
-// share one run; a wider level is a span of its own.
+// share one run of at most kRunLevels levels; a wider level is a span of its own.
 std::vector<LevelSpan> make_spans(const std::vector<int32_t> &lbeg) {
   std::vector<LevelSpan> spans;
   const int nlev = (int)lbeg.size() - 1;
   for (int l = 0; l < nlev; ++l) {
     const int rows = lbeg[l + 1] - lbeg[l];
     const bool narrow = rows <= ppk::kRunRows;
-    if (narrow && !spans.empty() && spans.back().run && spans.back().l1 == l) {
+    if (narrow && !spans.empty() && spans.back().run && spans.back().l1 == l &&
+        l - spans.back().l0 < ppk::kRunLevels) {
       spans.back().l1 = l + 1;
       spans.back().width = std::max(spans.back().width, rows);
     } else {
@@ -157,22 +158,36 @@ int build_sweep(int n, const int32_t *rp, const int32_t *ci, const int32_t *dpos
     ILU_TRY(tmp.take(&rs, S.nlev));
     ILU_TRY(tmp.take(&flag, 64));
     ILU_TRY(own.take(&S.esrc, (int64_t)w * n));
-    ILU_TRY(own.take(&S.lglob, S.nlev));
-    ILU_TRY_HIP(ppk::launch_fill<int32_t>(S.nlev, 0, S.lglob, s));
-    double *zero = nullptr;
-    ILU_TRY(own.take(&zero, 8));
-    ILU_TRY_HIP(ppk::launch_fill<double>(8, 0.0, zero, s));
-    S.zero = zero;
+    int32_t *lglob = nullptr;
+    ILU_TRY(tmp.take(&lglob, S.nlev));
+    ILU_TRY_HIP(ppk::launch_fill<int32_t>(S.nlev, 0, lglob, s));
     ILU_TRY_HIP(hipMemcpyAsync(rs, runstart.data(), S.nlev * sizeof(int32_t),
                                hipMemcpyHostToDevice, s));
     ILU_TRY_HIP(ppk::launch_fill<int32_t>(1, 0, flag, s));
     ILU_TRY_HIP(ppk::launch_sweep_inverse(n, S.row, qpos, s));
     ILU_TRY_HIP(ppk::launch_sweep_sources(n, w, S.nlev, S.lbeg, S.ecol, qpos, rs, S.esrc,
-                                          S.lglob, flag, s));
+                                          lglob, flag, s));
     int32_t far = 0;
+    std::vector<int32_t> hglob(S.nlev);
     ILU_TRY_HIP(hipMemcpyAsync(&far, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ILU_TRY_HIP(hipMemcpyAsync(hglob.data(), lglob, S.nlev * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
     ILU_TRY_HIP(hipStreamSynchronize(s));
-    if (far) S.esrc = nullptr;  // (its buffer stays owned and is freed with the factor)
+    if (far) {
+      S.esrc = nullptr;  // (its buffer stays owned and is freed with the factor)
+    } else {
+      for (ppk::LevelSpan &sp : S.spans)
+        if (sp.run)
+          for (int l = sp.l0; l < sp.l1; ++l) sp.glob = sp.glob || hglob[l] != 0;
+      if (w <= ppk::kRingSlots) {  // LDS-ring runs: their per-position data
+        uint32_t *rslot = nullptr;
+        ILU_TRY(own.take(&rslot, (int64_t)ppk::ring_swords(w) * n));
+        ILU_TRY(own.take(&S.rval, (int64_t)ppk::ring_vstride(w) * n));
+        ILU_TRY_HIP(ppk::launch_ring_pack(n, w, S.esrc, S.eval, upper ? S.diag : nullptr, rslot,
+                                          S.rval, s));
+        S.rslot = rslot;
+      }
+    }
   }
   return PP_OK;
 }
@@ -311,11 +326,18 @@ int pp_ilu0_levels(const pp_ilu *M, int32_t *nlev_forward, int32_t *nlev_backwar
   if (!M) return PP_ERR_ARG;
   if (nlev_forward) *nlev_forward = M->fwd.nlev;
   if (nlev_backward) *nlev_backward = M->bwd.nlev;
-  // the sweeps' spans, plus one level-order gather per sweep that has LDS-ring runs
-  auto gathers = [](const Sweep &S) { return (S.esrc && S.width <= ppk::kRingSlots) ? 1 : 0; };
+  // the sweeps' spans; a sweep with LDS-ring runs adds its level-order gather and,
+  // per run, the scatter of its solutions and (when the run waits for values solved
+  // by earlier launches) the right-hand-side update before it
+  auto extra = [](const Sweep &S) {
+    if (!S.rslot) return 0;
+    int k = 1;
+    for (const ppk::LevelSpan &sp : S.spans) k += sp.run ? (sp.glob ? 2 : 1) : 0;
+    return k;
+  };
   if (launches)
-    *launches = (int32_t)(M->fwd.spans.size() + M->bwd.spans.size() + gathers(M->fwd) +
-                          gathers(M->bwd));
+    *launches = (int32_t)(M->fwd.spans.size() + M->bwd.spans.size() + extra(M->fwd) +
+                          extra(M->bwd));
   return PP_OK;
 }
 
