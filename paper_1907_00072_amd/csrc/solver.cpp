@@ -90,6 +90,7 @@ struct Arena {
   size_t mat_cap = 0;
   double *host = nullptr;  // pinned
   size_t host_cap = 0;     // in doubles
+  hipEvent_t step_ev[2] = {nullptr, nullptr};  // completion of an Arnoldi step, per host slot
 };
 std::vector<Arena> g_arena;
 
@@ -128,6 +129,11 @@ int ensure_arena(Arena *a, size_t dev_bytes, size_t host_doubles) {
     }
     a->host_cap = host_doubles;
   }
+  for (hipEvent_t &e : a->step_ev)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      return PP_ERR_HIP;
+    }
   return PP_OK;
 }
 
@@ -230,7 +236,10 @@ struct Work {
   double *hbuf = nullptr;      // [2L + 8]: h1 | h2 | nrm
   double *coef1 = nullptr, *coef2 = nullptr, *ybuf = nullptr;  // [L] each
   double *misc = nullptr;      // [16]
-  double *host = nullptr;      // pinned [2L + 8 + L]
+  // pinned: two slots of 2L + 8 (an Arnoldi step's Hessenberg column h1 | h2 | nrm,
+  // slot j & 1 for step j), then the staging of y [L] and 16 spare
+  double *host = nullptr;
+  hipEvent_t step_ev[2] = {nullptr, nullptr};  // step j done: step_ev[j & 1]
   int32_t *fold_counter = nullptr;  // ticket counter of the folded reductions
   bool fold_armed = false;          // fold_counter zeroed on the device
   bool fold_ok = false;             // folded reductions asked for (PP_FOLD=1)
@@ -261,39 +270,65 @@ struct Work {
     fold_armed = false;
     fold_ok = fold_enabled();
   }
-  size_t host_doubles() const { return 3 * (size_t)L + 16; }
+  size_t host_doubles() const { return 2 * hslot_doubles() + (size_t)L + 16; }
+  size_t hslot_doubles() const { return 2 * (size_t)L + 8; }
+  double *hslot(int j) const { return host + (size_t)(j & 1) * hslot_doubles(); }
+  double *ystage() const { return host + 2 * hslot_doubles(); }
+  void attach(const Arena &a) {
+    host = a.host;
+    step_ev[0] = a.step_ev[0];
+    step_ev[1] = a.step_ev[1];
+  }
 };
 
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// Event-timed phases of the Arnoldi steps: one set of events per host slot (step j
+// uses set j & 1), so a step issued ahead does not overwrite the events of the
+// step still to be collected.
 struct Timers {
   bool on = false;
-  hipEvent_t ev[5] = {};
-  double chain = 0, spmv = 0, orth = 0, host = 0;
+  hipEvent_t ev[2][4] = {};
+  int slot = 0;         // the set mark() records into
+  double t_last = 0.0;  // wall clock at the previous step's collection
   int init() {
-    for (auto &e : ev)
-      if (hipEventCreate(&e) != hipSuccess) return PP_ERR_HIP;
+    for (auto &set : ev)
+      for (auto &e : set)
+        if (hipEventCreate(&e) != hipSuccess) return PP_ERR_HIP;
     return PP_OK;
   }
   ~Timers() {
-    for (auto &e : ev)
-      if (e) (void)hipEventDestroy(e);
+    for (auto &set : ev)
+      for (auto &e : set)
+        if (e) (void)hipEventDestroy(e);
   }
   void mark(int k, hipStream_t s) {
-    if (on) (void)hipEventRecord(ev[k], s);
+    if (on) (void)hipEventRecord(ev[slot][k], s);
   }
-  // Accumulate the event-timed phases of one Arnoldi step; the rest of the
-  // step's wall time (launch latency, the copy and synchronisation, host least
-  // squares) is counted as host time.
-  void collect(double wall) {
+  void start() {
+    if (on) t_last = now_s();
+  }
+  // Accumulate the event-timed phases of the step of set `set`; the rest of the wall
+  // time since the previous collection (launch latency, synchronisation, host least
+  // squares, whatever the device phases do not cover) is counted as host time.
+  void collect(int set) {
     if (!on) return;
+    const double now = now_s();
+    const double wall = now - t_last;
+    t_last = now;
     float a = 0, b = 0, c = 0;
-    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
-    (void)hipEventElapsedTime(&b, ev[1], ev[2]);
-    (void)hipEventElapsedTime(&c, ev[2], ev[3]);
+    (void)hipEventElapsedTime(&a, ev[set][0], ev[set][1]);
+    (void)hipEventElapsedTime(&b, ev[set][1], ev[set][2]);
+    (void)hipEventElapsedTime(&c, ev[set][2], ev[set][3]);
     chain += a * 1e-3;
     spmv += b * 1e-3;
     orth += c * 1e-3;
     host += std::max(0.0, wall - (a + b + c) * 1e-3);
   }
+  double chain = 0, spmv = 0, orth = 0, host = 0;
 };
 
 struct Counters {
@@ -307,11 +342,6 @@ struct Counters {
     if (history && history_len < history_cap) history[history_len++] = v;
   }
 };
-
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
-      .count();
-}
 
 inline bool finite(double v) { return std::isfinite(v); }
 
@@ -646,15 +676,17 @@ int dots_any(Work<T> &w, int nc, const T *vec, hipStream_t s, int *G, bool cache
   return PP_OK;
 }
 
-// One Arnoldi step j: w = Op(V_j), two CGS passes, V_{j+1} = w / ||w||.
-// hcol[0..j+1] receives column j of Hbar; *w0 an estimate of ||Op(V_j)||.
-// Returns PP_OK, or PP_WARN_NONFINITE when a coefficient is not finite.
+// The device part of Arnoldi step j: w = Op(V_j), two CGS passes, V_{j+1} =
+// w / ||w||, column j of Hbar (h1 | h2 | nrm) written to the pinned host slot
+// w.hslot(j) and the slot's event recorded.  Nothing waits on the host, so step
+// j + 1 can be issued before step j is collected: its input V_{j+1} is made on the
+// device, and it writes the other slot.
 template <typename T>
-int arnoldi_step(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int j,
-                 hipStream_t s, Timers &tm, Counters &cnt, double *hcol, double *w0) {
+int arnoldi_issue(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int j,
+                  hipStream_t s, Timers &tm, Counters &cnt) {
   const T *vj = w.V + (int64_t)j * w.ldv;
   const double *sj = w.colscale + j;
-  const double t_wall0 = tm.on ? now_s() : 0.0;
+  tm.slot = j & 1;
   tm.mark(0, s);
   if (pr.active() && !pr.power() && op_form == PP_OP_RESIDUAL_POLY) {
     PP_TRY(run_op_chain<T>(A, *pr.steps, vj, sj, w.W, w.P0, w.P1, w.Tb, s, &cnt,
@@ -732,7 +764,7 @@ int arnoldi_step(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, in
     f.nrm = nrm;
     f.inv = w.colscale + j + 1;
     f.copy_src = w.hbuf;
-    f.copy_dst = w.host;
+    f.copy_dst = w.hslot(j);
     f.copy_n = hcount;
     f.nrm_at = 2 * L;
     PP_TRY_HIP(ppk::launch_update<T>(w.n, rpt3, w.V, w.ldv, nc, w.coef2, nullptr, 1.0, w.W,
@@ -740,27 +772,113 @@ int arnoldi_step(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, in
   } else {
     PP_TRY(update_any<T>(w, nc, w.coef2, w.W, vnext, true, s, &G3, keep));
     PP_TRY_HIP(ppk::launch_reduce_norm(w.partial, G3, nrm, w.colscale + j + 1, s, w.hbuf,
-                                       w.host, hcount, 2 * L));
+                                       w.hslot(j), hcount, 2 * L));
   }
   cnt.dots += 3;
   // three sweeps over nc basis columns; w read three times and written twice
   cnt.bytes_orth += (double)sizeof(T) * w.n * (3.0 * nc + 5.0);
   tm.mark(3, s);
-  PP_TRY_HIP(hipStreamSynchronize(s));
+  PP_TRY_HIP(hipEventRecord(w.step_ev[j & 1], s));
+  return PP_OK;
+}
+
+// The host part of Arnoldi step j (issued by arnoldi_issue): waits for its slot,
+// hcol[0..j+1] receives column j of Hbar and *w0 an estimate of ||Op(V_j)||.
+// Returns PP_OK, or PP_WARN_NONFINITE when a coefficient is not finite.
+template <typename T>
+int arnoldi_collect(Work<T> &w, int j, Timers &tm, double *hcol, double *w0) {
+  PP_TRY_HIP(hipEventSynchronize(w.step_ev[j & 1]));
+  const int nc = j + 1, L = w.L;
+  const double *h = w.hslot(j);
   double a2 = 0.0;
   bool ok = true;
   for (int i = 0; i < nc; ++i) {
-    const double x1 = w.host[i], x2 = w.host[L + i];
+    const double x1 = h[i], x2 = h[L + i];
     hcol[i] = x1 + x2;
     a2 += x1 * x1 + x2 * x2;
     ok = ok && finite(x1) && finite(x2);
   }
-  const double hn = w.host[2 * L];
+  const double hn = h[2 * L];
   hcol[j + 1] = hn;
   *w0 = std::sqrt(a2 + hn * hn);
-  if (tm.on) tm.collect(now_s() - t_wall0);
+  tm.collect(j & 1);
   return (ok && finite(hn)) ? PP_OK : PP_WARN_NONFINITE;
 }
+
+// Device work of the step issued ahead, in the counters, so that it can be taken
+// back when the cycle stops before that step.
+struct IssueCounts {
+  int64_t spmvs = 0, dots = 0, launches_chain = 0;
+  double bytes_chain = 0, bytes_spmv = 0, bytes_orth = 0;
+  static IssueCounts of(const Counters &c) {
+    return IssueCounts{c.spmvs, c.dots, c.launches_chain, c.bytes_chain, c.bytes_spmv,
+                       c.bytes_orth};
+  }
+};
+
+// Lookahead: a step's device work is issued before the previous step is collected
+// (the host's wait, least squares and launches then overlap the device), when a
+// step is short enough that the host's share matters (at most kLookaheadBytes of
+// estimated traffic).  When the cycle stops at step j, a step j + 1 already issued
+// is wasted device work (its results are never read; V(:, j + 2) is past the
+// cycle's columns), one step per stop.  PP_LOOKAHEAD=0 turns it off.
+constexpr double kLookaheadBytes = 512.0 * 1024 * 1024;
+
+bool lookahead_enabled() {
+  static const bool on = [] {
+    const char *v = std::getenv("PP_LOOKAHEAD");
+    return !(v && std::atoi(v) == 0);
+  }();
+  return on;
+}
+
+template <typename T>
+struct StepPipe {
+  const Opr<T> &A;
+  const PolyRef &pr;
+  int op_form;
+  Work<T> &w;
+  hipStream_t s;
+  Timers &tm;
+  Counters &cnt;
+  int issued = -1;  // highest step issued
+  IssueCounts before, after;  // counters around the last issue
+
+  double step_bytes(int j) const {
+    int products = 1;
+    if (pr.power()) {
+      products += (int)pr.coeffs->size() - 1;
+    } else if (pr.active()) {
+      for (const ppn::Step &st : *pr.steps) products += st.kind == 0 ? 1 : 2;
+    }
+    return products * product_bytes(A, 1) + (double)sizeof(T) * w.n * (3.0 * (j + 1) + 5.0);
+  }
+  int issue(int j) {
+    before = IssueCounts::of(cnt);
+    PP_TRY(arnoldi_issue<T>(A, pr, op_form, w, j, s, tm, cnt));
+    after = IssueCounts::of(cnt);
+    issued = j;
+    return PP_OK;
+  }
+  // Step j's column, with step j + 1 (< jmax) issued first when lookahead applies.
+  int next(int j, int jmax, double *hcol, double *w0) {
+    if (issued < j) PP_TRY(issue(j));
+    if (j + 1 < jmax && lookahead_enabled() && step_bytes(j + 1) <= kLookaheadBytes)
+      PP_TRY(issue(j + 1));
+    return arnoldi_collect<T>(w, j, tm, hcol, w0);
+  }
+  // The caller stops after step j: a step issued past it leaves the counters.
+  void stop(int j) {
+    if (issued <= j) return;
+    cnt.spmvs -= after.spmvs - before.spmvs;
+    cnt.dots -= after.dots - before.dots;
+    cnt.launches_chain -= after.launches_chain - before.launches_chain;
+    cnt.bytes_chain -= after.bytes_chain - before.bytes_chain;
+    cnt.bytes_spmv -= after.bytes_spmv - before.bytes_spmv;
+    cnt.bytes_orth -= after.bytes_orth - before.bytes_orth;
+    issued = j;
+  }
+};
 
 // Start column: V(:,0) = (T) src (device double), colscale[0] = 1/||.||; returns the norm.
 template <typename T>
@@ -787,14 +905,18 @@ int build_poly_impl(const Opr<T> &A, const double *v0, int d, Work<T> &w, hipStr
   const int ldh = d + 1;
   std::vector<double> Hbar((size_t)ldh * d, 0.0), hcol(d + 1);
   int sdim = d;
+  const PolyRef none{};
+  StepPipe<T> pipe{A, none, 0, w, s, tm, cnt};
+  tm.start();
   for (int j = 0; j < d; ++j) {
     double w0 = 0.0;
-    int rc = arnoldi_step<T>(A, PolyRef{}, 0, w, j, s, tm, cnt, hcol.data(), &w0);
+    int rc = pipe.next(j, d, hcol.data(), &w0);
     if (rc < 0) return rc;
     if (rc == PP_WARN_NONFINITE) return PP_ERR_SINGULAR;
     for (int i = 0; i <= j + 1; ++i) Hbar[i + (size_t)j * ldh] = hcol[i];
     if (hcol[j + 1] <= kBreakdownRtol * w0) {
       sdim = j + 1;
+      pipe.stop(j);
       break;
     }
   }
@@ -927,13 +1049,16 @@ int gmres_cycle(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int
   *res = beta;
   *nonfinite = false;
   const int jmax = std::min(m, max_steps);
+  StepPipe<T> pipe{A, pr, op_form, w, s, tm, cnt};
+  tm.start();
   for (int j = 0; j < jmax; ++j) {
     double w0 = 0.0;
-    int rc = arnoldi_step<T>(A, pr, op_form, w, j, s, tm, cnt, hcol.data(), &w0);
+    int rc = pipe.next(j, jmax, hcol.data(), &w0);
     if (rc < 0) return rc;
     cnt.iters++;
     if (rc == PP_WARN_NONFINITE) {
       *nonfinite = true;
+      pipe.stop(j);
       break;
     }
     const double hn = hcol[j + 1];
@@ -945,9 +1070,13 @@ int gmres_cycle(const Opr<T> &A, const PolyRef &pr, int op_form, Work<T> &w, int
                    j + 1, *res / bscale);
     if (!finite(*res)) {
       *nonfinite = true;
+      pipe.stop(j);
       break;
     }
-    if (hn <= kBreakdownRtol * w0 || *res < tol_abs) break;
+    if (hn <= kBreakdownRtol * w0 || *res < tol_abs) {
+      pipe.stop(j);
+      break;
+    }
   }
   y.assign(std::max(*k, 1), 0.0);
   if (*k > 0 && !*nonfinite) {
@@ -964,8 +1093,8 @@ int cycle_update(const Opr<T> &A, const PolyRef &pr, Work<T> &w, int k,
                  const std::vector<double> &y, const T *x_in, T *x_out, hipStream_t s,
                  Counters &cnt) {
   if (k <= 0) return PP_OK;
-  std::memcpy(w.host + 2 * w.L + 8, y.data(), k * sizeof(double));
-  PP_TRY_HIP(hipMemcpyAsync(w.ybuf, w.host + 2 * w.L + 8, k * sizeof(double),
+  std::memcpy(w.ystage(), y.data(), k * sizeof(double));
+  PP_TRY_HIP(hipMemcpyAsync(w.ybuf, w.ystage(), k * sizeof(double),
                             hipMemcpyHostToDevice, s));
   const bool poly = pr.active();
   const int rpt =
@@ -1290,7 +1419,7 @@ int build_impl(const pp_csr *A, const double *v0, int d, hipStream_t s, pp_poly 
   PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
   Carver c(ar->dev);
   w.carve(c, n, d + 1);
-  w.host = ar->host;
+  w.attach(*ar);
   if (!v0) {
     v0gen = c.take<double>(n);
     PP_TRY_HIP(ppk::launch_uniform_pm1(n, kDefaultSeed, v0gen, s));
@@ -1415,7 +1544,7 @@ int solve_f64(const SolveIn &in, pp_stats *st) {
   prod = in.ilu ? c.take<double>(n) : nullptr;
   iscratch = c.take<int32_t>(64);
   v0gen = draw_v0 ? c.take<double>(n) : nullptr;
-  w.host = ar->host;
+  w.attach(*ar);
   Opr<double> A(with_sell(view<double>(in.A, in.A->vals), sc));
   A.ilu = in.ilu;
   A.prod = prod;
@@ -1561,8 +1690,8 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
   xsave = c.take<double>(n);
   iscratch = c.take<int32_t>(64);
   v0gen = draw_v0 ? c.take<double>(n) : nullptr;
-  w.host = ar->host;
-  w64.host = ar->host;
+  w.attach(*ar);
+  w64.attach(*ar);
   hipStream_t s = in.s;
   const SpMat<double> A64 = with_sell(view<double>(in.A, in.A->vals), sc);
   if (cast32) PP_TRY_HIP(ppk::launch_cast_f32(nnz, (const double *)in.A->vals, vals32, s));
@@ -1845,7 +1974,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
     PP_TRY(ensure_arena(ar, meas.off + 256, w.host_doubles()));
     Carver c(ar->dev);
     w.carve(c, n, 1);
-    w.host = ar->host;
+    w.attach(*ar);
     double bn = 0.0, rn = 0.0;
     PP_TRY(norm_f64(w, b, in.s, &bn));
     PP_TRY(residual_f64(view<double>(A, A->vals), w, b, x, in.s, &rn));
@@ -1881,7 +2010,7 @@ int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_deg
     Carver c(ar->dev);
     w.carve(c, n, L);
     double *gram = c.take<double>((size_t)L * L);
-    w.host = ar->host;
+    w.attach(*ar);
     const double *start = v0;
     if (!v0) {
       double *v0gen = c.take<double>(n);
@@ -2035,6 +2164,8 @@ void pp_release_workspace(void) {
     if (a.aux) (void)hipFree(a.aux);
     if (a.mat) (void)hipFree(a.mat);
     if (a.host) (void)hipHostFree(a.host);
+    for (hipEvent_t e : a.step_ev)
+      if (e) (void)hipEventDestroy(e);
     a = Arena{};
   }
   (void)hipSetDevice(cur);
