@@ -224,6 +224,12 @@ bool fold_enabled() {
   return v && std::atoi(v) != 0;
 }
 
+// One-step lookahead of short Arnoldi steps (see StepPipe); PP_LOOKAHEAD=0 turns it off.
+bool lookahead_enabled() {
+  const char *v = std::getenv("PP_LOOKAHEAD");
+  return !(v && std::atoi(v) == 0);
+}
+
 // Device workspace of one solve in compute type T.
 template <typename T>
 struct Work {
@@ -243,6 +249,7 @@ struct Work {
   int32_t *fold_counter = nullptr;  // ticket counter of the folded reductions
   bool fold_armed = false;          // fold_counter zeroed on the device
   bool fold_ok = false;             // folded reductions asked for (PP_FOLD=1)
+  bool lookahead_ok = true;         // short steps issued one ahead (PP_LOOKAHEAD)
 
   template <typename C>
   void carve(C &c, int n_, int L_) {
@@ -269,6 +276,7 @@ struct Work {
     fold_counter = c.template take<int32_t>(64);
     fold_armed = false;
     fold_ok = fold_enabled();
+    lookahead_ok = lookahead_enabled();
   }
   size_t host_doubles() const { return 2 * hslot_doubles() + (size_t)L + 16; }
   size_t hslot_doubles() const { return 2 * (size_t)L + 8; }
@@ -824,13 +832,6 @@ struct IssueCounts {
 // cycle's columns), one step per stop.  PP_LOOKAHEAD=0 turns it off.
 constexpr double kLookaheadBytes = 512.0 * 1024 * 1024;
 
-bool lookahead_enabled() {
-  static const bool on = [] {
-    const char *v = std::getenv("PP_LOOKAHEAD");
-    return !(v && std::atoi(v) == 0);
-  }();
-  return on;
-}
 
 template <typename T>
 struct StepPipe {
@@ -863,7 +864,7 @@ struct StepPipe {
   // Step j's column, with step j + 1 (< jmax) issued first when lookahead applies.
   int next(int j, int jmax, double *hcol, double *w0) {
     if (issued < j) PP_TRY(issue(j));
-    if (j + 1 < jmax && lookahead_enabled() && step_bytes(j + 1) <= kLookaheadBytes)
+    if (j + 1 < jmax && w.lookahead_ok && step_bytes(j + 1) <= kLookaheadBytes)
       PP_TRY(issue(j + 1));
     return arnoldi_collect<T>(w, j, tm, hcol, w0);
   }

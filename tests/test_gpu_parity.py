@@ -912,6 +912,39 @@ def test_folded_reductions_are_bitwise_the_separate_launches(B, cfg, N, precisio
     assert np.array_equal(s1.history, s0.history)
 
 
+@pytest.mark.parametrize("cfg,N,precision,m", [(1, None, "f64", None), (4, 96, "f64", None),
+                                               (4, 96, "f64", 7), (3, 12, "f32_ir", None),
+                                               (1, None, "f64_plain", 13)])
+def test_lookahead_is_bitwise_the_serial_steps(B, cfg, N, precision, m, monkeypatch):
+    """Short Arnoldi steps are issued one ahead of the host (the device part of step
+    j + 1 before step j's column is read); PP_LOOKAHEAD=0 runs them one at a time.
+    Same kernels in the same order: the same bits, iteration counts, residual
+    history and counters (a step issued past a cycle's stop is taken back out of
+    them).  Restart cycles of 7 and 13 steps stop both at the cycle's end and in its
+    middle."""
+    import warnings
+    P = W.config(cfg, N=N) if N else W.config(cfg)
+    A = B.CSRMatrix.from_host(P.A)
+    kw = dict(m=m or P.m, d=P.d, tol=P.tol, v0=_up(P.v0), history=4000, max_iters=4000)
+    if precision == "f32_ir":
+        kw.update(precision="f32_ir", inner_tol=1e-5)
+    if precision == "f64_plain":
+        kw.update(d=0)
+    runs = []
+    for la in ("1", "0"):
+        monkeypatch.setenv("PP_LOOKAHEAD", la)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", B.PPWarning)
+            x, st = B.pp_gmres_solve(A, _up(P.b), **kw)
+        runs.append((x, st))
+    (x1, s1), (x0, s0) = runs
+    assert s1.iters == s0.iters and s1.cycles == s0.cycles and s1.iters > 0
+    assert torch.equal(x1, x0)
+    assert np.array_equal(s1.history, s0.history)
+    assert (s1.spmvs, s1.dots) == (s0.spmvs, s0.dots)
+    assert s1.bytes_chain == s0.bytes_chain and s1.bytes_orth == s0.bytes_orth
+
+
 @pytest.mark.parametrize("block,layout", [(None, "auto"), (None, "sell"), (None, "csr"),
                                           (4096, "auto")])
 def test_permuted_stencil_solve_matches_oracle(B, block, layout):
