@@ -60,10 +60,26 @@ def _matrix(name):
         return W.random_csr(900, 10, seed=31, diag_shift=6.0).to_scipy()
     if name == "tridiag_500":
         return _tridiag(500)
+    if name == "ninept_48":  # four entries a row in each triangle: the widest LDS-ring rows
+        return _nine_point(48)
     raise KeyError(name)
 
 
-NAMES = ["recirc_33", "recirc_1", "cd3d_40", "stencil27_12", "rand_900", "tridiag_500"]
+def _nine_point(N):
+    # 2D nine-point stencil with seeded perturbations, diagonally dominant
+    rng = np.random.default_rng(43)
+    T = sp.diags([-1.0, 0.0, -1.0], [-1, 0, 1], shape=(N, N))
+    I = sp.identity(N)
+    A = (sp.kron(I, T) + sp.kron(T, I) + sp.kron(T, T)).tocsr()
+    A.data = A.data * (1.0 + 0.3 * rng.uniform(-1, 1, A.nnz))
+    A = A + sp.diags(9.0 + rng.uniform(0, 1, N * N))
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    return A
+
+
+NAMES = ["recirc_33", "recirc_1", "cd3d_40", "stencil27_12", "rand_900", "tridiag_500",
+         "ninept_48"]
 _cache = {}
 
 
@@ -97,6 +113,9 @@ def test_levels_match_oracle(B, name):
         assert f == b == 2 * 33 - 1 and launches == 6
     if name == "cd3d_40":
         assert f == b == 3 * 40 - 2 and launches > 2  # wide levels get their own launch
+    if name == "ninept_48":
+        # level of (x, y) is x + 2 y in both directions: one ring run per sweep
+        assert f == b == 3 * 48 - 2 and launches == 6
 
 
 @pytest.mark.parametrize("name", NAMES)
