@@ -805,7 +805,7 @@ static void launch_ring(const Sweep &S, const LevelSpan &sp, int n, double *work
 template <bool BACK>
 static void launch_slot_run(const Sweep &S, const LevelSpan &sp, int n, const double *rhs,
                             double *work, double *out, hipStream_t stream) {
-  if (S.rslot) {
+  if (S.rslot && sp.l1 - sp.l0 <= kRunLevels) {  // (make_spans keeps every run that short)
     switch (S.width) {
       case 1: launch_ring<1>(S, sp, n, work, out, stream); break;
       case 2: launch_ring<2>(S, sp, n, work, out, stream); break;
