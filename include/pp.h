@@ -139,7 +139,9 @@ typedef struct pp_ilu pp_ilu;
 typedef struct pp_opts {
   int32_t max_iters;      /* cap on Arnoldi steps (inner steps for F32_IR); 0 -> 100000 */
   int32_t precision;      /* PP_PREC_F64 (0) or PP_PREC_F32_IR */
-  double inner_tol;       /* F32_IR: inner cycle stops at this relative reduction; 0 -> 1e-5 */
+  double inner_tol;       /* F32_IR: inner cycle stops at this relative reduction; 0 ->
+                             automatic: 1e-5, or 0.5 tol / relres when that is larger (a
+                             refinement step needing less reduction stops earlier) */
   int32_t max_outer;      /* F32_IR: cap on refinement steps; 0 -> 100 */
   const double *v0;       /* device[n] start vector for the polynomial; NULL -> the
                              seeded U(-1, 1) vector pp_uniform_vector(n, v0_seed) drawn

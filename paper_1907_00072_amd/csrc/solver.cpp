@@ -66,6 +66,10 @@ constexpr int kSlabPerBandwidth = 8;
 constexpr int kAllLaunches = 1 << 20;
 // seed of the start vector drawn when pp_build_poly / pp_build_poly_power get none
 constexpr uint64_t kDefaultSeed = 0;
+// FP32 refinement: default inner relative reduction, and the margin of the
+// automatic looser one on a step close to tol (see solve_f32_ir)
+constexpr double kInnerTolDefault = 1e-5;
+constexpr double kInnerMargin = 0.5;
 
 #define PP_TRY_HIP(expr) PPD_TRY_HIP(expr, PP_ERR_HIP)
 #define PP_TRY(expr)                                  \
@@ -1756,7 +1760,11 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
   if (st) st->nroots = in.o.poly ? poly_size(in.o.poly) : (in.d > 0 ? (int)built.re.size() : 0);
   const int max_iters = in.o.max_iters > 0 ? in.o.max_iters : 100000;
   const int max_outer = in.o.max_outer > 0 ? in.o.max_outer : 100;
-  const double inner_tol = in.o.inner_tol > 0 ? in.o.inner_tol : 1e-5;
+  // inner stop: a given inner_tol as it is; by default 1e-5, loosened on a
+  // refinement step that needs less to kInnerMargin * tol / relres, the reduction
+  // still missing with a margin, so the last inner cycle does not overshoot
+  const bool inner_auto = !(in.o.inner_tol > 0);
+  const double inner_floor = inner_auto ? kInnerTolDefault : in.o.inner_tol;
   double relres = 0.0, relimp = 0.0;
   std::vector<double> y;
   double *r64 = w64.V;  // FP64 residual
@@ -1796,6 +1804,8 @@ int solve_f32_ir(const SolveIn &in, pp_stats *st) {
     int k = 0;
     double res = 0.0;
     bool nonfinite = false;
+    const double inner_tol =
+        inner_auto ? std::max(inner_floor, kInnerMargin * in.tol / relres) : inner_floor;
     PP_TRY(gmres_cycle<float>(A32, steps, in.o.op_form, w, in.m, beta_in, inner_tol * beta_in,
                               beta_in,
                               max_iters - cnt.iters, s, tm, cnt, y, &k, &res, &nonfinite));

@@ -151,6 +151,30 @@ def test_iterative_refinement_fp32_inner():
     assert np.max(np.abs(np.sort(st.roots.real) - np.sort(r64.real)) / np.abs(np.sort(r64.real))) < 1e-3
 
 
+def test_iterative_refinement_automatic_inner_stop():
+    """inner_tol = None: each inner cycle stops once its implicit residual drops
+    below tau_k = max(1e-5, 0.5 tol / relres_k) (relative to ||r_k||).  Checked
+    against runs with that tau fixed: the first refinement step (relres_0 = 1)
+    is the fixed 1e-5 run's first step, and a second step near tol stops at the
+    looser tau, so the automatic run takes fewer inner steps and still converges."""
+    P = W.config(1)
+    A = P.A.to_scipy()
+    tol = 1e-8
+    xa, sa = gmres.pp_gmres_ir(A, P.b, P.m, P.d, tol, P.v0, max_outer=20)
+    xf, sf = gmres.pp_gmres_ir(A, P.b, P.m, P.d, tol, P.v0, inner_tol=1e-5, max_outer=20)
+    assert sa.converged and sf.converged and sa.outer >= 2
+    # both start with the same step: same polynomial, same first inner cycle
+    assert sa.true_history[:2] == sf.true_history[:2]
+    # the automatic second inner cycle stops at its own tau, never below it
+    tau1 = max(1e-5, 0.5 * tol / sa.true_history[1])
+    assert tau1 > 1e-5
+    _, s1 = gmres.pp_gmres_ir(A, P.b, P.m, P.d, tol, P.v0, inner_tol=1e-5, max_outer=1)
+    k1 = s1.iters                        # inner steps of the first refinement step
+    second = sa.history[k1:]
+    assert second[-1] < tau1 and (len(second) == 1 or second[-2] >= tau1)
+    assert sa.iters < sf.iters
+
+
 @pytest.mark.parametrize("cfg,N", [(1, None), (4, 128)])
 def test_iterative_refinement_inner_arithmetic_is_fp32(cfg, N):
     """The refinement's inner cycle and its polynomial run in FP32, not FP64.
