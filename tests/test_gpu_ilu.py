@@ -60,6 +60,12 @@ def _matrix(name):
         return W.random_csr(900, 10, seed=31, diag_shift=6.0).to_scipy()
     if name == "tridiag_500":
         return _tridiag(500)
+    if name == "tridiag_5000":  # 5000 one-row levels: a chain longer than one run holds
+        return _tridiag(5000)
+    if name == "tridiag_5000":
+        # each sweep: two runs (4096 + 904 levels); the second waits for the first's last
+        # row, taken out of its right-hand side first: gather, 2 x (run, scatter), update
+        assert f == b == 5000 and launches == 12
     if name == "ninept_48":  # four entries a row in each triangle: the widest LDS-ring rows
         return _nine_point(48)
     raise KeyError(name)
@@ -79,7 +85,7 @@ def _nine_point(N):
 
 
 NAMES = ["recirc_33", "recirc_1", "cd3d_40", "stencil27_12", "rand_900", "tridiag_500",
-         "ninept_48"]
+         "ninept_48", "tridiag_5000"]
 _cache = {}
 
 
@@ -113,6 +119,10 @@ def test_levels_match_oracle(B, name):
         assert f == b == 2 * 33 - 1 and launches == 6
     if name == "cd3d_40":
         assert f == b == 3 * 40 - 2 and launches > 2  # wide levels get their own launch
+    if name == "tridiag_5000":
+        # each sweep: two runs (4096 + 904 levels); the second waits for the first's last
+        # row, taken out of its right-hand side first: gather, 2 x (run, scatter), update
+        assert f == b == 5000 and launches == 12
     if name == "ninept_48":
         # level of (x, y) is x + 2 y in both directions: one ring run per sweep
         assert f == b == 3 * 48 - 2 and launches == 6
@@ -197,6 +207,23 @@ def test_composed_solve_product_form_and_determinism(B):
     x3, s3 = B.pp_gmres_solve(Ad, _up(b), m=50, d=8, tol=1e-8, v0=v0, left_ilu=M, op_form="p")
     assert s3.relres_true < 1e-8 and abs(s3.iters - s1.iters) <= 1
     assert _rel(x3.cpu().numpy(), x1.cpu().numpy()) <= 1e-5
+
+
+def test_composed_solve_lookahead_is_bitwise(B, monkeypatch):
+    # the one-step lookahead of short Arnoldi steps (PP_LOOKAHEAD=0: one at a time)
+    A, b = W.recirculating_flow(33)
+    Ad = B.CSRMatrix.from_host(A)
+    M = B.pp_ilu0_factor(Ad)
+    v0 = _up(W.uniform(A.n, 106))
+    runs = []
+    for la in ("1", "0"):
+        monkeypatch.setenv("PP_LOOKAHEAD", la)
+        runs.append(B.pp_gmres_solve(Ad, _up(b), m=4, d=8, tol=1e-10, v0=v0, left_ilu=M,
+                                     history=500))
+    (x1, s1), (x0, s0) = runs
+    assert s1.iters == s0.iters and s1.cycles == s0.cycles and s1.cycles > 1
+    assert torch.equal(x1, x0) and np.array_equal(s1.history, s0.history)
+    assert (s1.spmvs, s1.dots) == (s0.spmvs, s0.dots)
 
 
 def test_chain_schedule_is_ignored_with_ilu(B):
