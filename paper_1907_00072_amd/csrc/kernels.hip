@@ -69,6 +69,81 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sums over the 64 lanes of a wavefront of NCB per-lane values (one per basis
+// column), by recursive halving: in round r (lane distance d = 32 >> r) a lane keeps
+// one half of its current values, the lower half when bit d of its lane is clear,
+// and adds its partner's (lane ^ d) copy of that half, so after H rounds each lane
+// holds NCB >> H values, and a butterfly over the remaining low lane bits completes
+// them.  H is the number of times NCB halves evenly (at most 6).  On return a[k],
+// k < NCB >> H, is the wavefront's sum of column first + k, first being returned;
+// the lanes that differ only in the low 6 - H bits hold the same columns and the
+// same bits (a + b == b + a).  About NCB shuffles in all, against 6 per column for
+// a butterfly per column.
+constexpr int halvings(int ncb) {
+  int h = 0;
+  while (h < 6 && ncb % 2 == 0) {
+    ncb /= 2;
+    ++h;
+  }
+  return h;
+}
+
+// Round R of wave_col_sums (a template per round, so every array index is a
+// compile-time constant and the values stay in registers).
+template <int NCB, int R>
+__device__ __forceinline__ void col_halve(double (&a)[NCB], int lane, int &first) {
+  if constexpr (R < halvings(NCB)) {
+    constexpr int d = 32 >> R, half = NCB >> (R + 1);
+    const bool up = (lane & d) != 0;
+#pragma unroll
+    for (int k = 0; k < half; ++k) {
+      const double give = up ? a[k] : a[k + half];
+      const double keep = up ? a[k + half] : a[k];
+      a[k] = keep + __shfl_xor(give, d, 64);
+    }
+    first += up ? half : 0;
+    col_halve<NCB, R + 1>(a, lane, first);
+  } else if constexpr (R < 6) {
+    constexpr int d = 32 >> R;
+#pragma unroll
+    for (int k = 0; k < (NCB >> halvings(NCB)); ++k) a[k] += __shfl_xor(a[k], d, 64);
+    col_halve<NCB, R + 1>(a, lane, first);
+  }
+}
+
+template <int NCB>
+__device__ __forceinline__ int wave_col_sums(double (&a)[NCB], int lane) {
+  int first = 0;
+  col_halve<NCB, 0>(a, lane, first);
+  return first;
+}
+
+// The per-workgroup partial dots of nc (<= NCB) columns from every thread's acc:
+// the wavefront sums (wave_col_sums) into red[wave][column], then thread c adds
+// the four waves' sums of column c in a fixed order and writes it to
+// partial[(c0 + c) * gridDim.x + blockIdx.x].
+template <int NCB, typename T>
+__device__ __forceinline__ void block_col_partials(const T (&acc)[NCB], int nc, int c0,
+                                                   double (*red)[NCB],
+                                                   double *__restrict__ partial) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int H = halvings(NCB), M = NCB >> H;
+  double a[NCB];
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) a[c] = (double)acc[c];
+  const int first = wave_col_sums<NCB>(a, lane);
+  if ((lane & ((1 << (6 - H)) - 1)) == 0) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) red[wv][first + k] = a[k];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nc) {
+    const int c = threadIdx.x;
+    partial[(int64_t)(c0 + c) * gridDim.x + blockIdx.x] =
+        ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+  }
+}
+
 // Sum over the 256 threads of a workgroup, identical on every thread.
 __device__ __forceinline__ double block_sum(double v, double *red4) {
   v = wave_sum(v);
@@ -632,20 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(int n, int rpt, const T *__rest
       for (int c = 0; c < NCB; ++c) acc[c] += v[c] * wi;
     }
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < NCB; ++c) {
-    if (c < nc) {
-      const double s = wave_sum((double)acc[c]);
-      if (lane == 0) red[wv][c] = s;
-    }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < nc) {
-    const int c = threadIdx.x;
-    partial[(int64_t)(c0 + c) * gridDim.x + blockIdx.x] =
-        ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
-  }
+  block_col_partials<NCB>(acc, nc, c0, red, partial);
   if constexpr (FOLD) {
     if (last_to_arrive(f.counter)) fold_cols(partial, gridDim.x, c0, nc, f);
   }
@@ -692,20 +754,7 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, int rpt, const T *__re
     }
   }
   if constexpr (DOTS) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < NCB; ++c) {
-      if (c < nc) {
-        const double s = wave_sum((double)acc[c]);
-        if (lane == 0) red[wv][c] = s;
-      }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nc) {
-      const int c = threadIdx.x;
-      partial[(int64_t)c * gridDim.x + blockIdx.x] =
-          ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
-    }
+    block_col_partials<NCB>(acc, nc, 0, red, partial);
     if constexpr (FOLD) {
       if (last_to_arrive(f.counter)) fold_cols(partial, gridDim.x, 0, nc, f);
     }
