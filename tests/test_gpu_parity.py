@@ -857,6 +857,24 @@ def test_arnoldi_breakdown_reduces_the_degree(B):
     assert roots.size == 1 and abs(roots[0] - dg[3]) <= 1e-13 * dg[3]
 
 
+@pytest.mark.parametrize("d", [0, 3])
+def test_lucky_breakdown_ends_the_solve(B, d):
+    # b an eigenvector of a diagonal A: the first Arnoldi step already spans the
+    # solution (h_21 = 0).  The step issued ahead of it normalises a zero vector; its
+    # results are never read, and the solve ends after one step with x = b / a_33.
+    n = 50
+    dg = np.linspace(1.0, 5.0, n)
+    Ah = W.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), dg)
+    A = B.CSRMatrix.from_host(Ah)
+    b = np.zeros(n)
+    b[3] = 2.0
+    x, st = B.pp_gmres_solve(A, _up(b), m=10, d=d, tol=1e-12, v0=_up(W.uniform(n, 5)))
+    assert st.iters == 1 and st.relres_true < 1e-14
+    ref = np.zeros(n)
+    ref[3] = 2.0 / dg[3]
+    assert np.allclose(x.cpu().numpy(), ref, rtol=1e-13, atol=0)
+
+
 def test_checkpoint_and_resume_is_exact(B):
     # a solve interrupted at a cycle boundary and resumed from (x, roots) ends with
     # the same bits as the uninterrupted solve.  The layout is fixed: with "auto" a
