@@ -1428,26 +1428,35 @@ int orth_grid(int n, int rpt) {
   return (int)((n + per - 1) / per);
 }
 
-// Column-count buckets of the CGS2 kernels.
-#define PP_NCB_SWITCH(nc, CALL) \
-  do {                          \
-    if ((nc) <= 8) {            \
-      CALL(8);                  \
-    } else if ((nc) <= 16) {    \
-      CALL(16);                 \
-    } else if ((nc) <= 24) {    \
-      CALL(24);                 \
-    } else if ((nc) <= 32) {    \
-      CALL(32);                 \
-    } else if ((nc) <= 40) {    \
-      CALL(40);                 \
-    } else if ((nc) <= 48) {    \
-      CALL(48);                 \
-    } else if ((nc) <= 56) {    \
-      CALL(56);                 \
-    } else {                    \
-      CALL(64);                 \
-    }                           \
+// Column-count buckets of the CGS2 kernels: steps of 4 columns, so a sweep loads
+// at most 3 columns beyond its nc (those re-read column nc - 1 and are multiplied
+// by a zero coefficient) and holds no more registers than its bucket needs.
+#define PP_NCB_CASE(B, CALL) \
+  case (B) / 4:              \
+    CALL(B);                 \
+    break
+#define PP_NCB_SWITCH(nc, CALL)   \
+  do {                            \
+    switch (((nc) + 3) / 4) {     \
+      PP_NCB_CASE(4, CALL);       \
+      PP_NCB_CASE(8, CALL);       \
+      PP_NCB_CASE(12, CALL);      \
+      PP_NCB_CASE(16, CALL);      \
+      PP_NCB_CASE(20, CALL);      \
+      PP_NCB_CASE(24, CALL);      \
+      PP_NCB_CASE(28, CALL);      \
+      PP_NCB_CASE(32, CALL);      \
+      PP_NCB_CASE(36, CALL);      \
+      PP_NCB_CASE(40, CALL);      \
+      PP_NCB_CASE(44, CALL);      \
+      PP_NCB_CASE(48, CALL);      \
+      PP_NCB_CASE(52, CALL);      \
+      PP_NCB_CASE(56, CALL);      \
+      PP_NCB_CASE(60, CALL);      \
+      default:                    \
+        CALL(64);                 \
+        break;                    \
+    }                             \
   } while (0)
 
 template <typename T>
