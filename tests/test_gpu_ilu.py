@@ -62,10 +62,6 @@ def _matrix(name):
         return _tridiag(500)
     if name == "tridiag_5000":  # 5000 one-row levels: a chain longer than one run holds
         return _tridiag(5000)
-    if name == "tridiag_5000":
-        # each sweep: two runs (4096 + 904 levels); the second waits for the first's last
-        # row, taken out of its right-hand side first: gather, 2 x (run, scatter), update
-        assert f == b == 5000 and launches == 12
     if name == "ninept_48":  # four entries a row in each triangle: the widest LDS-ring rows
         return _nine_point(48)
     raise KeyError(name)
