@@ -121,7 +121,11 @@ int ensure_arena(Arena *a, size_t dev_bytes, size_t host_doubles) {
     a->dev_cap = dev_bytes;
   }
   if (host_doubles > a->host_cap) {
-    if (a->host) (void)hipHostFree(a->host);
+    if (a->host) {
+      // kernels write step results into it: nothing may still be in flight
+      if (hipDeviceSynchronize() != hipSuccess) return PP_ERR_HIP;
+      (void)hipHostFree(a->host);
+    }
     a->host = nullptr;
     a->host_cap = 0;
     // coherent: kernels write small results straight into it (the Arnoldi step's
@@ -1870,6 +1874,14 @@ void enter(const char *entry) {
 
 }  // namespace ppd
 
+// An error can end a call with work of its own still queued (a step issued one
+// ahead of the one that failed): wait for it, so that nothing the call launched
+// outlives it.
+static int settle(int rc, hipStream_t s) {
+  if (rc < 0) (void)hipStreamSynchronize(s);
+  return rc;
+}
+
 extern "C" {
 
 int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_poly **out) {
@@ -1881,8 +1893,9 @@ int pp_build_poly(const pp_csr *A, const double *v0, int d, void *stream, pp_pol
   std::lock_guard<std::mutex> lk(g_lock);
   hipStream_t s = static_cast<hipStream_t>(stream);
   PP_TRY(validate_csr(A, s));
-  return A->dtype == PP_F64 ? build_impl<double>(A, v0, d, s, out)
-                            : build_impl<float>(A, v0, d, s, out);
+  const int rc = A->dtype == PP_F64 ? build_impl<double>(A, v0, d, s, out)
+                                    : build_impl<float>(A, v0, d, s, out);
+  return settle(rc, s);
 }
 
 int pp_apply(const pp_csr *A, const pp_poly *p, const void *v, void *y, void *stream) {
@@ -1972,6 +1985,7 @@ int pp_gmres_solve(const pp_csr *A, const double *b, double *x, int m, int d, do
     in.b = bs;
   }
   int rc = in.o.precision == PP_PREC_F64 ? solve_f64(in, st) : solve_f32_ir(in, st);
+  rc = settle(rc, in.s);
   if (st) {
     st->status = rc;
     st->relres_original = st->relres_true;
@@ -2040,7 +2054,7 @@ int pp_build_poly_power(const pp_csr *A, const double *v0, int deg, int auto_deg
     *out = p;
     return rc;
   };
-  return A->dtype == PP_F64 ? go(double{}) : go(float{});
+  return settle(A->dtype == PP_F64 ? go(double{}) : go(float{}), s);
 }
 
 int pp_poly_coeffs(const pp_poly *p, double *c, int cap, int *n_out) {
