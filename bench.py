@@ -94,7 +94,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
@@ -817,7 +817,7 @@ def cpu_baseline(P, As, st, grid):
     """Oracle time for the whole solve on this host: an estimate from timings of the
     oracle's own functions on the full matrix (cpu_estimate), with the oracle's own
     roots, scaled to the oracle's step and cycle counts (the GPU's, equal within 2%).
-    The complete oracle solve measured once on the GPU machine host is quoted beside it
+    The complete oracle solve measured once on a host of the GPU machine is quoted beside it
     (profiles/oracle_cpu_cd3d_256_pe100.json, written by `bench.py --cpu-full-solve`),
     with the estimator's value from that same run as its calibration."""
     roots, src = oracle_roots(P, grid)
