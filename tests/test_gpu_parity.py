@@ -875,6 +875,42 @@ def test_lucky_breakdown_ends_the_solve(B, d):
     assert np.allclose(x.cpu().numpy(), ref, rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("layout", ["csr", "sell"])
+def test_smallest_systems(B, layout):
+    """Degenerate sizes: one row, and two rows whose two roots are a conjugate pair.
+    With d = n roots the residual polynomial vanishes on A, so p(A) = A^-1 (the
+    special case of the method that reduces to a direct solve): p(A) v is checked
+    against numpy.linalg.solve, and the solve ends after one Arnoldi step."""
+    # n = 1: one root, theta = a
+    A1 = W.CSR(1, np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32),
+               np.array([3.0]))
+    Ad = B.CSRMatrix.from_host(A1, layout=layout)
+    p = B.pp_build_poly(Ad, _up(np.array([0.7])), 1)
+    r = B.pp_poly_roots(p)
+    assert np.allclose(r.real, [3.0], rtol=1e-15) and not np.any(r.imag)
+    y = B.pp_apply(Ad, p, _up(np.array([6.0]))).cpu().numpy()
+    assert abs(y[0] - 2.0) <= 1e-15
+    x, st = B.pp_gmres_solve(Ad, _up(np.array([6.0])), m=1, d=1, tol=1e-12,
+                             v0=_up(np.array([0.7])))
+    assert st.iters == 1 and abs(x.cpu().numpy()[0] - 2.0) <= 1e-15
+    # n = 2: A = [[2, -1], [1, 2]], eigenvalues 2 +- i: one pair step
+    Ad2 = np.array([[2.0, -1.0], [1.0, 2.0]])
+    As = sp.csr_matrix(Ad2)
+    A2 = W.CSR(2, As.indptr.astype(np.int32), As.indices.astype(np.int32), As.data)
+    Ad = B.CSRMatrix.from_host(A2, layout=layout)
+    p = B.pp_build_poly(Ad, _up(np.array([1.0, 0.3])), 2)
+    r = B.pp_poly_roots(p)
+    assert np.allclose(np.sort(r.real), [2.0, 2.0], rtol=1e-14)
+    assert np.allclose(np.sort(r.imag), [-1.0, 1.0], rtol=1e-14)
+    v = np.array([0.4, -1.3])
+    y = B.pp_apply(Ad, p, _up(v)).cpu().numpy()
+    ref = np.linalg.solve(Ad2, v)
+    assert np.max(np.abs(y - ref)) <= 1e-14 * np.max(np.abs(ref))
+    x, st = B.pp_gmres_solve(Ad, _up(v), m=2, d=2, tol=1e-12, v0=_up(np.array([1.0, 0.3])))
+    assert st.iters == 1 and st.relres_true < 1e-14
+    assert np.max(np.abs(x.cpu().numpy() - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
 def test_checkpoint_and_resume_is_exact(B):
     # a solve interrupted at a cycle boundary and resumed from (x, roots) ends with
     # the same bits as the uninterrupted solve.  The layout is fixed: with "auto" a
